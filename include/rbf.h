@@ -1,0 +1,265 @@
+/*
+ * rbf.h -- C ABI of librbf, the gfx950 (MI355X) RBF terrain hot path.
+ *
+ * The method (Liu & Zhang, "Terrain-Awared LiDAR-Inertial Odometry for
+ * Legged-Wheel Robots Based on Radial Basis Function Approximation"):
+ *   f(x; w) = sum_j w_j phi(||x - c_j||),  phi(r) = exp(-r^2 / (2 sigma^2))
+ * (eqs. RBF_fml, RBF_def), centers chosen adaptively on a mesh (subsection
+ * "The RBF Approximation Model"), weights estimated by ridge regression on
+ * the moment-corrected regressor m(x) (eq. RBF_estimator and the ridge
+ * estimator after it) and updated recursively scan by scan (eqs.
+ * weights_update, H_update, kf_w_update, H_inverse_update), then evaluated
+ * with its gradient and the manifold residual / Jacobian (eqs.
+ * residual_manifold_left_wheel, manifold_derivative, manidolf_grad_detail,
+ * manifold_grad_2).
+ *
+ * Conventions (all entry points)
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless
+ *     the comment says "host". The library never frees or retains caller
+ *     memory after a call returns.
+ *   - Matrices are row-major. Sizes are int64_t.
+ *   - Work is enqueued on the context's HIP stream and is asynchronous,
+ *     except where an argument is documented as a host output (the call
+ *     then synchronises the stream before returning).
+ *   - Argument errors are detected on the host and returned before any
+ *     launch. Errors found by kernels (non-positive Cholesky pivot,
+ *     non-finite input, capacity overflow) are recorded in a device status
+ *     word; rbf_sync_status() returns and clears it.
+ *   - A context is bound to one device and one stream; it is not
+ *     thread-safe. No C++ exception crosses this ABI.
+ *   - Kernel truncation: phi is taken as exactly zero for r > cutoff*sigma
+ *     and kept for r == cutoff*sigma (the paper calls the kernel compactly
+ *     supported without giving the radius; cutoff = 3 is the default).
+ */
+#ifndef RBF_H
+#define RBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBF_OK = 0,
+  RBF_E_INVALID_ARG = 1,  /* bad pointer, size, layout or parameter       */
+  RBF_E_NOMEM = 2,        /* workspace allocation failed                  */
+  RBF_E_NOT_SPD = 3,      /* non-positive pivot in a Cholesky factor      */
+  RBF_E_NONFINITE = 4,    /* NaN/Inf in an input or an innovation         */
+  RBF_E_NO_CONVERGE = 5,  /* iterative refinement did not reach rtol      */
+  RBF_E_CAPACITY = 6,     /* output capacity (cap, kmax, nnz) exceeded     */
+  RBF_E_HIP = 7           /* a HIP runtime call failed                    */
+} rbf_status;
+
+typedef enum { RBF_F64 = 0, RBF_F32 = 1, RBF_BF16 = 2 } rbf_prec;
+
+enum { RBF_SELECT_RADIUS = 0, RBF_SELECT_VOXEL = 1 };
+
+/* Model and filter parameters.
+ *   sigma     Gaussian bandwidth of phi (eq. RBF_def), metres.
+ *   cutoff    truncation radius in units of sigma (3.0 by default).
+ *   sigma_eps std of the isotropic xy point noise; the regressor is then
+ *             m(x) = (sigma^2/sigma_t^2) kappa_{sigma_t}(x; c) with
+ *             sigma_t^2 = sigma^2 + sigma_eps^2 (moment regressor in the
+ *             ridge-regression subsection), truncated at cutoff*sigma_t.
+ *   lambda    ridge penalty; calH = lambda I + sum_i m(x_i) m(x_i)^T.
+ *   R         height-measurement variance. The paper writes the Woodbury
+ *             update with R = 1; here the covariance is P = R calH^{-1},
+ *             so w does not depend on R and P scales with it. */
+typedef struct {
+  double sigma;
+  double cutoff;
+  double sigma_eps;
+  double lambda;
+  double R;
+} rbf_params;
+
+typedef struct rbf_ctx rbf_ctx;   /* device, stream, status word, workspace */
+typedef struct rbf_grid rbf_grid; /* neighbour-binned copy of a center set  */
+
+/* ------------------------------------------------------------------ ctx */
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). *out receives the handle. */
+rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream);
+/* Destroy a context and free its workspace (synchronises its stream). */
+rbf_status rbf_ctx_destroy(rbf_ctx* ctx);
+/* Re-bind the context to another stream of the same device. */
+rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream);
+/* Synchronise the stream, return the first device-side error recorded
+ * since the last call (RBF_OK if none) and clear it. */
+rbf_status rbf_sync_status(rbf_ctx* ctx);
+/* Index attached to the last device error returned by rbf_sync_status
+ * (the batch index for rbf_update, the row for capacity errors), or -1. */
+int64_t rbf_last_error_index(const rbf_ctx* ctx);
+/* Human-readable text of the last error seen by this context (static
+ * storage inside the context; valid until the next call). */
+const char* rbf_last_error(const rbf_ctx* ctx);
+const char* rbf_status_string(rbf_status s);
+
+/* ------------------------------------------------------ center selection */
+
+/* Adaptive center selection (subsection "The RBF Approximation Model").
+ * Candidate nodes are the cell centers of a `res` mesh over the ROI
+ * roi = {x0, y0, x1, y1} (host array): nx = ceil((x1-x0)/res),
+ * ny = ceil((y1-y0)/res), node (i, j) = (x0+(i+1/2)res, y0+(j+1/2)res).
+ * A node is accepted iff its support count is strictly greater than thr
+ * ("exceeds"):
+ *   RBF_SELECT_RADIUS  points with ||p - node||^2 <= r_kd^2 (the k-d tree
+ *                      radius count of the paper, done exactly by binning),
+ *   RBF_SELECT_VOXEL   points with floor((p - (x0,y0)) / res) == (i, j).
+ * xy: M x 2 f64. centers_out: cap x 2 f64, accepted nodes in mesh order
+ * (y outer, x inner). *n_out (host) receives the number accepted; the call
+ * synchronises. Returns RBF_E_CAPACITY (and writes the first cap) if more
+ * than cap nodes are accepted. */
+rbf_status rbf_select_centers(rbf_ctx* ctx, const double* xy, int64_t M,
+                              const double* roi, double res, double r_kd,
+                              int32_t thr, int32_t mode, double* centers_out,
+                              int64_t cap, int64_t* n_out);
+
+/* --------------------------------------------------------------- binning */
+
+/* Build the neighbour-binned center table used by every kernel below:
+ * square bins of side slightly above cutoff*max(sigma, sigma_t), so all
+ * centers within the kernel support of a point lie in its 3x3 bins. The
+ * centers (N x 2 f64, device) are copied; the caller may free them after
+ * the call. The grid owns its device memory until rbf_grid_destroy.
+ * The call synchronises (it reads the centers' bounding box). */
+rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* params,
+                           const double* centers, int64_t N, rbf_grid** out);
+rbf_status rbf_grid_destroy(rbf_grid* grid);
+/* Host outputs: number of centers, bins in x and y, and the largest number
+ * of centers that can lie within one point's 3x3 bins (an upper bound on
+ * the nonzeros of one regressor row). Any pointer may be NULL. */
+rbf_status rbf_grid_info(const rbf_grid* grid, int64_t* N, int32_t* nbx,
+                         int32_t* nby, int32_t* max_candidates);
+
+/* Spatially sort points by the grid's bins (a counting sort; points in one
+ * bin keep their input order). xy: M x 2 f64 and z: M f64 (z may be NULL).
+ * Writes xy_out, z_out (if z != NULL) and perm (M int32, perm[k] = input
+ * index of output k). Sorting is optional: every entry point accepts any
+ * point order; compact batches make the covariance update cheaper. */
+rbf_status rbf_sort_points(rbf_ctx* ctx, const rbf_grid* grid,
+                           const double* xy, const double* z, int64_t M,
+                           double* xy_out, double* z_out, int32_t* perm);
+
+/* -------------------------------------------------------------- assembly */
+
+/* Regressor rows m(x_i)^T (eq. rbf_kernel, the columns of the kernel matrix
+ * of one scan) in point-major ELL form. Row i holds nnz[i] <= kmax entries
+ * (cols[i*kmax + k], vals[i*kmax + k]) with distinct column indices into the
+ * original center order, in a fixed order; entries k >= nnz[i] are zero with
+ * column 0. prec: RBF_F64 (vals double) or RBF_F32 (vals float).
+ * Rows with more than kmax nonzeros are truncated and recorded as
+ * RBF_E_CAPACITY (index = row). */
+rbf_status rbf_assemble_phi(rbf_ctx* ctx, const rbf_params* params,
+                            const rbf_grid* grid, const double* xy, int64_t M,
+                            rbf_prec prec, void* vals, int32_t* cols,
+                            int32_t* nnz, int32_t kmax);
+
+/* Structural pattern of calH: row j lists the centers k whose regressor
+ * supports overlap j's (||c_j - c_k|| <= 2 cutoff sigma_t), in ascending
+ * order. rowptr: N+1 int64, colidx: cap int32. *nnz_out (host) receives the
+ * total; the call synchronises. RBF_E_CAPACITY if nnz > cap (rowptr is
+ * still complete, so the call can be repeated with a larger buffer). */
+rbf_status rbf_gram_pattern(rbf_ctx* ctx, const rbf_params* params,
+                            const rbf_grid* grid, int64_t* rowptr,
+                            int32_t* colidx, int64_t cap, int64_t* nnz_out);
+
+/* Accumulate the information matrix and right-hand side of the ridge
+ * estimator: vals += sum_i m(x_i) m(x_i)^T (on the pattern above, CSR with
+ * the same rowptr/colidx) and b += sum_i m(x_i) z_i; with add_lambda != 0
+ * also vals += lambda on the diagonal (the ridge term, added once).
+ * xy: M x 2, z: M, both f64. Deterministic (no atomics). */
+rbf_status rbf_assemble_gram(rbf_ctx* ctx, const rbf_params* params,
+                             const rbf_grid* grid, const double* xy,
+                             const double* z, int64_t M,
+                             const int64_t* rowptr, const int32_t* colidx,
+                             double* vals, double* b, int32_t add_lambda);
+
+/* ------------------------------------------------------ recursive update */
+
+/* Absorb M points into (w, P) by the Kalman-style recursion of eqs.
+ * kf_w_update and H_inverse_update, in consecutive batches of `batch`
+ * points (0 = library default) taken in the given order. Per batch, with
+ * H the B x N regressor block and y = z - H w:
+ *   U = P H^T,  S = H U + R I,  L L^T = S (FP64),  V = U L^{-T},
+ *   t = L^{-1} y,  w += V t,  P -= V V^T.
+ * P is N x N with leading dimension ldp >= N, symmetric in full storage;
+ * it is kept exactly symmetric (each lower tile is written to both
+ * triangles). gemm_prec selects the operand precision of the covariance
+ * product V V^T (RBF_F64: FP64 MFMA; RBF_F32 / RBF_BF16: low-precision
+ * operands with FP32 accumulation subtracted from the FP64 P).
+ * Batches are committed one at a time: if a batch fails (RBF_E_NOT_SPD,
+ * RBF_E_NONFINITE) no later batch runs, and (w, P) is the state after the
+ * batches before it. n_done (host, may be NULL): if non-NULL the call
+ * synchronises and stores the number of points absorbed; if NULL the call
+ * is asynchronous and errors are read with rbf_sync_status. */
+rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* params,
+                      const rbf_grid* grid, double* w, double* P, int64_t ldp,
+                      const double* xy, const double* z, int64_t M,
+                      int64_t batch, rbf_prec gemm_prec, int64_t* n_done);
+
+/* ----------------------------------------------------------------- solve */
+
+/* Solve calH X = B for the sparse SPD matrix in CSR (rowptr N+1 int64,
+ * colidx int32, vals f64; both triangles stored), the "sparse kernel
+ * matrix inversion" of the GPU-acceleration section. B and X are N x nrhs
+ * (leading dimensions ldb, ldx >= nrhs). The matrix is reordered into
+ * dense diagonal / sub-diagonal blocks of its bandwidth, factored in the
+ * `inner` precision (RBF_F32 or RBF_F64), and refined in FP64 until
+ * ||B_k - calH X_k||_2 <= rtol ||B_k||_2 for every column k, or max_iter
+ * sweeps. relres (host, nrhs doubles, may be NULL) and iters (host, may be
+ * NULL) report the result; the call synchronises. Returns
+ * RBF_E_NO_CONVERGE if rtol was not met, RBF_E_NOT_SPD if the factor
+ * broke down. With B = I it returns calH^{-1} (so P = R X). */
+rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
+                     const int32_t* colidx, const double* vals,
+                     const double* B, int64_t ldb, double* X, int64_t ldx,
+                     int64_t nrhs, double rtol, int32_t max_iter,
+                     rbf_prec inner, double* relres, int32_t* iters);
+
+/* ------------------------------------------------------------ evaluation */
+
+/* Evaluate the terrain model at Q points.
+ *   dim == 2: pts are world xy (Q x 2); outputs f (Q) and grad (Q x 2):
+ *             f = sum_j w_j phi, grad f = -sum_j w_j phi (x - c_j)/sigma^2
+ *             (eqs. RBF_fml, manidolf_grad_detail with the sign of the
+ *             derivative of exp restored). pose must be NULL.
+ *   dim == 3: pts are body-frame points p (Q x 3) and pose (host, 12
+ *             doubles: R row-major then t) maps them to xi = R p + t.
+ *             Outputs f, grad at xi_xy, the residual
+ *             r = xi_z - z_off - f(xi_x, xi_y) (eq.
+ *             residual_manifold_left_wheel, z_off = wheel radius or 0), and
+ *             its Jacobian J (Q x 6) for the right perturbation
+ *             R <- R Exp(dtheta), t <- t + dt, ordered [dtheta, dt]:
+ *             J = [ (p x R^T g)^T, g^T ], g = (-f_x, -f_y, 1)
+ *             (eqs. manifold_derivative, manifold_grad_2 with the body
+ *             point in the skew matrix).
+ * prec RBF_F64: pts and outputs are double; RBF_F32: float (w stays f64
+ * and is rounded per load). Any output pointer except f may be NULL. */
+rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* params,
+                    const rbf_grid* grid, const double* w, const void* pts,
+                    int64_t Q, int32_t dim, const double* pose, double z_off,
+                    rbf_prec prec, void* f, void* grad, void* resid,
+                    void* jac);
+
+/* Adjoint of rbf_eval for L = sum_i gbar_f[i] f_i + gbar_r[i] r_i
+ * (gbar_r only for dim == 3; either gbar may be NULL = zero).
+ *   d_pts  (Q x dim, same precision as pts, may be NULL): dL/dpts,
+ *   d_w    (N f64, may be NULL): dL/dw, ACCUMULATED (+=) into the buffer,
+ *   d_pose (6 f64, device, may be NULL, dim == 3): dL/d[dtheta, dt],
+ *          ACCUMULATED (+=).
+ * Accumulations use atomics, so d_w and d_pose are reproducible only up to
+ * the order of floating-point additions. */
+rbf_status rbf_eval_adjoint(rbf_ctx* ctx, const rbf_params* params,
+                            const rbf_grid* grid, const double* w,
+                            const void* pts, int64_t Q, int32_t dim,
+                            const double* pose, rbf_prec prec,
+                            const void* gbar_f, const void* gbar_r,
+                            void* d_pts, double* d_w, double* d_pose);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBF_H */

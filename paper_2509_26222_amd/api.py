@@ -1,0 +1,303 @@
+"""Python binding of librbf: argument marshalling on torch tensors only.
+
+Every computation runs in the library's HIP kernels. Tensors must already
+live on the context's device with the documented dtype and be contiguous;
+nothing is copied or converted silently. PyTorch provides device memory and
+the stream the context enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+class RbfError(RuntimeError):
+    def __init__(self, status: int, msg: str, index: int = -1):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.index = index
+
+
+@dataclass
+class Params:
+    sigma: float = 0.5
+    cutoff: float = 3.0
+    sigma_eps: float = 0.0
+    lam: float = 1e-3
+    R: float = 0.02 ** 2
+
+    def c(self) -> L.Params:
+        return L.Params(self.sigma, self.cutoff, self.sigma_eps, self.lam, self.R)
+
+
+_PREC = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16,
+         torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
+_DT = {L.F64: torch.float64, L.F32: torch.float32}
+
+
+def _prec(p) -> int:
+    if isinstance(p, int):
+        return p
+    return _PREC[p]
+
+
+def _ptr(t: torch.Tensor | None, dtype=None, name="tensor", dev=None) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+    if dev is not None and t.device.index != dev:
+        raise ValueError(f"{name}: on device {t.device}, context is on cuda:{dev}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t.data_ptr()
+
+
+class Context:
+    """rbf_ctx bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.lib = L.lib()
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = s
+        h = C.c_void_p()
+        self._check(self.lib.rbf_ctx_create(C.byref(h), device, C.c_void_p(s.cuda_stream)),
+                    "rbf_ctx_create", ctx=False)
+        self.h = h
+
+    def _check(self, st: int, what: str, ctx: bool = True):
+        if st != L.RBF_OK:
+            msg = what
+            idx = -1
+            if ctx and getattr(self, "h", None):
+                msg = self.lib.rbf_last_error(self.h).decode(errors="replace")
+                idx = self.lib.rbf_last_error_index(self.h)
+            raise RbfError(st, msg, idx)
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        self._check(self.lib.rbf_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)),
+                    "rbf_ctx_set_stream")
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def sync_status(self) -> int:
+        """Synchronise and raise RbfError on a recorded device error."""
+        st = self.lib.rbf_sync_status(self.h)
+        self._check(st, "device status")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ steps
+
+    def select_centers(self, xy: torch.Tensor, roi, res: float, r_kd: float,
+                       thr: int, mode: int = L.SELECT_RADIUS, cap: int | None = None):
+        M = xy.shape[0]
+        x0, y0, x1, y1 = [float(v) for v in roi]
+        import math
+        nx = int(math.ceil((x1 - x0) / res))
+        ny = int(math.ceil((y1 - y0) / res))
+        cap = cap if cap is not None else max(nx * ny, 1)
+        out = torch.empty((cap, 2), dtype=torch.float64, device=xy.device)
+        roi_c = (C.c_double * 4)(x0, y0, x1, y1)
+        n = C.c_int64()
+        self._check(self.lib.rbf_select_centers(
+            self.h, _ptr(xy, torch.float64, "xy", self.device), M, roi_c, res, r_kd, thr,
+            mode, _ptr(out, torch.float64, "centers_out"), cap, C.byref(n)),
+            "rbf_select_centers")
+        return out[: n.value]
+
+    def grid(self, params: Params, centers: torch.Tensor) -> "Grid":
+        return Grid(self, params, centers)
+
+    def sort_points(self, grid: "Grid", xy: torch.Tensor, z: torch.Tensor | None = None):
+        M = xy.shape[0]
+        xy_o = torch.empty_like(xy)
+        z_o = torch.empty_like(z) if z is not None else None
+        perm = torch.empty(M, dtype=torch.int32, device=xy.device)
+        self._check(self.lib.rbf_sort_points(
+            self.h, grid.h, _ptr(xy, torch.float64, "xy", self.device),
+            _ptr(z, torch.float64, "z"), M, _ptr(xy_o), _ptr(z_o), _ptr(perm)),
+            "rbf_sort_points")
+        return xy_o, z_o, perm
+
+    def assemble_phi(self, params: Params, grid: "Grid", xy: torch.Tensor,
+                     kmax: int | None = None, prec="f64"):
+        prec = _prec(prec)
+        M = xy.shape[0]
+        kmax = kmax if kmax is not None else grid.max_candidates
+        vals = torch.empty((M, kmax), dtype=_DT[prec], device=xy.device)
+        cols = torch.empty((M, kmax), dtype=torch.int32, device=xy.device)
+        nnz = torch.empty(M, dtype=torch.int32, device=xy.device)
+        pc = params.c()
+        self._check(self.lib.rbf_assemble_phi(
+            self.h, C.byref(pc), grid.h, _ptr(xy, torch.float64, "xy", self.device), M, prec,
+            _ptr(vals), _ptr(cols), _ptr(nnz), kmax), "rbf_assemble_phi")
+        return vals, cols, nnz
+
+    def gram_pattern(self, params: Params, grid: "Grid", cap: int | None = None):
+        N = grid.N
+        rowptr = torch.empty(N + 1, dtype=torch.int64, device=f"cuda:{self.device}")
+        cap = cap if cap is not None else N * 64
+        pc = params.c()
+        for _ in range(2):
+            colidx = torch.empty(max(cap, 1), dtype=torch.int32, device=rowptr.device)
+            nnz = C.c_int64()
+            st = self.lib.rbf_gram_pattern(self.h, C.byref(pc), grid.h, _ptr(rowptr),
+                                           _ptr(colidx), cap, C.byref(nnz))
+            if st == 6 and nnz.value > cap:  # capacity: retry with the exact size
+                cap = nnz.value
+                continue
+            self._check(st, "rbf_gram_pattern")
+            return rowptr, colidx[: nnz.value]
+        raise RbfError(6, "rbf_gram_pattern: capacity")
+
+    def assemble_gram(self, params: Params, grid: "Grid", xy: torch.Tensor,
+                      z: torch.Tensor, rowptr: torch.Tensor, colidx: torch.Tensor,
+                      vals: torch.Tensor | None = None, b: torch.Tensor | None = None,
+                      add_lambda: bool = True):
+        dev = xy.device
+        if vals is None:
+            vals = torch.zeros(colidx.shape[0], dtype=torch.float64, device=dev)
+        if b is None:
+            b = torch.zeros(grid.N, dtype=torch.float64, device=dev)
+        pc = params.c()
+        self._check(self.lib.rbf_assemble_gram(
+            self.h, C.byref(pc), grid.h, _ptr(xy, torch.float64, "xy", self.device),
+            _ptr(z, torch.float64, "z"), xy.shape[0], _ptr(rowptr, torch.int64, "rowptr"),
+            _ptr(colidx, torch.int32, "colidx"), _ptr(vals, torch.float64, "vals"),
+            _ptr(b, torch.float64, "b"), int(add_lambda)), "rbf_assemble_gram")
+        return vals, b
+
+    def update(self, params: Params, grid: "Grid", w: torch.Tensor, P: torch.Tensor,
+               xy: torch.Tensor, z: torch.Tensor, batch: int = 0, gemm_prec="f64",
+               sync: bool = True) -> int | None:
+        ldp = P.stride(0)
+        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] != grid.N or P.shape[1] != grid.N:
+            raise ValueError("P must be an N x N row-major tensor")
+        pc = params.c()
+        nd = C.c_int64()
+        st = self.lib.rbf_update(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            P.data_ptr() if P.dtype == torch.float64 and P.is_cuda else None, ldp,
+            _ptr(xy, torch.float64, "xy"), _ptr(z, torch.float64, "z"), xy.shape[0],
+            batch, _prec(gemm_prec), C.byref(nd) if sync else None)
+        self._check(st, "rbf_update")
+        return nd.value if sync else None
+
+    def solve(self, rowptr, colidx, vals, B: torch.Tensor, rtol: float = 1e-10,
+              max_iter: int = 50, inner="f32", X: torch.Tensor | None = None):
+        N = rowptr.shape[0] - 1
+        Bm = B if B.dim() == 2 else B.view(-1, 1)
+        nrhs = Bm.shape[1]
+        if X is None:
+            X = torch.empty_like(Bm)
+        rel = (C.c_double * max(nrhs, 1))()
+        it = C.c_int32()
+        st = self.lib.rbf_solve(
+            self.h, N, _ptr(rowptr, torch.int64, "rowptr", self.device),
+            _ptr(colidx, torch.int32, "colidx"), _ptr(vals, torch.float64, "vals"),
+            _ptr(Bm, torch.float64, "B"), Bm.stride(0), _ptr(X, torch.float64, "X"),
+            X.stride(0), nrhs, rtol, max_iter, _prec(inner), rel, C.byref(it))
+        relres = [rel[k] for k in range(nrhs)]
+        if st not in (L.RBF_OK, 5):
+            self._check(st, "rbf_solve")
+        out = X if B.dim() == 2 else X.view(-1)
+        return out, relres, it.value, st
+
+    def eval(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
+             pose=None, z_off: float = 0.0, grad=True, resid=True, jac=True):
+        Q, dim = pts.shape
+        prec = _PREC[pts.dtype]
+        dt = pts.dtype
+        dev = pts.device
+        f = torch.empty(Q, dtype=dt, device=dev)
+        g = torch.empty((Q, 2), dtype=dt, device=dev) if grad else None
+        r = torch.empty(Q, dtype=dt, device=dev) if (resid and dim == 3) else None
+        J = torch.empty((Q, 6), dtype=dt, device=dev) if (jac and dim == 3) else None
+        pose_c = _pose(pose)
+        pc = params.c()
+        self._check(self.lib.rbf_eval(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            _ptr(pts, None, "pts"), Q, dim, pose_c, z_off, prec, _ptr(f), _ptr(g),
+            _ptr(r), _ptr(J)), "rbf_eval")
+        return {"f": f, "grad": g, "resid": r, "jac": J}
+
+    def eval_adjoint(self, params: Params, grid: "Grid", w: torch.Tensor,
+                     pts: torch.Tensor, pose=None, gbar_f=None, gbar_r=None,
+                     d_pts=True, d_w: torch.Tensor | None = None,
+                     d_pose: torch.Tensor | None = None):
+        Q, dim = pts.shape
+        prec = _PREC[pts.dtype]
+        dp = torch.empty_like(pts) if d_pts else None
+        pc = params.c()
+        self._check(self.lib.rbf_eval_adjoint(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            _ptr(pts, None, "pts"), Q, dim, _pose(pose), prec,
+            _ptr(gbar_f, pts.dtype, "gbar_f"), _ptr(gbar_r, pts.dtype, "gbar_r"),
+            _ptr(dp), _ptr(d_w, torch.float64, "d_w"),
+            _ptr(d_pose, torch.float64, "d_pose")), "rbf_eval_adjoint")
+        return dp, d_w, d_pose
+
+
+def _pose(pose):
+    if pose is None:
+        return None
+    R, t = pose
+    vals = [float(v) for v in list(torch.as_tensor(R).reshape(-1).tolist())
+            + list(torch.as_tensor(t).reshape(-1).tolist())]
+    if len(vals) != 12:
+        raise ValueError("pose must be (R 3x3, t 3)")
+    return (C.c_double * 12)(*vals)
+
+
+class Grid:
+    """Neighbour-binned center table (rbf_grid)."""
+
+    def __init__(self, ctx: Context, params: Params, centers: torch.Tensor):
+        self.ctx = ctx
+        self.params = params
+        h = C.c_void_p()
+        pc = params.c()
+        ctx._check(ctx.lib.rbf_grid_create(
+            ctx.h, C.byref(pc), _ptr(centers, torch.float64, "centers", ctx.device),
+            centers.shape[0], C.byref(h)), "rbf_grid_create")
+        self.h = h
+        N = C.c_int64()
+        nbx, nby, mc = C.c_int32(), C.c_int32(), C.c_int32()
+        ctx.lib.rbf_grid_info(h, C.byref(N), C.byref(nbx), C.byref(nby), C.byref(mc))
+        self.N = N.value
+        self.nbx, self.nby = nbx.value, nby.value
+        self.max_candidates = mc.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rbf_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

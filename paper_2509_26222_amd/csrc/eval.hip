@@ -1,0 +1,353 @@
+// Evaluation of the terrain model and its adjoint.
+//
+// f(x) = sum_j w_j phi(x, c_j) (eq. RBF_fml), grad f = -sum_j w_j phi
+// (x - c_j)/sigma^2 (eq. manidolf_grad_detail with the sign of d/dx exp
+// restored), the manifold residual r = xi_z - z_off - f(xi_xy) at
+// xi = R p + t (eq. residual_manifold_left_wheel) and its pose Jacobian
+// J = [(p x R^T g)^T, g^T], g = (-f_x, -f_y, 1) (eqs. manifold_derivative,
+// manifold_grad_2, right perturbation, body-frame point).
+//
+// One lane per point. A point's candidates are the centers of its 3x3 bin
+// neighbourhood, read as three contiguous runs of a packed, bin-sorted
+// table (x, y, w) that stays resident in L2. Each lane accumulates its own
+// sums in registers, so no cross-lane reduction is needed and the output is
+// written once, coalesced.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace rbf {
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+
+template <typename T>
+struct EvalK {
+  T rc2;     // (cutoff sigma)^2
+  T kexp;    // f64: -1/(2 sigma^2); f32: -log2(e)/(2 sigma^2) for exp2
+  T inv_s2;  // 1/sigma^2
+  T R[9];
+  T t[3];
+  T z_off;
+};
+
+__device__ inline double kexp_eval(double a) { return exp(a); }
+__device__ inline float kexp_eval(float a) { return __builtin_amdgcn_exp2f(a); }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pack_centers(const T* __restrict__ cxy,
+                                                      const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ w, int64_t n,
+                                                      typename Vec4<T>::type* __restrict__ tab) {
+  int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  typename Vec4<T>::type v;
+  v.x = cxy[2 * s];
+  v.y = cxy[2 * s + 1];
+  v.z = (T)w[idx[s]];
+  v.w = (T)0;
+  tab[s] = v;
+}
+
+// Accumulate f, sum w phi dx, sum w phi dy over the 3x3 neighbourhood of
+// (x, y). Returns false if no bin is in range.
+template <typename T>
+__device__ inline void accumulate(T x, T y, const typename Vec4<T>::type* __restrict__ tab,
+                                  const int32_t* __restrict__ start, const GridGeom& g,
+                                  const EvalK<T>& k, T& f, T& sx, T& sy) {
+  f = sx = sy = (T)0;
+  int bx0, bx1, by0, by1;
+  if (!bin_range((double)x, g.x0, g.inv_h, g.nbx, &bx0, &bx1)) return;
+  if (!bin_range((double)y, g.y0, g.inv_h, g.nby, &by0, &by1)) return;
+  for (int by = by0; by <= by1; ++by) {
+    const int row = by * g.nbx;
+    const int s0 = start[row + bx0], s1 = start[row + bx1 + 1];
+    for (int s = s0; s < s1; ++s) {
+      const typename Vec4<T>::type c = tab[s];
+      const T dx = x - c.x, dy = y - c.y;
+      const T d2 = dx * dx + dy * dy;
+      if (d2 <= k.rc2) {
+        const T we = c.z * kexp_eval(d2 * k.kexp);
+        f += we;
+        sx += we * dx;
+        sy += we * dy;
+      }
+    }
+  }
+}
+
+template <typename T, bool POSE>
+__global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t Q,
+                                              const typename Vec4<T>::type* __restrict__ tab,
+                                              const int32_t* __restrict__ start, GridGeom g,
+                                              EvalK<T> k, T* __restrict__ f_out,
+                                              T* __restrict__ grad_out, T* __restrict__ r_out,
+                                              T* __restrict__ jac_out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= Q) return;
+  T x, y, zw, px = 0, py = 0, pz = 0;
+  if (POSE) {
+    px = pts[3 * i];
+    py = pts[3 * i + 1];
+    pz = pts[3 * i + 2];
+    x = k.R[0] * px + k.R[1] * py + k.R[2] * pz + k.t[0];
+    y = k.R[3] * px + k.R[4] * py + k.R[5] * pz + k.t[1];
+    zw = k.R[6] * px + k.R[7] * py + k.R[8] * pz + k.t[2];
+  } else {
+    x = pts[2 * i];
+    y = pts[2 * i + 1];
+    zw = 0;
+  }
+  T f, sx, sy;
+  accumulate<T>(x, y, tab, start, g, k, f, sx, sy);
+  const T fx = -sx * k.inv_s2, fy = -sy * k.inv_s2;
+  f_out[i] = f;
+  if (grad_out) {
+    grad_out[2 * i] = fx;
+    grad_out[2 * i + 1] = fy;
+  }
+  if (POSE) {
+    if (r_out) r_out[i] = zw - k.z_off - f;
+    if (jac_out) {
+      // g = (-fx, -fy, 1); q = R^T g; J_rot = p x q
+      const T g0 = -fx, g1 = -fy, g2 = (T)1;
+      const T q0 = k.R[0] * g0 + k.R[3] * g1 + k.R[6] * g2;
+      const T q1 = k.R[1] * g0 + k.R[4] * g1 + k.R[7] * g2;
+      const T q2 = k.R[2] * g0 + k.R[5] * g1 + k.R[8] * g2;
+      T* J = jac_out + 6 * i;
+      J[0] = py * q2 - pz * q1;
+      J[1] = pz * q0 - px * q2;
+      J[2] = px * q1 - py * q0;
+      J[3] = g0;
+      J[4] = g1;
+      J[5] = g2;
+    }
+  }
+}
+
+// Adjoint: L = sum_i gf_i f_i + gr_i r_i. With a_i = gf_i - gr_i:
+//   dL/dw_j   = sum_i a_i phi(xi_i, c_j)            (scattered, atomics)
+//   dL/dxi_i  = (a_i f_x, a_i f_y, gr_i),  dL/dp_i = R^T dL/dxi_i
+//   dL/dpose  = sum_i [p_i x (R^T dL/dxi_i), dL/dxi_i]  (block-reduced)
+template <typename T, bool POSE>
+__global__ void __launch_bounds__(256) k_eval_adjoint(
+    const T* __restrict__ pts, int64_t Q, const typename Vec4<T>::type* __restrict__ tab,
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ start, GridGeom g,
+    EvalK<T> k, const T* __restrict__ gbar_f, const T* __restrict__ gbar_r,
+    T* __restrict__ d_pts, double* __restrict__ d_w, double* __restrict__ d_pose) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  if (i < Q) {
+    T x, y, px = 0, py = 0, pz = 0;
+    if (POSE) {
+      px = pts[3 * i];
+      py = pts[3 * i + 1];
+      pz = pts[3 * i + 2];
+      x = k.R[0] * px + k.R[1] * py + k.R[2] * pz + k.t[0];
+      y = k.R[3] * px + k.R[4] * py + k.R[5] * pz + k.t[1];
+    } else {
+      x = pts[2 * i];
+      y = pts[2 * i + 1];
+    }
+    const T gf = gbar_f ? gbar_f[i] : (T)0;
+    const T gr = (POSE && gbar_r) ? gbar_r[i] : (T)0;
+    const T a = gf - gr;
+    T sx = 0, sy = 0;
+    int bx0, bx1, by0, by1;
+    if (bin_range((double)x, g.x0, g.inv_h, g.nbx, &bx0, &bx1) &&
+        bin_range((double)y, g.y0, g.inv_h, g.nby, &by0, &by1)) {
+      for (int by = by0; by <= by1; ++by) {
+        const int row = by * g.nbx;
+        const int s0 = start[row + bx0], s1 = start[row + bx1 + 1];
+        for (int s = s0; s < s1; ++s) {
+          const typename Vec4<T>::type c = tab[s];
+          const T dx = x - c.x, dy = y - c.y;
+          const T d2 = dx * dx + dy * dy;
+          if (d2 <= k.rc2) {
+            const T e = kexp_eval(d2 * k.kexp);
+            const T we = c.z * e;
+            sx += we * dx;
+            sy += we * dy;
+            if (d_w && a != (T)0) atomicAdd(&d_w[idx[s]], (double)(a * e));
+          }
+        }
+      }
+    }
+    const T fx = -sx * k.inv_s2, fy = -sy * k.inv_s2;
+    const T dx0 = a * fx, dx1 = a * fy, dx2 = gr;
+    if (POSE) {
+      const T q0 = k.R[0] * dx0 + k.R[3] * dx1 + k.R[6] * dx2;
+      const T q1 = k.R[1] * dx0 + k.R[4] * dx1 + k.R[7] * dx2;
+      const T q2 = k.R[2] * dx0 + k.R[5] * dx1 + k.R[8] * dx2;
+      if (d_pts) {
+        d_pts[3 * i] = q0;
+        d_pts[3 * i + 1] = q1;
+        d_pts[3 * i + 2] = q2;
+      }
+      acc[0] = (double)(py * q2 - pz * q1);
+      acc[1] = (double)(pz * q0 - px * q2);
+      acc[2] = (double)(px * q1 - py * q0);
+      acc[3] = (double)dx0;
+      acc[4] = (double)dx1;
+      acc[5] = (double)dx2;
+    } else if (d_pts) {
+      d_pts[2 * i] = dx0;
+      d_pts[2 * i + 1] = dx1;
+    }
+  }
+  if (POSE && d_pose) {
+    __shared__ double red[6][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = acc[c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[c][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      double v = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
+                 red[threadIdx.x][3];
+      atomicAdd(&d_pose[threadIdx.x], v);
+    }
+  }
+}
+
+template <typename T>
+static EvalK<T> make_consts(const rbf_params* p, const double* pose, double z_off) {
+  EvalK<T> k;
+  const double rc = p->cutoff * p->sigma;
+  k.rc2 = (T)(rc * rc);
+  const double inv2s2 = 1.0 / (2.0 * p->sigma * p->sigma);
+  if (sizeof(T) == 8)
+    k.kexp = (T)(-inv2s2);
+  else
+    k.kexp = (T)(-inv2s2 * 1.4426950408889634);  // log2(e)
+  k.inv_s2 = (T)(1.0 / (p->sigma * p->sigma));
+  for (int q = 0; q < 9; ++q) k.R[q] = pose ? (T)pose[q] : (T)0;
+  for (int q = 0; q < 3; ++q) k.t[q] = pose ? (T)pose[9 + q] : (T)0;
+  k.z_off = (T)z_off;
+  return k;
+}
+
+static rbf_status check_eval_args(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                                  const double* w, const void* pts, int64_t Q, int32_t dim,
+                                  const double* pose, rbf_prec prec, const char* who) {
+  if (!p || !g || !w) return fail(ctx, RBF_E_INVALID_ARG, "%s: null params/grid/w", who);
+  if (Q < 0 || (Q > 0 && !pts)) return fail(ctx, RBF_E_INVALID_ARG, "%s: bad pts/Q", who);
+  if (dim != 2 && dim != 3) return fail(ctx, RBF_E_INVALID_ARG, "%s: dim must be 2 or 3", who);
+  if ((dim == 3) != (pose != nullptr))
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: pose required iff dim == 3", who);
+  if (prec != RBF_F64 && prec != RBF_F32)
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: prec must be F64 or F32", who);
+  if (!(p->sigma > 0) || !(p->cutoff > 0) || p->sigma != g->sigma || p->cutoff != g->cutoff)
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "%s: sigma/cutoff differ from the grid's (rebuild the grid)", who);
+  if (g->device != ctx->device)
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: grid on another device", who);
+  if (pose)
+    for (int q = 0; q < 12; ++q)
+      if (!std::isfinite(pose[q])) return fail(ctx, RBF_E_NONFINITE, "%s: non-finite pose", who);
+  return RBF_OK;
+}
+
+template <typename T>
+static rbf_status pack(rbf_ctx* ctx, const rbf_grid* g, const double* w,
+                       typename Vec4<T>::type** tab_out) {
+  rbf_status st;
+  auto* tab = (typename Vec4<T>::type*)ws_get(ctx, WS_TMP2,
+                                               sizeof(typename Vec4<T>::type) * g->N, &st);
+  if (!tab) return st;
+  const T* cxy = sizeof(T) == 8 ? (const T*)g->d_cxy : (const T*)g->d_cxyf;
+  k_pack_centers<T><<<ceil_div(g->N, 256), 256, 0, ctx->stream>>>(cxy, g->d_idx, w, g->N, tab);
+  RBF_LAUNCHED(ctx, "k_pack_centers");
+  *tab_out = tab;
+  return RBF_OK;
+}
+
+template <typename T>
+static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
+                         const void* pts, int64_t Q, int32_t dim, const double* pose,
+                         double z_off, void* f, void* grad, void* resid, void* jac) {
+  typename Vec4<T>::type* tab;
+  RBF_TRY(pack<T>(ctx, g, w, &tab));
+  EvalK<T> k = make_consts<T>(p, pose, z_off);
+  const int64_t blocks = ceil_div(Q, 256);
+  if (dim == 3)
+    k_eval<T, true><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->d_start, geom(g),
+                                                     k, (T*)f, (T*)grad, (T*)resid, (T*)jac);
+  else
+    k_eval<T, false><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->d_start,
+                                                      geom(g), k, (T*)f, (T*)grad, nullptr,
+                                                      nullptr);
+  RBF_LAUNCHED(ctx, "k_eval");
+  return RBF_OK;
+}
+
+template <typename T>
+static rbf_status adjoint_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                            const double* w, const void* pts, int64_t Q, int32_t dim,
+                            const double* pose, const void* gf, const void* gr, void* d_pts,
+                            double* d_w, double* d_pose) {
+  typename Vec4<T>::type* tab;
+  RBF_TRY(pack<T>(ctx, g, w, &tab));
+  EvalK<T> k = make_consts<T>(p, pose, 0.0);
+  const int64_t blocks = ceil_div(Q, 256);
+  if (dim == 3)
+    k_eval_adjoint<T, true><<<blocks, 256, 0, ctx->stream>>>(
+        (const T*)pts, Q, tab, g->d_idx, g->d_start, geom(g), k, (const T*)gf, (const T*)gr,
+        (T*)d_pts, d_w, d_pose);
+  else
+    k_eval_adjoint<T, false><<<blocks, 256, 0, ctx->stream>>>(
+        (const T*)pts, Q, tab, g->d_idx, g->d_start, geom(g), k, (const T*)gf, nullptr,
+        (T*)d_pts, d_w, nullptr);
+  RBF_LAUNCHED(ctx, "k_eval_adjoint");
+  return RBF_OK;
+}
+
+}  // namespace rbf
+
+using namespace rbf;
+
+extern "C" {
+
+rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
+                    const void* pts, int64_t Q, int32_t dim, const double* pose, double z_off,
+                    rbf_prec prec, void* f, void* grad, void* resid, void* jac) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  RBF_TRY(check_eval_args(ctx, p, g, w, pts, Q, dim, pose, prec, "rbf_eval"));
+  if (Q > 0 && !f) return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval: f is required");
+  if (dim == 2 && (resid || jac))
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval: resid/jac need dim == 3");
+  if (Q == 0) return RBF_OK;
+  RBF_TRY(set_device(ctx));
+  if (prec == RBF_F64) return eval_t<double>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad,
+                                             resid, jac);
+  return eval_t<float>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac);
+}
+
+rbf_status rbf_eval_adjoint(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                            const double* w, const void* pts, int64_t Q, int32_t dim,
+                            const double* pose, rbf_prec prec, const void* gbar_f,
+                            const void* gbar_r, void* d_pts, double* d_w, double* d_pose) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  RBF_TRY(check_eval_args(ctx, p, g, w, pts, Q, dim, pose, prec, "rbf_eval_adjoint"));
+  if (dim == 2 && (gbar_r || d_pose))
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval_adjoint: gbar_r/d_pose need dim == 3");
+  if (Q == 0) return RBF_OK;
+  RBF_TRY(set_device(ctx));
+  if (prec == RBF_F64)
+    return adjoint_t<double>(ctx, p, g, w, pts, Q, dim, pose, gbar_f, gbar_r, d_pts, d_w,
+                             d_pose);
+  return adjoint_t<float>(ctx, p, g, w, pts, Q, dim, pose, gbar_f, gbar_r, d_pts, d_w, d_pose);
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Internal declarations of librbf (gfx950). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "rbf.h"
+
+namespace rbf {
+
+// Workspace slots owned by a context (grow-only device buffers).
+enum WsSlot {
+  WS_TMP0 = 0,
+  WS_TMP1,
+  WS_TMP2,
+  WS_TMP3,
+  WS_SORT0,
+  WS_SORT1,
+  WS_SORT2,
+  WS_UPD_ELL,   // update: regressor rows of a batch
+  WS_UPD_UT,    // update: U^T then V^T (B x ldu)
+  WS_UPD_S,     // update: S then L (B x B)
+  WS_UPD_LINV,  // update: inverses of the diagonal blocks of L
+  WS_UPD_VLO,   // update: low-precision copy of V^T
+  WS_UPD_TILES, // update: SYRK tile schedule
+  WS_SOLVE0,
+  WS_SOLVE1,
+  WS_SOLVE2,
+  WS_SOLVE3,
+  WS_SOLVE4,
+  WS_SOLVE5,
+  WS_SOLVE6,
+  WS_COUNT
+};
+
+}  // namespace rbf
+
+struct rbf_ctx {
+  int device;
+  hipStream_t stream;
+  // d_status[0]: first error code, d_status[1]: unused,
+  // d_status[2..3]: int64 index attached to the error.
+  int32_t* d_status;
+  void* ws[rbf::WS_COUNT];
+  size_t ws_bytes[rbf::WS_COUNT];
+  int64_t last_index;
+  char err[512];
+  int64_t tiles_key;  // cached SYRK schedule key (N, tile)
+  int64_t tiles_count;
+};
+
+struct rbf_grid {
+  int device;
+  int64_t N;
+  double x0, y0, h, inv_h;
+  int32_t nbx, nby;
+  int32_t max_cand;
+  double sigma, cutoff, sigma_eps;
+  int32_t* d_start;  // nbins + 1 offsets into the sorted arrays
+  int32_t* d_idx;    // sorted position -> original center index
+  int32_t* d_rank;   // original center index -> sorted position
+  double* d_cxy;     // sorted centers, interleaved (x, y), f64
+  float* d_cxyf;     // sorted centers, interleaved (x, y), f32
+};
+
+namespace rbf {
+
+rbf_status fail(rbf_ctx* ctx, rbf_status s, const char* fmt, ...);
+void* ws_get(rbf_ctx* ctx, int slot, size_t bytes, rbf_status* st);
+rbf_status check_launch(rbf_ctx* ctx, const char* what);
+rbf_status set_device(rbf_ctx* ctx);
+
+// Geometry of a grid, passed by value to kernels.
+struct GridGeom {
+  double x0, y0, inv_h;
+  int32_t nbx, nby;
+};
+
+inline GridGeom geom(const rbf_grid* g) {
+  GridGeom r;
+  r.x0 = g->x0;
+  r.y0 = g->y0;
+  r.inv_h = g->inv_h;
+  r.nbx = g->nbx;
+  r.nby = g->nby;
+  return r;
+}
+
+// Record a device-side error: the first error wins, its index is kept.
+__device__ inline void set_status(int32_t* st, int code, int64_t index) {
+  if (atomicCAS(st, 0, code) == 0) {
+    *reinterpret_cast<int64_t*>(st + 2) = index;
+  }
+}
+
+// Bin range [lo, hi] of the 3x3 neighbourhood of coordinate v, clipped to
+// [0, n-1]. Returns false if the neighbourhood misses the grid (or v is not
+// finite), in which case no center can be within the kernel support.
+__device__ inline bool bin_range(double v, double o, double inv_h, int n,
+                                 int* lo, int* hi) {
+  double f = (v - o) * inv_h;
+  if (!(f >= -1.0 && f < (double)n + 1.0)) return false;
+  int b = (int)floor(f);
+  *lo = b - 1 < 0 ? 0 : b - 1;
+  *hi = b + 1 > n - 1 ? n - 1 : b + 1;
+  return *lo <= *hi;
+}
+
+// Bin of coordinate v clamped to [0, n-1] (non-finite -> 0).
+__device__ inline int bin_of(double v, double o, double inv_h, int n) {
+  double f = (v - o) * inv_h;
+  if (!(f >= 0.0)) return 0;
+  if (f >= (double)n) return n - 1;
+  return (int)f;
+}
+
+// Single-workgroup exclusive scan (1024 threads) of n int64 counts in place;
+// out[n] receives the total. Used for small scans (bins, rows).
+__global__ void k_scan_excl_i64(int64_t* data, int64_t n);
+__global__ void k_scan_excl_i32(int32_t* data, int64_t n);
+
+// Zero device memory with a kernel (no memset node, so the call is safe
+// inside stream capture).
+rbf_status fill_zero(rbf_ctx* ctx, void* p, size_t bytes);
+
+// Stable counting sort by a precomputed key in [0, nkeys): writes perm
+// (sorted position -> item) and start (nkeys + 1 offsets).
+rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
+                           int32_t nkeys, int32_t* perm, int32_t* start);
+
+}  // namespace rbf
+
+#define RBF_HIP(ctx, call)                                               \
+  do {                                                                   \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess)                                                \
+      return ::rbf::fail((ctx), RBF_E_HIP, "%s failed: %s", #call,       \
+                         hipGetErrorString(e_));                         \
+  } while (0)
+
+#define RBF_TRY(expr)                 \
+  do {                                \
+    rbf_status s_ = (expr);           \
+    if (s_ != RBF_OK) return s_;      \
+  } while (0)
+
+#define RBF_LAUNCHED(ctx, what) RBF_TRY(::rbf::check_launch((ctx), (what)))
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -28,3 +28,14 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    import torch
+    from paper_2509_26222_amd import api
+    c = api.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+

@@ -1,0 +1,145 @@
+"""rbf_eval (f, grad f, residual, Jacobian) against the FP64 oracle.
+
+FP64 bound: each term w_j phi_j carries a few ulp of rounding, so
+|f_gpu - f| <= 1e-13 * sum_j |w_j phi_j| (and likewise for the gradient
+with |w_j phi_j (x - c_j)| / sigma^2). FP32 bound (the stated target):
+|f_gpu - f| <= 1e-4 m and ||grad_gpu - grad|| <= 1e-3 max(||grad||, 0.01),
+over points not within 1e-4 rc^2 of a cutoff circle (those are counted).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import dev, host
+from paper_2509_26222_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def abs_sums(q, c, w, sigma, cutoff):
+    Phi = O.phi_dense(q, c, sigma, cutoff)
+    A = np.abs(Phi * w[None, :])
+    dx = np.abs(q[:, 0:1] - c[None, :, 0])
+    dy = np.abs(q[:, 1:2] - c[None, :, 1])
+    return A.sum(1), (A * (dx + dy)).sum(1) / sigma ** 2
+
+
+def ambiguous(q, c, sigma, cutoff, rel=1e-4):
+    rc2 = (cutoff * sigma) ** 2
+    d2 = O.sq_dist(q, c)
+    return (np.abs(d2 - rc2) <= rel * rc2).any(axis=1)
+
+
+@pytest.fixture(scope="module")
+def small(ctx):
+    s = synth.small_case(0)
+    p = api.Params()
+    w, _ = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R,
+                         with_P=False)
+    grid = ctx.grid(p, dev(s.centers))
+    return s, p, w, grid
+
+
+def test_eval_xy_f64(ctx, small):
+    s, p, w, grid = small
+    out = ctx.eval(p, grid, dev(w), dev(s.queries))
+    f0, g0 = O.eval_height_grad(s.queries, s.centers, w, p.sigma, p.cutoff)
+    af, ag = abs_sums(s.queries, s.centers, w, p.sigma, p.cutoff)
+    assert np.all(np.abs(host(out["f"]) - f0) <= 1e-13 * af + 1e-300)
+    assert np.all(np.abs(host(out["grad"]) - g0).max(1) <= 1e-13 * ag + 1e-300)
+
+
+def test_eval_xy_f32(ctx, small):
+    s, p, w, grid = small
+    out = ctx.eval(p, grid, dev(w), dev(s.queries, torch.float32))
+    q32 = s.queries.astype(np.float32).astype(np.float64)
+    f0, g0 = O.eval_height_grad(q32, s.centers, w, p.sigma, p.cutoff)
+    ok = ~ambiguous(q32, s.centers, p.sigma, p.cutoff)
+    assert ok.sum() > 0.99 * len(ok)
+    ef = np.abs(host(out["f"]).astype(np.float64) - f0)[ok]
+    eg = np.linalg.norm(host(out["grad"]).astype(np.float64) - g0, axis=1)[ok]
+    gn = np.maximum(np.linalg.norm(g0, axis=1)[ok], 0.01)
+    print(f"f32 xy: max|df| {ef.max():.2e} m, max grad rel {np.max(eg / gn):.2e}, "
+          f"ambiguous {int((~ok).sum())}")
+    assert ef.max() <= 1e-4
+    assert np.max(eg / gn) <= 1e-3
+
+
+def _scan_points(s, w, p, n, seed):
+    rng = np.random.default_rng(seed)
+    R = synth.rot_zyx(0.4, 0.06, -0.03)
+    t = np.array([5.0, 5.0, 0.6])
+    xy = rng.uniform(-0.5, 10.5, size=(n, 2))  # includes points off the map
+    z = s.terrain.height(xy) + rng.normal(0, 0.02, size=n)
+    world = np.concatenate([xy, z[:, None]], 1)
+    return np.ascontiguousarray((world - t) @ R), R, t
+
+
+@pytest.mark.parametrize("n", [1, 63, 257, 5003])
+def test_eval_pose_f64(ctx, small, n):
+    s, p, w, grid = small
+    pts, R, t = _scan_points(s, w, p, n, 7 + n)
+    out = ctx.eval(p, grid, dev(w), dev(pts), pose=(R, t), z_off=0.03)
+    f0, g0, r0, J0 = O.eval_pose(pts, R, t, 0.03, s.centers, w, p.sigma, p.cutoff)
+    xi = O.to_world(pts, R, t)
+    af, ag = abs_sums(xi[:, :2], s.centers, w, p.sigma, p.cutoff)
+    assert np.all(np.abs(host(out["f"]) - f0) <= 1e-13 * af + 1e-14)
+    assert np.all(np.abs(host(out["resid"]) - r0) <= 1e-13 * af + 1e-14)
+    assert np.all(np.abs(host(out["grad"]) - g0).max(1) <= 1e-13 * ag + 1e-14)
+    scale = 1.0 + np.abs(pts).max(1)
+    assert np.all(np.abs(host(out["jac"]) - J0).max(1) <= 1e-13 * scale * (ag + 1.0))
+
+
+def test_eval_pose_f32(ctx, small):
+    s, p, w, grid = small
+    pts, R, t = _scan_points(s, w, p, 20000, 3)
+    out = ctx.eval(p, grid, dev(w), dev(pts, torch.float32), pose=(R, t), z_off=0.0)
+    p32 = pts.astype(np.float32).astype(np.float64)
+    f0, g0, r0, J0 = O.eval_pose(p32, R, t, 0.0, s.centers, w, p.sigma, p.cutoff)
+    xi = O.to_world(p32, R, t)
+    ok = ~ambiguous(xi[:, :2], s.centers, p.sigma, p.cutoff)
+    ef = np.abs(host(out["f"]).astype(np.float64) - f0)[ok]
+    er = np.abs(host(out["resid"]).astype(np.float64) - r0)[ok]
+    eg = np.linalg.norm(host(out["grad"]).astype(np.float64) - g0, axis=1)[ok]
+    gn = np.maximum(np.linalg.norm(g0, axis=1)[ok], 0.01)
+    print(f"f32 pose: max|df| {ef.max():.2e}, max|dr| {er.max():.2e}, "
+          f"grad rel {np.max(eg / gn):.2e}, ambiguous {int((~ok).sum())}")
+    assert ef.max() <= 1e-4 and er.max() <= 1e-4
+    assert np.max(eg / gn) <= 1e-3
+
+
+def test_eval_empty_and_far(ctx, small):
+    s, p, w, grid = small
+    out = ctx.eval(p, grid, dev(w), torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
+    assert out["f"].numel() == 0
+    far = np.array([[-100.0, 5.0], [5.0, 1e6], [np.nan, 1.0], [30.0, 30.0]])
+    out = ctx.eval(p, grid, dev(w), dev(far))
+    assert np.all(host(out["f"])[[0, 1, 3]] == 0.0)
+
+
+def test_eval_full_size_odometry_sampled(ctx):
+    """200k scan points of one odometry frame on 10k centers, in the launch
+    configuration the benchmark times; 2000 sampled points vs the oracle."""
+    od = synth.OdometryCase()
+    p = api.Params()
+    allxy = np.concatenate([od.ground_xy(k) for k in range(od.N_FRAMES)])
+    centers = O.select_centers(allxy, od.roi, 0.5, 0.5, 4, O.VOXEL)
+    assert centers.shape[0] == 10000
+    rng = np.random.default_rng(0)
+    w = rng.normal(0, 0.3, size=centers.shape[0])
+    grid = ctx.grid(p, dev(centers))
+    pts, R, t = od.scan(10)
+    idx = rng.choice(pts.shape[0], 2000, replace=False)
+    f0, g0, r0, J0 = O.eval_pose(pts[idx], R, t, 0.0, centers, w, p.sigma, p.cutoff)
+    for dt in (torch.float64, torch.float32):
+        out = ctx.eval(p, grid, dev(w), dev(pts, dt), pose=(R, t))
+        f = host(out["f"]).astype(np.float64)[idx]
+        r = host(out["resid"]).astype(np.float64)[idx]
+        if dt == torch.float64:
+            assert np.abs(f - f0).max() <= 1e-12
+            assert np.abs(r - r0).max() <= 1e-12
+        else:
+            xi = O.to_world(pts[idx].astype(np.float32).astype(np.float64), R, t)
+            ok = ~ambiguous(xi[:, :2], centers, p.sigma, p.cutoff)
+            assert np.abs(f - f0)[ok].max() <= 1e-4
