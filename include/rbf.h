@@ -259,6 +259,27 @@ rbf_status rbf_eval_adjoint(rbf_ctx* ctx, const rbf_params* params,
                             const void* gbar_f, const void* gbar_r,
                             void* d_pts, double* d_w, double* d_pose);
 
+/* ----------------------------------------------------------- diagnostics */
+
+/* Kernel timing with HIP events recorded on the context stream around each
+ * launch of a kernel family (for roofline figures). Off by default; do not
+ * enable while the stream is being captured into a graph. */
+enum {
+  RBF_PROF_SYRK = 0,   /* covariance product P -= V V^T                   */
+  RBF_PROF_EVAL = 1,   /* evaluation kernel of rbf_eval                   */
+  RBF_PROF_TRSM = 2,   /* V^T = L^{-1} U^T of rbf_update                  */
+  RBF_PROF_CHOL = 3,   /* Cholesky of S (all launches of one batch)       */
+  RBF_PROF_GATHER = 4, /* U^T = H P gather of rbf_update                  */
+  RBF_PROF_KINDS = 5
+};
+/* Enable (non-zero) or disable timing; enabling clears the accumulators. */
+rbf_status rbf_profile_enable(rbf_ctx* ctx, int32_t enable);
+/* Synchronise, then report the summed elapsed time (ms, host) and the
+ * number of timed launches (host) of one kind since the last read, and
+ * reset that kind. */
+rbf_status rbf_profile_read(rbf_ctx* ctx, int32_t kind, double* total_ms,
+                            int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,7 +59,10 @@ SIGNATURES = {
                            C.c_int, vp, vp, vp, vp]),
     "rbf_eval_adjoint": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl),
                                    C.c_int, vp, vp, vp, vp, vp]),
+    "rbf_profile_enable": (C.c_int, [vp, i32]),
+    "rbf_profile_read": (C.c_int, [vp, i32, C.POINTER(dbl), C.POINTER(i64)]),
 }
+PROF_SYRK, PROF_EVAL, PROF_TRSM, PROF_CHOL, PROF_GATHER = range(5)
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

@@ -98,6 +98,16 @@ class Context:
         self._check(st, "device status")
         return st
 
+    def profile(self, enable: bool = True):
+        self._check(self.lib.rbf_profile_enable(self.h, int(enable)), "rbf_profile_enable")
+
+    def profile_read(self, kind: int):
+        """(total ms, launches) of one kernel family since the last read."""
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self.lib.rbf_profile_read(self.h, kind, C.byref(ms), C.byref(n)),
+                    "rbf_profile_read")
+        return ms.value, n.value
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.rbf_ctx_destroy(self.h)

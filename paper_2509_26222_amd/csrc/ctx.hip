@@ -124,6 +124,26 @@ rbf_status fill_zero(rbf_ctx* ctx, void* p, size_t bytes) {
   return RBF_OK;
 }
 
+// --------------------------------------------------------- kernel timing
+
+void prof_begin(rbf_ctx* ctx, int kind) {
+  if (!ctx->prof_on || !ctx->prof_ev[kind]) return;
+  const int n = ctx->prof_n[kind];
+  if (n >= PROF_CAP) {
+    ctx->prof_dropped[kind]++;
+    return;
+  }
+  (void)hipEventRecord(ctx->prof_ev[kind][2 * n], ctx->stream);
+}
+
+void prof_end(rbf_ctx* ctx, int kind) {
+  if (!ctx->prof_on || !ctx->prof_ev[kind]) return;
+  const int n = ctx->prof_n[kind];
+  if (n >= PROF_CAP) return;
+  (void)hipEventRecord(ctx->prof_ev[kind][2 * n + 1], ctx->stream);
+  ctx->prof_n[kind] = n + 1;
+}
+
 // ------------------------------------------------------ stable key sort
 //
 // Items are cut into chunks of SORT_CHUNK. counts[c * nkeys + k] counts key
@@ -256,6 +276,11 @@ rbf_status rbf_ctx_destroy(rbf_ctx* ctx) {
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
+  for (int k = 0; k < RBF_PROF_KINDS; ++k) {
+    if (!ctx->prof_ev[k]) continue;
+    for (int e = 0; e < 2 * PROF_CAP; ++e) (void)hipEventDestroy(ctx->prof_ev[k][e]);
+    delete[] ctx->prof_ev[k];
+  }
   delete ctx;
   return RBF_OK;
 }
@@ -283,6 +308,46 @@ rbf_status rbf_sync_status(rbf_ctx* ctx) {
                 rbf_status_string((rbf_status)h[0]), (long long)idx);
   }
   ctx->last_index = -1;
+  return RBF_OK;
+}
+
+rbf_status rbf_profile_enable(rbf_ctx* ctx, int32_t enable) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  RBF_TRY(set_device(ctx));
+  if (enable) {
+    for (int k = 0; k < RBF_PROF_KINDS; ++k) {
+      if (!ctx->prof_ev[k]) {
+        ctx->prof_ev[k] = new (std::nothrow) hipEvent_t[2 * PROF_CAP];
+        if (!ctx->prof_ev[k]) return RBF_E_NOMEM;
+        for (int e = 0; e < 2 * PROF_CAP; ++e)
+          RBF_HIP(ctx, hipEventCreate(&ctx->prof_ev[k][e]));
+      }
+      ctx->prof_n[k] = 0;
+      ctx->prof_dropped[k] = 0;
+    }
+  }
+  ctx->prof_on = enable ? 1 : 0;
+  return RBF_OK;
+}
+
+rbf_status rbf_profile_read(rbf_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!ctx || kind < 0 || kind >= RBF_PROF_KINDS || !total_ms || !launches)
+    return RBF_E_INVALID_ARG;
+  *total_ms = 0.0;
+  *launches = 0;
+  if (!ctx->prof_ev[kind]) return RBF_OK;
+  RBF_TRY(set_device(ctx));
+  RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (int e = 0; e < ctx->prof_n[kind]; ++e) {
+    float ms = 0.f;
+    RBF_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_ev[kind][2 * e], ctx->prof_ev[kind][2 * e + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = ctx->prof_n[kind];
+  ctx->prof_n[kind] = 0;
+  ctx->prof_dropped[kind] = 0;
   return RBF_OK;
 }
 

@@ -281,6 +281,7 @@ static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, c
   RBF_TRY(pack<T>(ctx, g, w, &tab));
   EvalK<T> k = make_consts<T>(p, pose, z_off);
   const int64_t blocks = ceil_div(Q, 256);
+  prof_begin(ctx, RBF_PROF_EVAL);
   if (dim == 3)
     k_eval<T, true><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->d_start, geom(g),
                                                      k, (T*)f, (T*)grad, (T*)resid, (T*)jac);
@@ -289,6 +290,7 @@ static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, c
                                                       geom(g), k, (T*)f, (T*)grad, nullptr,
                                                       nullptr);
   RBF_LAUNCHED(ctx, "k_eval");
+  prof_end(ctx, RBF_PROF_EVAL);
   return RBF_OK;
 }
 

@@ -51,6 +51,11 @@ struct rbf_ctx {
   char err[512];
   int64_t tiles_key;  // cached SYRK schedule key (N, tile)
   int64_t tiles_count;
+  // kernel timing (rbf_profile_*): event pairs per kind
+  int32_t prof_on;
+  hipEvent_t* prof_ev[RBF_PROF_KINDS];
+  int32_t prof_n[RBF_PROF_KINDS];
+  int32_t prof_dropped[RBF_PROF_KINDS];
 };
 
 struct rbf_grid {
@@ -122,6 +127,11 @@ __device__ inline int bin_of(double v, double o, double inv_h, int n) {
 // out[n] receives the total. Used for small scans (bins, rows).
 __global__ void k_scan_excl_i64(int64_t* data, int64_t n);
 __global__ void k_scan_excl_i32(int32_t* data, int64_t n);
+
+// Kernel timing: record the opening / closing event of one timed launch.
+constexpr int PROF_CAP = 4096;  // event pairs kept per kind between reads
+void prof_begin(rbf_ctx* ctx, int kind);
+void prof_end(rbf_ctx* ctx, int kind);
 
 // Zero device memory with a kernel (no memset node, so the call is safe
 // inside stream capture).

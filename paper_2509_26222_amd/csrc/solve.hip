@@ -1,8 +1,345 @@
-// Sparse solve with FP64 iterative refinement.
-#include "internal.hpp"
+// Sparse solve calH X = B (the "sparse kernel matrix inversion" of the GPU
+// section), with iterative refinement in FP64.
+//
+// calH couples only centers closer than 2 cutoff sigma_t, so with centers in
+// a spatial (mesh) order its bandwidth bw is small against N. The rows are
+// cut into blocks of s >= bw (a multiple of 64): calH is then block
+// tridiagonal with dense s x s diagonal blocks D_i and super-diagonal blocks
+// U_i = E_i^T. Block Cholesky:
+//   D_0 = L_0 L_0^T;  G_i = L_i^{-1} U_i;  D_{i+1} - G_i^T G_i = L_{i+1} L_{i+1}^T
+// so calH = L L^T with L block bidiagonal (diagonal L_i, sub-diagonal
+// G_i^T). A solve is a forward sweep y_i = L_i^{-1} (r_i - G_{i-1}^T y_{i-1})
+// and a backward sweep x_i = L_i^{-T} (y_i - G_i x_{i+1}). Refinement:
+// x += solve(b - calH x) until ||b - calH x|| <= rtol ||b|| per column.
+// Dense blocks use the FP64 MFMA kernels of the covariance update.
+#include <cmath>
+#include <vector>
 
-extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t, const int64_t*, const int32_t*,
-                                const double*, const double*, int64_t, double*, int64_t,
-                                int64_t, double, int32_t, rbf_prec, double*, int32_t*) {
-  return rbf::fail(ctx, RBF_E_INVALID_ARG, "rbf_solve: not built yet");
+#include "internal.hpp"
+#include "update.hpp"
+
+namespace rbf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline bool sfailed(const int32_t* st) { return *(volatile const int32_t*)st != 0; }
+
+__global__ void __launch_bounds__(256) k_csr_bandwidth(const int64_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ colidx,
+                                                       int64_t N, int32_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= N) return;
+  int64_t bw = 0;
+  bool bad = false;
+  for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int64_t c = colidx[e];
+    if (c < 0 || c >= N) bad = true;
+    const int64_t d = c > r ? c - r : r - c;
+    bw = d > bw ? d : bw;
+  }
+  atomicMax(out, bad ? INT32_MAX : (int32_t)bw);
+}
+
+// D_i[a][b] and U_i[a][b] from the CSR rows; padding rows get D = I.
+__global__ void __launch_bounds__(256) k_csr_to_blocks(const int64_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ colidx,
+                                                       const double* __restrict__ vals,
+                                                       int64_t N, int32_t s, int32_t nblk,
+                                                       double* __restrict__ D,
+                                                       double* __restrict__ U) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= (int64_t)nblk * s) return;
+  const int64_t i = r / s, a = r % s;
+  const int64_t ss = (int64_t)s * s;
+  if (r >= N) {
+    D[i * ss + a * s + a] = 1.0;
+    return;
+  }
+  for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int64_t c = colidx[e];
+    const int64_t bi = c / s, b = c % s;
+    if (bi == i)
+      D[i * ss + a * s + b] = vals[e];
+    else if (bi == i + 1)
+      U[i * ss + a * s + b] = vals[e];
+  }
+}
+
+// C[m][n] -= sum_k op(A)[m][k] B[k][n] on FP64 MFMA; op(A) = A (M x K) or
+// A^T (A is K x M). 64x64 output tile per workgroup, K in chunks of 16.
+constexpr int GT = 64, GK = 16;
+
+template <bool TA>
+__global__ void __launch_bounds__(256) k_gemm_sub(int64_t M, int64_t Nc, int64_t K,
+                                                  const double* __restrict__ A, int64_t lda,
+                                                  const double* __restrict__ B, int64_t ldb,
+                                                  double* __restrict__ C, int64_t ldc,
+                                                  const int32_t* __restrict__ status) {
+  if (sfailed(status)) return;
+  __shared__ double As[GK][GT + 1];  // As[k][m]
+  __shared__ double Bs[GK][GT + 1];  // Bs[k][n]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * GT, n0 = (int64_t)blockIdx.x * GT;
+  const int rb = 32 * (wave >> 1), cb = 32 * (wave & 1);
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = 0; k0 < K; k0 += GK) {
+    // 16 x 64 elements of each operand: 4 per thread
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      const int kk = e >> 6, mm = e & 63;
+      const int64_t gk = k0 + kk, gm = m0 + mm, gn = n0 + mm;
+      double av = 0.0, bv = 0.0;
+      if (gk < K && gm < M) av = TA ? A[gk * lda + gm] : A[gm * lda + gk];
+      if (gk < K && gn < Nc) bv = B[gk * ldb + gn];
+      As[kk][mm] = av;
+      Bs[kk][mm] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GK; k += 4) {
+      const int kk = k + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        a[u] = As[kk][rb + 16 * u + (lane & 15)];
+        b[u] = Bs[kk][cb + 16 * u + (lane & 15)];
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + rb + 16 * mi + 4 * v + (lane >> 4);
+        const int64_t gn = n0 + cb + 16 * ni + (lane & 15);
+        if (gm < M && gn < Nc) C[gm * ldc + gn] -= acc[mi][ni][v];
+      }
+}
+
+static rbf_status gemm_sub(rbf_ctx* ctx, bool ta, int64_t M, int64_t Nc, int64_t K,
+                           const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                           int64_t ldc) {
+  dim3 grid((unsigned)ceil_div(Nc, GT), (unsigned)ceil_div(M, GT));
+  if (ta)
+    k_gemm_sub<true><<<grid, 256, 0, ctx->stream>>>(M, Nc, K, A, lda, B, ldb, C, ldc,
+                                                    ctx->d_status);
+  else
+    k_gemm_sub<false><<<grid, 256, 0, ctx->stream>>>(M, Nc, K, A, lda, B, ldb, C, ldc,
+                                                     ctx->d_status);
+  RBF_LAUNCHED(ctx, "k_gemm_sub");
+  return RBF_OK;
+}
+
+// Y (padded rows, ld nrhs) = R (N rows, ld ldr); padding rows zero.
+__global__ void __launch_bounds__(256) k_pad_copy(const double* __restrict__ R, int64_t ldr,
+                                                  int64_t N, int64_t Np, int64_t nrhs,
+                                                  double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= Np * nrhs) return;
+  const int64_t r = e / nrhs, c = e % nrhs;
+  Y[e] = r < N ? R[r * ldr + c] : 0.0;
+}
+
+// X (ld ldx) (+)= Y[:N]
+__global__ void __launch_bounds__(256) k_accum(double* __restrict__ X, int64_t ldx,
+                                               const double* __restrict__ Y, int64_t N,
+                                               int64_t nrhs, int32_t first) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N * nrhs) return;
+  const int64_t r = e / nrhs, c = e % nrhs;
+  X[r * ldx + c] = first ? Y[e] : X[r * ldx + c] + Y[e];
+}
+
+// R = B - calH X (FP64); one thread per (row, column).
+__global__ void __launch_bounds__(256) k_residual(const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colidx,
+                                                  const double* __restrict__ vals, int64_t N,
+                                                  const double* __restrict__ B, int64_t ldb,
+                                                  const double* __restrict__ X, int64_t ldx,
+                                                  int64_t nrhs, double* __restrict__ R) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N * nrhs) return;
+  const int64_t r = e / nrhs, c = e % nrhs;
+  double s = B[r * ldb + c];
+  for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) s -= vals[k] * X[(int64_t)colidx[k] * ldx + c];
+  R[r * nrhs + c] = s;
+}
+
+// Column sums of squares: part[g][c] over row group g (1024 rows), then
+// out[c] = sum_g part[g][c] in order.
+constexpr int NRG = 1024;
+__global__ void __launch_bounds__(256) k_colsq_part(const double* __restrict__ A, int64_t lda,
+                                                    int64_t N, int64_t nrhs,
+                                                    double* __restrict__ part) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= nrhs) return;
+  const int64_t r0 = (int64_t)blockIdx.y * NRG;
+  const int64_t r1 = r0 + NRG < N ? r0 + NRG : N;
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double v = A[r * lda + c];
+    s += v * v;
+  }
+  part[(int64_t)blockIdx.y * nrhs + c] = s;
+}
+
+__global__ void __launch_bounds__(256) k_colsq_sum(const double* __restrict__ part, int64_t nrhs,
+                                                   int32_t ngroups, double* __restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= nrhs) return;
+  double s = 0.0;
+  for (int g = 0; g < ngroups; ++g) s += part[(int64_t)g * nrhs + c];
+  out[c] = s;
+}
+
+static rbf_status col_norms(rbf_ctx* ctx, const double* A, int64_t lda, int64_t N, int64_t nrhs,
+                            double* part, double* dout, std::vector<double>& host) {
+  const int32_t ng = (int32_t)ceil_div(N, NRG);
+  dim3 g1((unsigned)ceil_div(nrhs, 256), (unsigned)ng);
+  k_colsq_part<<<g1, 256, 0, ctx->stream>>>(A, lda, N, nrhs, part);
+  RBF_LAUNCHED(ctx, "k_colsq_part");
+  k_colsq_sum<<<ceil_div(nrhs, 256), 256, 0, ctx->stream>>>(part, nrhs, ng, dout);
+  RBF_LAUNCHED(ctx, "k_colsq_sum");
+  host.resize(nrhs);
+  RBF_HIP(ctx, hipMemcpyAsync(host.data(), dout, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& v : host) v = std::sqrt(v);
+  return RBF_OK;
+}
+
+}  // namespace rbf
+
+using namespace rbf;
+
+extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
+                                const int32_t* colidx, const double* vals, const double* B,
+                                int64_t ldb, double* X, int64_t ldx, int64_t nrhs, double rtol,
+                                int32_t max_iter, rbf_prec inner, double* relres,
+                                int32_t* iters) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  if (iters) *iters = 0;
+  if (N <= 0 || N >= ((int64_t)1 << 31) || !rowptr || !colidx || !vals || !B || !X ||
+      nrhs <= 0 || ldb < nrhs || ldx < nrhs || !(rtol > 0) || max_iter < 1)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_solve: bad arguments");
+  if (inner != RBF_F64)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_solve: inner precision %d not available",
+                (int)inner);
+  RBF_TRY(set_device(ctx));
+  rbf_status st;
+  // ---- bandwidth -> block size
+  int32_t* d_bw = (int32_t*)ws_get(ctx, WS_SOLVE6, 256, &st);
+  if (!d_bw) return st;
+  RBF_TRY(fill_zero(ctx, d_bw, sizeof(int32_t)));
+  k_csr_bandwidth<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(rowptr, colidx, N, d_bw);
+  RBF_LAUNCHED(ctx, "k_csr_bandwidth");
+  int32_t bw = 0;
+  RBF_HIP(ctx, hipMemcpyAsync(&bw, d_bw, sizeof(bw), hipMemcpyDeviceToHost, ctx->stream));
+  RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (bw == INT32_MAX) return fail(ctx, RBF_E_INVALID_ARG, "rbf_solve: column index out of range");
+  const int64_t s = ceil_div(bw > 0 ? bw : 1, 64) * 64;
+  const int64_t nblk = ceil_div(N, s);
+  const int64_t Np = nblk * s;
+  const int64_t ss = s * s;
+  if (s > 16384)
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_solve: bandwidth %d too large (order the centers spatially)", bw);
+  // ---- workspace
+  double* D = (double*)ws_get(ctx, WS_SOLVE0, sizeof(double) * nblk * ss, &st);
+  if (!D) return st;
+  double* Ub = (double*)ws_get(ctx, WS_SOLVE1, sizeof(double) * nblk * ss, &st);
+  if (!Ub) return st;
+  double* Lb = (double*)ws_get(ctx, WS_SOLVE2, sizeof(double) * nblk * ss, &st);
+  if (!Lb) return st;
+  const int64_t nsub = s / 64;
+  double* Linv = (double*)ws_get(ctx, WS_SOLVE3, sizeof(double) * nblk * nsub * 4096, &st);
+  if (!Linv) return st;
+  double* Y = (double*)ws_get(ctx, WS_SOLVE4, sizeof(double) * Np * nrhs, &st);
+  if (!Y) return st;
+  double* Rr = (double*)ws_get(ctx, WS_SOLVE5, sizeof(double) * N * nrhs, &st);
+  if (!Rr) return st;
+  const int32_t ngroups = (int32_t)ceil_div(N, NRG);
+  double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (ngroups + 1) * nrhs, &st);
+  if (!part) return st;
+  double* dnorm = (double*)ws_get(ctx, WS_TMP2, sizeof(double) * nrhs, &st);
+  if (!dnorm) return st;
+  // ---- blocks
+  RBF_TRY(fill_zero(ctx, D, sizeof(double) * nblk * ss));
+  RBF_TRY(fill_zero(ctx, Ub, sizeof(double) * nblk * ss));
+  k_csr_to_blocks<<<ceil_div(Np, 256), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, (int32_t)s,
+                                                              (int32_t)nblk, D, Ub);
+  RBF_LAUNCHED(ctx, "k_csr_to_blocks");
+  // ---- block Cholesky
+  for (int64_t i = 0; i < nblk; ++i) {
+    double* Di = D + i * ss;
+    if (i > 0) RBF_TRY(gemm_sub(ctx, true, s, s, s, Ub + (i - 1) * ss, s, Ub + (i - 1) * ss, s, Di, s));
+    RBF_TRY(chol_blocked(ctx, Di, (int32_t)s, Lb + i * ss, Linv + i * nsub * 4096, i));
+    if (i + 1 < nblk)
+      RBF_TRY(trsm_blocks(ctx, Ub + i * ss, s, s, (int32_t)nsub, Lb + i * ss, s,
+                          Linv + i * nsub * 4096, false));
+  }
+  {
+    int32_t h[4];
+    RBF_HIP(ctx, hipMemcpyAsync(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h[0] != 0) return rbf_sync_status(ctx);
+  }
+  // ---- refinement
+  std::vector<double> bn, rn;
+  RBF_TRY(col_norms(ctx, B, ldb, N, nrhs, part, dnorm, bn));
+  const double* R = B;
+  int64_t ldr = ldb;
+  int32_t it = 0;
+  bool conv = false;
+  for (it = 0; it < max_iter && !conv; ++it) {
+    k_pad_copy<<<ceil_div(Np * nrhs, 256), 256, 0, ctx->stream>>>(R, ldr, N, Np, nrhs, Y);
+    RBF_LAUNCHED(ctx, "k_pad_copy");
+    for (int64_t i = 0; i < nblk; ++i) {
+      double* Yi = Y + i * s * nrhs;
+      if (i > 0)
+        RBF_TRY(gemm_sub(ctx, true, s, nrhs, s, Ub + (i - 1) * ss, s, Yi - s * nrhs, nrhs, Yi,
+                         nrhs));
+      RBF_TRY(trsm_blocks(ctx, Yi, nrhs, nrhs, (int32_t)nsub, Lb + i * ss, s,
+                          Linv + i * nsub * 4096, false));
+    }
+    for (int64_t i = nblk - 1; i >= 0; --i) {
+      double* Yi = Y + i * s * nrhs;
+      if (i + 1 < nblk)
+        RBF_TRY(gemm_sub(ctx, false, s, nrhs, s, Ub + i * ss, s, Yi + s * nrhs, nrhs, Yi, nrhs));
+      RBF_TRY(trsm_blocks(ctx, Yi, nrhs, nrhs, (int32_t)nsub, Lb + i * ss, s,
+                          Linv + i * nsub * 4096, true));
+    }
+    k_accum<<<ceil_div(N * nrhs, 256), 256, 0, ctx->stream>>>(X, ldx, Y, N, nrhs, it == 0);
+    RBF_LAUNCHED(ctx, "k_accum");
+    k_residual<<<ceil_div(N * nrhs, 256), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, B, ldb,
+                                                                 X, ldx, nrhs, Rr);
+    RBF_LAUNCHED(ctx, "k_residual");
+    R = Rr;
+    ldr = nrhs;
+    RBF_TRY(col_norms(ctx, Rr, nrhs, N, nrhs, part, dnorm, rn));
+    conv = true;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double rel = bn[c] > 0 ? rn[c] / bn[c] : rn[c];
+      if (relres) relres[c] = rel;
+      if (!(rel <= rtol)) conv = false;
+    }
+  }
+  if (iters) *iters = it;
+  RBF_TRY(rbf_sync_status(ctx));
+  if (!conv)
+    return fail(ctx, RBF_E_NO_CONVERGE, "rbf_solve: relres above %g after %d sweeps", rtol, it);
+  return RBF_OK;
 }

@@ -140,9 +140,11 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
   const int64_t nt = ceil_div(N, ST);
   const int64_t T = nt * (nt + 1) / 2;
   const int64_t per_xcd = ceil_div(T, 8);
+  prof_begin(ctx, RBF_PROF_SYRK);
   k_syrk_f64<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T,
                                                                per_xcd, ctx->d_status);
   RBF_LAUNCHED(ctx, "k_syrk_f64");
+  prof_end(ctx, RBF_PROF_SYRK);
   return RBF_OK;
 }
 

@@ -20,6 +20,8 @@
 
 namespace rbf {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 constexpr int NB = 64;       // Cholesky / TRSM block size
 constexpr int LDT = NB + 1;  // padded LDS row of a 64x64 tile
 
@@ -31,7 +33,8 @@ __device__ inline bool failed(const int32_t* st) { return *(volatile const int32
 
 // ------------------------------------------------------------ batch rows
 
-// Regressor rows of the batch (ELL), innovation y = z - H w into U^T[:, N].
+// Regressor rows of the batch in column-major ELL (entry q of row b at
+// q * Bp + b), and the innovation y = z - H w into U^T[:, N].
 __global__ void __launch_bounds__(256) k_upd_rows(
     const double* __restrict__ xy, const double* __restrict__ z, int32_t Bc, int32_t Bp,
     const double* __restrict__ cxy, const int32_t* __restrict__ idx,
@@ -47,8 +50,6 @@ __global__ void __launch_bounds__(256) k_upd_rows(
     return;
   }
   const double x = xy[2 * b], y = xy[2 * b + 1];
-  double* vrow = vals + (int64_t)b * kmax;
-  int32_t* crow = cols + (int64_t)b * kmax;
   int n = 0;
   double hw = 0.0;
   int bx0, bx1, by0, by1;
@@ -63,8 +64,8 @@ __global__ void __launch_bounds__(256) k_upd_rows(
         if (d2 <= k.rc2 && n < kmax) {
           const double v = k.scale * exp(-d2 / k.den);
           const int32_t c = idx[s];
-          vrow[n] = v;
-          crow[n] = c;
+          vals[(int64_t)n * Bp + b] = v;
+          cols[(int64_t)n * Bp + b] = c;
           hw += v * w[c];
           ++n;
         }
@@ -82,9 +83,9 @@ __global__ void __launch_bounds__(256) k_upd_rows(
 // U^T[b, n] = sum_k vals[b,k] P[cols[b,k], n]  (P symmetric: rows of P).
 // Block: 8 batch rows x 1024 columns; each thread 4 columns.
 __global__ void __launch_bounds__(256) k_upd_gather_u(
-    const double* __restrict__ P, int64_t ldp, int64_t N, int32_t Bc,
+    const double* __restrict__ P, int64_t ldp, int64_t N, int32_t Bc, int32_t Bp,
     const double* __restrict__ vals, const int32_t* __restrict__ cols,
-    const int32_t* __restrict__ nnz, int32_t kmax, double* __restrict__ Ut, int64_t ldu,
+    const int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu,
     const int32_t* __restrict__ status) {
   if (failed(status)) return;
   const int64_t n0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
@@ -94,11 +95,9 @@ __global__ void __launch_bounds__(256) k_upd_gather_u(
     double acc[4] = {0, 0, 0, 0};
     if (b < Bc) {
       const int nz = nnz[b];
-      const double* vr = vals + (int64_t)b * kmax;
-      const int32_t* cr = cols + (int64_t)b * kmax;
       for (int q = 0; q < nz; ++q) {
-        const double v = vr[q];
-        const double* prow = P + (int64_t)cr[q] * ldp;
+        const double v = vals[(int64_t)q * Bp + b];
+        const double* prow = P + (int64_t)cols[(int64_t)q * Bp + b] * ldp;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t n = n0 + 256 * u;
@@ -118,7 +117,7 @@ __global__ void __launch_bounds__(256) k_upd_gather_u(
 // padding rows a >= Bc carry the identity.
 __global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
                                                const int32_t* __restrict__ cols,
-                                               const int32_t* __restrict__ nnz, int32_t kmax,
+                                               const int32_t* __restrict__ nnz,
                                                const double* __restrict__ Ut, int64_t ldu,
                                                int32_t Bc, int32_t Bp, double R,
                                                double* __restrict__ S,
@@ -132,87 +131,176 @@ __global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
     s = (a == b) ? R : 0.0;
     const double* ub = Ut + (int64_t)b * ldu;
     const int nz = nnz[a];
-    const double* vr = vals + (int64_t)a * kmax;
-    const int32_t* cr = cols + (int64_t)a * kmax;
-    for (int q = 0; q < nz; ++q) s += vr[q] * ub[cr[q]];
+    for (int q = 0; q < nz; ++q) s += vals[(int64_t)q * Bp + a] * ub[cols[(int64_t)q * Bp + a]];
   } else {
     s = (a == b) ? 1.0 : 0.0;
   }
   S[(int64_t)a * Bp + b] = s;
 }
 
-// ------------------------------------------------------------- Cholesky
+// ------------------------------------------------------------- 64x64 tiles
 
-// Load a 64x64 block of a row-major matrix into an LDS tile.
+// All 16 loads of a thread are issued before the first LDS store, so a tile
+// costs one memory latency rather than sixteen.
 __device__ inline void load_tile(double (*T)[LDT], const double* __restrict__ A, int64_t lda) {
-  for (int e = threadIdx.x; e < NB * NB; e += 256) T[e >> 6][e & 63] = A[(int64_t)(e >> 6) * lda + (e & 63)];
+  double v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    v[u] = A[(int64_t)(e >> 6) * lda + (e & 63)];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    T[e >> 6][e & 63] = v[u];
+  }
 }
 
 __device__ inline void store_tile(const double (*T)[LDT], double* __restrict__ A, int64_t lda) {
-  for (int e = threadIdx.x; e < NB * NB; e += 256) A[(int64_t)(e >> 6) * lda + (e & 63)] = T[e >> 6][e & 63];
-}
-
-// acc (4x4 micro-tile at rows r0.., cols c0..) = X Y^T over 64 (both LDS).
-__device__ inline void mm_nt(const double (*X)[LDT], const double (*Y)[LDT], double acc[4][4],
-                             int r0, int c0) {
-  for (int q = 0; q < NB; ++q) {
-    double a[4], b[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = X[r0 + u][q];
-      b[u] = Y[c0 + u][q];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    A[(int64_t)(e >> 6) * lda + (e & 63)] = T[e >> 6][e & 63];
   }
 }
 
-// In-place Cholesky of the lower triangle of T (64x64), then Tinv = L^{-1}
-// (lower). Upper parts of both are set to zero. A non-positive or non-finite
-// pivot records RBF_E_NOT_SPD with `index`.
-__device__ void chol64(double (*T)[LDT], double (*Tinv)[LDT], int32_t* status, int64_t index) {
+// C = X Y^T for 64x64 LDS tiles on FP64 MFMA. Wave w owns the 32x32
+// quadrant (w >> 1, w & 1); acc[mi][ni][v] is element
+// (32 (w>>1) + 16 mi + 4 v + lane/16, 32 (w&1) + 16 ni + lane%16).
+struct Acc64 {
+  v4d c[2][2];
+};
+
+__device__ inline int acc_row(int mi, int v) {
+  return 32 * ((threadIdx.x >> 6) >> 1) + 16 * mi + 4 * v + ((threadIdx.x & 63) >> 4);
+}
+__device__ inline int acc_col(int ni) {
+  return 32 * ((threadIdx.x >> 6) & 1) + 16 * ni + (threadIdx.x & 15);
+}
+
+__device__ inline void mm_nt(const double (*X)[LDT], const double (*Y)[LDT], Acc64& A) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb = 32 * (wave >> 1), cb = 32 * (wave & 1);
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) A.c[mi][ni] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < NB; k += 4) {
+    const int kk = k + (lane >> 4);
+    double a[2], b[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      a[u] = X[rb + 16 * u + (lane & 15)][kk];
+      b[u] = Y[cb + 16 * u + (lane & 15)][kk];
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        A.c[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], A.c[mi][ni], 0, 0, 0);
+  }
+}
+
+__device__ inline void acc_to_lds(const Acc64& A, double (*T)[LDT]) {
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[acc_row(mi, v)][acc_col(ni)] = A.c[mi][ni][v];
+}
+
+// In-place Cholesky of the lower triangle of T (64x64) and Tinv = L^{-1}.
+// Lane group g = tid / 4 (four lanes, part p = tid % 4) owns row g of L and
+// column g of L^{-1}, the entries with index = p mod 4 held in registers
+// (a[k] = L[g][4k+p], x[k] = Linv[4k+p][g]). Step j (fully unrolled):
+//   groups g >  j: L[g][j] = (A[g][j] - sum_{q<j} L[g][q] L[j][q]) / L[j][j]
+//                  (left-looking; row j is read from LDS), and group j+1
+//                  takes its pivot from its running remainder
+//                  r_g = A[g][g] - sum_q L[g][q]^2;
+//   groups c <= j: Linv[j][c] = (delta_jc - sum_{c<=q<j} L[j][q] Linv[q][c])
+//                  / L[j][j].
+// Partial sums of the four lanes meet through two lane shuffles; one
+// barrier per step. A non-positive or non-finite pivot records
+// RBF_E_NOT_SPD with `index` (the factor then continues with pivot 1).
+__device__ __noinline__ void chol64(double (*T)[LDT], double (*Tinv)[LDT], int32_t* status,
+                                    int64_t index) {
   const int tid = threadIdx.x;
-  __shared__ double piv;
+  const int g = tid >> 2, p = tid & 3;
   __shared__ int bad;
+  // v: row g of A / L while j < g, then (once row g is in LDS) column g of
+  // the inverse
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = T[g][4 * k + p];
+  double r = T[g][g];
+  __syncthreads();
   if (tid == 0) bad = 0;
+  if (g == 0) {
+    const bool ok = r > 0.0 && isfinite(r);
+    const double d = ok ? sqrt(r) : 1.0;
+    if (p == 0) {
+      if (!ok) bad = 1;
+      T[0][0] = d;
+    }
+  }
   __syncthreads();
+#pragma clang loop unroll(full)
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = T[j][j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
+    const double ljj = T[j][j];
+    if (g > j) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int k = 0; 4 * k < j; ++k) {
+        const int q = 4 * k + p;
+        const double t = (q < j) ? v[k] * T[j][q] : 0.0;
+        if (k & 1) s1 += t; else s0 += t;
       }
-      piv = sqrt(d);
-      T[j][j] = piv;
-    }
-    __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int i = j + 1 + tid; i < NB; i += 256) T[i][j] *= inv;
-    __syncthreads();
-    // trailing update of the lower triangle
-    const int m = NB - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = j + 1 + e / m, c = j + 1 + e % m;
-      if (c <= i) T[i][c] -= T[i][j] * T[c][j];
+      double sd = s0 + s1;
+      sd += __shfl_xor(sd, 1, 64);
+      sd += __shfl_xor(sd, 2, 64);
+      const double agj = __shfl(v[j >> 2], (tid & ~3) | (j & 3), 64);
+      const double l = (agj - sd) / ljj;
+      if (p == (j & 3)) {
+        v[j >> 2] = l;
+        T[g][j] = l;
+      }
+      r -= l * l;
+      if (g == j + 1) {
+        const bool ok = r > 0.0 && isfinite(r);
+        const double d = ok ? sqrt(r) : 1.0;
+        if (p == ((j + 1) & 3)) {
+          if (!ok) bad = 1;
+          T[g][g] = d;
+        }
+      }
+    } else {
+      if (g == j) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = 0.0;
+      }
+      // column c = g <= j of the inverse, row j
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int k = 0; 4 * k < j; ++k) {
+        const int q = 4 * k + p;
+        const double t = (q < j && q >= g) ? T[j][q] * v[k] : 0.0;
+        if (k & 1) s1 += t; else s0 += t;
+      }
+      double sd = s0 + s1;
+      sd += __shfl_xor(sd, 1, 64);
+      sd += __shfl_xor(sd, 2, 64);
+      const double xv = ((g == j ? 1.0 : 0.0) - sd) / ljj;
+      if (p == (j & 3)) v[j >> 2] = xv;
     }
     __syncthreads();
   }
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e >> 6, c = e & 63;
-    if (c > i) T[i][c] = 0.0;
-  }
-  __syncthreads();
-  // Tinv: forward substitution L X = I, one column per thread (64 columns)
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int q = c; q < i; ++q) s -= T[i][q] * Tinv[q][c];
-      Tinv[i][c] = (i < c) ? 0.0 : s / T[i][i];
-    }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int q = 4 * k + p;
+    Tinv[q][g] = (q >= g) ? v[k] : 0.0;
+    if (q > g) T[g][q] = 0.0;
   }
   __syncthreads();
   if (tid == 0 && bad) set_status(status, RBF_E_NOT_SPD, index);
@@ -261,132 +349,282 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
     i = kb + 1 + ii;
     j = kb + 1 + (u - ii * (ii + 1) / 2);
   }
-  const int tid = threadIdx.x;
-  const int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
-  const double* Lkk_inv = Linv + (int64_t)kb * NB * NB;
-  load_tile(Li, Lkk_inv, NB);
+  load_tile(Li, Linv + (int64_t)kb * NB * NB, NB);
   load_tile(T1, S + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
+  if (!panel && j != i) load_tile(T2, S + (int64_t)j * NB * Bp + (int64_t)kb * NB, Bp);
   __syncthreads();
-  double acc[4][4] = {};
-  mm_nt(T1, Li, acc, r0, c0);  // L_ik
+  Acc64 A;
+  mm_nt(T1, Li, A);  // L_ik = A_ik Linv_kk^T
   if (panel) {
+    double* out = Lb + (int64_t)i * NB * Bp + (int64_t)kb * NB;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Lb[(int64_t)(i * NB + r0 + u) * Bp + kb * NB + c0 + v] = acc[u][v];
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(int64_t)acc_row(mi, v) * Bp + acc_col(ni)] = A.c[mi][ni][v];
     return;
   }
+  Acc64 Bq;
+  if (j != i) mm_nt(T2, Li, Bq);  // L_jk
   __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) T2[r0 + u][c0 + v] = acc[u][v];  // T2 = L_ik
-  if (j != i) {
-    __syncthreads();
-    load_tile(T1, S + (int64_t)j * NB * Bp + (int64_t)kb * NB, Bp);
-    __syncthreads();
-    double bcc[4][4] = {};
-    mm_nt(T1, Li, bcc, r0, c0);  // L_jk
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T1[r0 + u][c0 + v] = bcc[u][v];
-  }
+  acc_to_lds(A, T1);  // T1 = L_ik
+  if (j != i) acc_to_lds(Bq, T2);  // T2 = L_jk
   __syncthreads();
-  double (*Lj)[LDT] = (j != i) ? T1 : T2;
-  double upd[4][4] = {};
-  mm_nt(T2, Lj, upd, r0, c0);  // L_ik L_jk^T
+  Acc64 U;
+  mm_nt(T1, (j != i) ? T2 : T1, U);  // L_ik L_jk^T
   double* Aij = S + (int64_t)i * NB * Bp + (int64_t)j * NB;
   if (i == kb + 1 && j == kb + 1) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Li[r0 + u][c0 + v] = Aij[(int64_t)(r0 + u) * Bp + c0 + v] - upd[u][v];
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = acc_row(mi, v), c = acc_col(ni);
+          Li[r][c] = Aij[(int64_t)r * Bp + c] - U.c[mi][ni][v];
+        }
     __syncthreads();
-    chol64(Li, T1, status, batch);
+    chol64(Li, T2, status, batch);
     store_tile(Li, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
-    store_tile(T1, Linv + (int64_t)i * NB * NB, NB);
+    store_tile(T2, Linv + (int64_t)i * NB * NB, NB);
     return;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Aij[(int64_t)(r0 + u) * Bp + c0 + v] -= upd[u][v];
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Aij[(int64_t)acc_row(mi, v) * Bp + acc_col(ni)] -= U.c[mi][ni][v];
 }
 
 // ----------------------------------------------------------------- TRSM
 
-// V^T = L^{-1} U^T in place on a slab of TW columns per workgroup:
-// X_i = Linv_ii (U_i - sum_{j<i} L_ij X_j), block rows in order.
-constexpr int TW = 16;
-__global__ void __launch_bounds__(256) k_upd_trsm(double* __restrict__ Ut, int64_t ldu,
-                                                  int64_t ncols, int32_t nblk,
-                                                  const double* __restrict__ Lb, int32_t Bp,
-                                                  const double* __restrict__ Linv,
-                                                  const int32_t* __restrict__ status) {
-  if (failed(status)) return;
-  __shared__ double Lt[NB][LDT];
-  __shared__ double X[NB][TW + 1];
-  const int tid = threadIdx.x;
-  const int64_t col0 = (int64_t)blockIdx.x * TW;
-  const int r = tid >> 2;          // row within the block (0..63)
-  const int cq = (tid & 3) * 4;    // 4 columns per thread
-  for (int i = 0; i < nblk; ++i) {
-    double acc[4];
+// Blocked triangular solve in place on a slab of TW = 32 columns per
+// workgroup, on FP64 MFMA, for a lower-triangular L held as off-diagonal
+// 64x64 blocks (Lb, leading dimension ldl) and inverses of its diagonal
+// blocks (Linv):
+//   TRANS = false: X := L^{-1} X,   X_i = Linv_ii (X_i - sum_{j<i} L_ij X_j),
+//                  block rows i = 0, 1, ...
+//   TRANS = true : X := L^{-T} X,   X_i = Linv_ii^T (X_i - sum_{j>i} L_ji^T X_j),
+//                  block rows i = nblk-1, ..., 0.
+// The work of a slab is a sequence of tile pairs (i, j) ending each block
+// row with (i, i), which applies the diagonal inverse; the next pair's tiles
+// are loaded into registers while the current pair computes. Wave w owns
+// rows 16w..16w+15 of a block row and both 16-column halves of the slab.
+constexpr int TW = 32;
+constexpr int LDX = TW + 1;
+
+struct TrsmPre {
+  double l[16];  // 64x64 tile: element (e >> 6, e & 63), e = tid + 256 u
+  double x[8];   // 64x32 tile (e / 32, e % 32), e = tid + 256 u; or X_i values
+};
+
+template <bool TRANS>
+__device__ inline void trsm_fetch(TrsmPre& pf, int i, int j, const double* __restrict__ Ut,
+                                  int64_t ldu, int64_t ncols, int64_t col0,
+                                  const double* __restrict__ Lb, int64_t ldl,
+                                  const double* __restrict__ Linv) {
+  const int tid = threadIdx.x, lane = tid & 63, rr = 16 * (tid >> 6);
+  const double* src;
+  int64_t lds;
+  if (j != i) {
+    src = TRANS ? Lb + (int64_t)j * NB * ldl + (int64_t)i * NB
+                : Lb + (int64_t)i * NB * ldl + (int64_t)j * NB;
+    lds = ldl;
+  } else {
+    src = Linv + (int64_t)i * NB * NB;
+    lds = NB;
+  }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t c = col0 + cq + v;
-      acc[v] = c < ncols ? Ut[(int64_t)(i * NB + r) * ldu + c] : 0.0;
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + 256 * u;
+    pf.l[u] = src[(int64_t)(e >> 6) * lds + (e & 63)];
+  }
+  if (j != i) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      const int64_t gc = col0 + (e & 31);
+      pf.x[u] = gc < ncols ? Ut[(int64_t)(j * NB + (e >> 5)) * ldu + gc] : 0.0;
     }
-    for (int j = 0; j < i; ++j) {
-      __syncthreads();
-      load_tile(Lt, Lb + (int64_t)i * NB * Bp + (int64_t)j * NB, Bp);
-      for (int e = tid; e < NB * TW; e += 256) {
-        const int rr = e / TW, cc = e % TW;
-        const int64_t c = col0 + cc;
-        X[rr][cc] = c < ncols ? Ut[(int64_t)(j * NB + rr) * ldu + c] : 0.0;
+  } else {
+    // X_i in the MFMA accumulator layout of this lane
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rr + 4 * v + (lane >> 4), c = 16 * n + (lane & 15);
+        const int64_t gc = col0 + c;
+        pf.x[4 * n + v] = gc < ncols ? Ut[(int64_t)(i * NB + r) * ldu + gc] : 0.0;
       }
-      __syncthreads();
-      for (int q = 0; q < NB; ++q) {
-        const double l = Lt[r][q];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] -= l * X[q][cq + v];
-      }
+  }
+}
+
+template <bool TRANS>
+__device__ inline void trsm_next(int i, int j, int nblk, int* ni, int* nj) {
+  if (!TRANS) {
+    *ni = i;
+    *nj = j + 1;
+    if (*nj > i) {
+      *ni = i + 1;
+      *nj = 0;
     }
-    __syncthreads();
-    load_tile(Lt, Linv + (int64_t)i * NB * NB, NB);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) X[r][cq + v] = acc[v];
-    __syncthreads();
-    double out[4] = {0, 0, 0, 0};
-    for (int q = 0; q <= r; ++q) {
-      const double l = Lt[r][q];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) out[v] += l * X[q][cq + v];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t c = col0 + cq + v;
-      if (c < ncols) Ut[(int64_t)(i * NB + r) * ldu + c] = out[v];
+  } else {
+    if (j > i) {
+      *ni = i;
+      *nj = j - 1;
+    } else {
+      *ni = i - 1;
+      *nj = nblk - 1;
     }
   }
 }
 
-// w[n] += sum_b V^T[b, n] t[b], t = V^T[:, N].
-__global__ void __launch_bounds__(256) k_upd_w(double* __restrict__ w,
-                                               const double* __restrict__ Ut, int64_t ldu,
-                                               int64_t N, int32_t Bc,
-                                               const int32_t* __restrict__ status) {
+template <bool TRANS>
+__global__ void __launch_bounds__(256) k_trsm_blocks(double* __restrict__ Ut, int64_t ldu,
+                                                     int64_t ncols, int32_t nblk,
+                                                     const double* __restrict__ Lb, int64_t ldl,
+                                                     const double* __restrict__ Linv,
+                                                     const int32_t* __restrict__ status) {
+  if (failed(status)) return;
+  __shared__ double Lt[NB][LDT];
+  __shared__ double X[NB][LDX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t col0 = (int64_t)blockIdx.x * TW;
+  const int rr = 16 * wave;
+  TrsmPre pf;
+  int i = TRANS ? nblk - 1 : 0, j = i;  // current pair
+  trsm_fetch<TRANS>(pf, i, j, Ut, ldu, ncols, col0, Lb, ldl, Linv);
+  v4d acc[2] = {(v4d){0.0, 0.0, 0.0, 0.0}, (v4d){0.0, 0.0, 0.0, 0.0}};
+  while (i >= 0 && i < nblk) {
+    const bool diag = (j == i);
+    __syncthreads();  // previous pair done with LDS (and its X_i stores)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u;
+      Lt[e >> 6][e & 63] = pf.l[u];
+    }
+    if (!diag) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u;
+        X[e >> 5][e & 31] = pf.x[u];
+      }
+    } else {
+      // R_i = X_i - sum_j (off-diagonal block) X_j, in the accumulator layout
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          X[rr + 4 * v + (lane >> 4)][16 * n + (lane & 15)] = pf.x[4 * n + v] - acc[n][v];
+    }
+    __syncthreads();
+    // Next pair. Its X_j blocks were finished by earlier diagonal steps,
+    // except right after the first diagonal step, whose successor needs the
+    // block just solved: that fetch waits for the stores below.
+    int ni, nj;
+    trsm_next<TRANS>(i, j, nblk, &ni, &nj);
+    const bool nvalid = ni >= 0 && ni < nblk;
+    const bool late = diag && nj == i;
+    if (nvalid && !late) trsm_fetch<TRANS>(pf, ni, nj, Ut, ldu, ncols, col0, Lb, ldl, Linv);
+    v4d out[2] = {(v4d){0.0, 0.0, 0.0, 0.0}, (v4d){0.0, 0.0, 0.0, 0.0}};
+#pragma unroll 4
+    for (int k = 0; k < NB; k += 4) {
+      const int kk = k + (lane >> 4);
+      const double a = TRANS ? Lt[kk][rr + (lane & 15)] : Lt[rr + (lane & 15)][kk];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const double b = X[kk][16 * n + (lane & 15)];
+        if (diag)
+          out[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, out[n], 0, 0, 0);
+        else
+          acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
+      }
+    }
+    if (diag) {
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rr + 4 * v + (lane >> 4), c = 16 * n + (lane & 15);
+          const int64_t gc = col0 + c;
+          if (gc < ncols) Ut[(int64_t)(i * NB + r) * ldu + gc] = out[n][v];
+        }
+      acc[0] = (v4d){0.0, 0.0, 0.0, 0.0};
+      acc[1] = (v4d){0.0, 0.0, 0.0, 0.0};
+      if (late && nvalid) {
+        __syncthreads();  // X_i stored by all waves before it is read back
+        trsm_fetch<TRANS>(pf, ni, nj, Ut, ldu, ncols, col0, Lb, ldl, Linv);
+      }
+    }
+    i = ni;
+    j = nj;
+  }
+}
+
+// w[n] += sum_b V^T[b, n] t[b], t = V^T[:, N]; stage 1 sums groups of 64
+// rows into part[g][n], stage 2 adds the groups in order (deterministic).
+__global__ void __launch_bounds__(256) k_upd_w_part(const double* __restrict__ Ut, int64_t ldu,
+                                                    int64_t N, int32_t Bc,
+                                                    double* __restrict__ part,
+                                                    const int32_t* __restrict__ status) {
+  if (failed(status)) return;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int b0 = blockIdx.y * 64;
+  const int b1 = b0 + 64 < Bc ? b0 + 64 : Bc;
+  double s0 = 0.0, s1 = 0.0;
+  int b = b0;
+  for (; b + 1 < b1; b += 2) {
+    s0 += Ut[(int64_t)b * ldu + n] * Ut[(int64_t)b * ldu + N];
+    s1 += Ut[(int64_t)(b + 1) * ldu + n] * Ut[(int64_t)(b + 1) * ldu + N];
+  }
+  if (b < b1) s0 += Ut[(int64_t)b * ldu + n] * Ut[(int64_t)b * ldu + N];
+  part[(int64_t)blockIdx.y * N + n] = s0 + s1;
+}
+
+__global__ void __launch_bounds__(256) k_upd_w_sum(double* __restrict__ w,
+                                                   const double* __restrict__ part, int64_t N,
+                                                   int32_t ngroups,
+                                                   const int32_t* __restrict__ status) {
   if (failed(status)) return;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   double s = 0.0;
-  for (int b = 0; b < Bc; ++b) s += Ut[(int64_t)b * ldu + n] * Ut[(int64_t)b * ldu + N];
+  for (int g = 0; g < ngroups; ++g) s += part[(int64_t)g * N + n];
   w[n] += s;
+}
+
+rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
+                        int64_t index) {
+  const int32_t nblk = n / NB;
+  k_chol_first<<<1, 256, 0, ctx->stream>>>(S, n, Lb, Linv, ctx->d_status, index);
+  RBF_LAUNCHED(ctx, "k_chol_first");
+  for (int32_t kb = 0; kb + 1 < nblk; ++kb) {
+    const int m = nblk - kb - 1;
+    k_chol_step<<<m + m * (m + 1) / 2, 256, 0, ctx->stream>>>(S, n, nblk, kb, Lb, Linv,
+                                                             ctx->d_status, index);
+    RBF_LAUNCHED(ctx, "k_chol_step");
+  }
+  return RBF_OK;
+}
+
+rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int32_t nblk,
+                       const double* Lb, int64_t ldl, const double* Linv, bool trans) {
+  if (ncols <= 0 || nblk <= 0) return RBF_OK;
+  const unsigned grid = (unsigned)ceil_div(ncols, TW);
+  if (trans)
+    k_trsm_blocks<true><<<grid, 256, 0, ctx->stream>>>(X, ldx, ncols, nblk, Lb, ldl, Linv,
+                                                       ctx->d_status);
+  else
+    k_trsm_blocks<false><<<grid, 256, 0, ctx->stream>>>(X, ldx, ncols, nblk, Lb, ldl, Linv,
+                                                        ctx->d_status);
+  RBF_LAUNCHED(ctx, "k_trsm_blocks");
+  return RBF_OK;
 }
 
 }  // namespace rbf
@@ -434,6 +672,8 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
   double* Linv = (double*)ws_get(ctx, WS_UPD_LINV, sizeof(double) * (size_t)nblk_max * NB * NB,
                                  &st);
   if (!Linv) return st;
+  double* wpart = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (size_t)nblk_max * N, &st);
+  if (!wpart) return st;
   const double st_ = std::sqrt(p->sigma * p->sigma + p->sigma_eps * p->sigma_eps);
   RegKU rk;
   rk.rc2 = (p->cutoff * st_) * (p->cutoff * st_);
@@ -449,27 +689,28 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
         xy + 2 * s0, z + s0, Bc, Bpc, g->d_cxy, g->d_idx, g->d_start, geom(g), rk, kmax, w,
         vals, cols, nnz, Ut, ldu, N, ctx->d_status, bi);
     RBF_LAUNCHED(ctx, "k_upd_rows");
+    prof_begin(ctx, RBF_PROF_GATHER);
     dim3 gg((unsigned)ceil_div(N, 1024), (unsigned)ceil_div(Bpc, 8));
-    k_upd_gather_u<<<gg, 256, 0, ctx->stream>>>(P, ldp, N, Bc, vals, cols, nnz, kmax, Ut, ldu,
+    k_upd_gather_u<<<gg, 256, 0, ctx->stream>>>(P, ldp, N, Bc, Bpc, vals, cols, nnz, Ut, ldu,
                                                  ctx->d_status);
     RBF_LAUNCHED(ctx, "k_upd_gather_u");
+    prof_end(ctx, RBF_PROF_GATHER);
     dim3 gs((unsigned)ceil_div(Bpc, 256), (unsigned)Bpc);
-    k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, kmax, Ut, ldu, Bc, Bpc, p->R, S,
+    k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,
                                          ctx->d_status);
     RBF_LAUNCHED(ctx, "k_upd_S");
-    k_chol_first<<<1, 256, 0, ctx->stream>>>(S, Bpc, Lb, Linv, ctx->d_status, bi);
-    RBF_LAUNCHED(ctx, "k_chol_first");
-    for (int32_t kb = 0; kb + 1 < nblk; ++kb) {
-      const int m = nblk - kb - 1;
-      k_chol_step<<<m + m * (m + 1) / 2, 256, 0, ctx->stream>>>(S, Bpc, nblk, kb, Lb, Linv,
-                                                               ctx->d_status, bi);
-      RBF_LAUNCHED(ctx, "k_chol_step");
-    }
-    k_upd_trsm<<<ceil_div(N + 1, TW), 256, 0, ctx->stream>>>(Ut, ldu, N + 1, nblk, Lb, Bpc,
-                                                             Linv, ctx->d_status);
-    RBF_LAUNCHED(ctx, "k_upd_trsm");
-    k_upd_w<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(w, Ut, ldu, N, Bc, ctx->d_status);
-    RBF_LAUNCHED(ctx, "k_upd_w");
+    prof_begin(ctx, RBF_PROF_CHOL);
+    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, bi));
+    prof_end(ctx, RBF_PROF_CHOL);
+    prof_begin(ctx, RBF_PROF_TRSM);
+    RBF_TRY(trsm_blocks(ctx, Ut, ldu, N + 1, nblk, Lb, Bpc, Linv, false));
+    prof_end(ctx, RBF_PROF_TRSM);
+    dim3 gw((unsigned)ceil_div(N, 256), (unsigned)ceil_div(Bc, 64));
+    k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Ut, ldu, N, Bc, wpart, ctx->d_status);
+    RBF_LAUNCHED(ctx, "k_upd_w_part");
+    k_upd_w_sum<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(w, wpart, N, (int32_t)gw.y,
+                                                           ctx->d_status);
+    RBF_LAUNCHED(ctx, "k_upd_w_sum");
     RBF_TRY(syrk_update(ctx, P, ldp, N, Ut, ldu, Bc, gemm_prec));
   }
   if (n_done) {

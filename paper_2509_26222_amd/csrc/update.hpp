@@ -15,4 +15,19 @@ constexpr int64_t UPDATE_DEFAULT_BATCH = 1024;
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
                        int64_t ldu, int32_t Bc, rbf_prec prec);
 
+// FP64 blocked Cholesky of the n x n (n a multiple of 64, row-major,
+// leading dimension n) symmetric matrix S, lower triangle used. S is
+// overwritten with intermediate trailing blocks; the factor is returned as
+// its off-diagonal 64x64 blocks in Lb (n x n, leading dimension n) and the
+// inverses of its diagonal blocks in Linv ((n/64) x 64 x 64). A breakdown
+// records RBF_E_NOT_SPD with `index` in the status word.
+rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
+                        int64_t index);
+
+// X := L^{-1} X (trans = false) or X := L^{-T} X (trans = true) in place for
+// X with nblk*64 rows, ncols columns and leading dimension ldx, with L given
+// as by chol_blocked (Lb with leading dimension ldl, Linv).
+rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int32_t nblk,
+                       const double* Lb, int64_t ldl, const double* Linv, bool trans);
+
 }  // namespace rbf
