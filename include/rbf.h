@@ -259,6 +259,56 @@ rbf_status rbf_eval_adjoint(rbf_ctx* ctx, const rbf_params* params,
                             const void* gbar_f, const void* gbar_r,
                             void* d_pts, double* d_w, double* d_pose);
 
+/* -------------------------------------------------------- many patches */
+
+/* One independent terrain patch for the batched form: its own centers
+ * (grid), weights and covariance, a scan of update points and a set of
+ * evaluation points. All pointers are device pointers except `pose`
+ * (host values, R row-major then t, read when the plan is built). */
+typedef struct {
+  const rbf_grid* grid;
+  double* w;            /* N_p, in/out                                    */
+  double* P;            /* N_p x ldp, in/out, symmetric                   */
+  int64_t ldp;
+  const double* xy;     /* M x 2 update points                            */
+  const double* z;      /* M heights                                      */
+  int64_t M;
+  const void* pts;      /* Q x dim evaluation points (plan's precision)   */
+  int64_t Q;
+  double pose[12];      /* dim == 3 only                                  */
+  void* f;              /* Q, required                                    */
+  void* grad;           /* Q x 2 or NULL                                  */
+  void* resid;          /* Q or NULL (dim == 3)                           */
+  void* jac;            /* Q x 6 or NULL (dim == 3)                       */
+  int64_t batch;        /* Kalman batch of this patch, 0 = plan default   */
+} rbf_patch;
+
+typedef struct rbf_batched rbf_batched;
+
+/* Plan the recursive update (as rbf_update) followed by the evaluation (as
+ * rbf_eval) of n independent patches, to be run as ONE hipGraph launch on
+ * the context's stream. The patches are spread over `streams` (1..16)
+ * concurrent branches of the graph by longest-processing-time assignment on
+ * the cost N_p^2 M_p; each branch has its own workspace, reserved here, so
+ * a run allocates nothing. The patch table is copied; the buffers it points
+ * to must stay valid while the plan lives. Calls on `ctx` must not run
+ * concurrently with the plan's runs. */
+rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params,
+                            const rbf_patch* patches, int32_t n, int32_t dim,
+                            rbf_prec eval_prec, rbf_prec gemm_prec,
+                            int32_t streams, int64_t default_batch,
+                            double z_off, rbf_batched** out);
+/* Enqueue one run of the plan: the first call captures the graph, later
+ * calls relaunch it. Asynchronous. */
+rbf_status rbf_batched_run(rbf_batched* b);
+/* Synchronise; return the device error of the last run (RBF_OK if none)
+ * and, in *failed_patch (host, may be NULL), the lowest index of a patch
+ * whose update failed (-1 if none). A failed patch keeps the state of its
+ * last committed batch; the later patches of its branch were skipped and
+ * keep their previous state. */
+rbf_status rbf_batched_sync(rbf_batched* b, int32_t* failed_patch);
+rbf_status rbf_batched_destroy(rbf_batched* b);
+
 /* ----------------------------------------------------------- diagnostics */
 
 /* Kernel timing with HIP events recorded on the context stream around each

@@ -262,6 +262,16 @@ def skew(v):
     return np.array([[0.0, -v[2], v[1]], [v[2], 0.0, -v[0]], [-v[1], v[0], 0.0]])
 
 
+def skew_rows(p):
+    """[p_i]x for every row of p (Q x 3 x 3)."""
+    p = np.asarray(p, np.float64)
+    K = np.zeros((p.shape[0], 3, 3))
+    K[:, 0, 1], K[:, 0, 2] = -p[:, 2], p[:, 1]
+    K[:, 1, 0], K[:, 1, 2] = p[:, 2], -p[:, 0]
+    K[:, 2, 0], K[:, 2, 1] = -p[:, 1], p[:, 0]
+    return K
+
+
 def to_world(p, Rs, t):
     """xi = R_s p + t for body-frame points p (Q x 3)."""
     return np.asarray(p, np.float64) @ np.asarray(Rs, np.float64).T + t
@@ -278,9 +288,9 @@ def eval_pose(p, Rs, t, z_off, c, w, sigma, cutoff):
     r = xi[:, 2] - z_off - f
     g = np.stack([-grad[:, 0], -grad[:, 1], np.ones_like(f)], axis=1)
     J = np.empty((p.shape[0], 6))
-    for i in range(p.shape[0]):
-        J[i, :3] = g[i] @ (-Rs @ skew(p[i]))
-        J[i, 3:] = g[i]
+    # row i: g_i^T (-R_s [p_i]x), then g_i^T
+    J[:, :3] = np.einsum("qa,ab,qbc->qc", g, -Rs, skew_rows(p))
+    J[:, 3:] = g
     return f, grad, r, J
 
 
@@ -312,9 +322,9 @@ def eval_adjoint_pose(p, Rs, t, z_off, c, w, sigma, cutoff, gbar_f, gbar_r):
     Phi = phi_dense(xi[:, :2], c, sigma, cutoff)
     d_w = Phi.T @ a
     d_pose = np.zeros(6)
-    for i in range(p.shape[0]):
-        d_pose[:3] += d_xi[i] @ (-Rs @ skew(p[i]))
-        d_pose[3:] += d_xi[i]
+    # sum_i dL/dxi_i^T (-R_s [p_i]x) and sum_i dL/dxi_i
+    d_pose[:3] = np.einsum("qa,ab,qbc->c", d_xi, -Rs, skew_rows(p))
+    d_pose[3:] = d_xi.sum(axis=0)
     return d_p, d_w, d_pose
 
 

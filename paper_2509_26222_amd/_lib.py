@@ -32,6 +32,13 @@ i32 = C.c_int32
 dbl = C.c_double
 pp = C.POINTER(Params)
 
+
+class Patch(C.Structure):
+    """rbf_patch (include/rbf.h)."""
+    _fields_ = [("grid", vp), ("w", vp), ("P", vp), ("ldp", i64), ("xy", vp), ("z", vp),
+                ("M", i64), ("pts", vp), ("Q", i64), ("pose", dbl * 12), ("f", vp),
+                ("grad", vp), ("resid", vp), ("jac", vp), ("batch", i64)]
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "rbf_ctx_create": (C.c_int, [C.POINTER(vp), C.c_int, vp]),
@@ -59,6 +66,11 @@ SIGNATURES = {
                            C.c_int, vp, vp, vp, vp]),
     "rbf_eval_adjoint": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl),
                                    C.c_int, vp, vp, vp, vp, vp]),
+    "rbf_batched_plan": (C.c_int, [vp, pp, vp, i32, i32, C.c_int, C.c_int, i32, i64,
+                                   dbl, C.POINTER(vp)]),
+    "rbf_batched_run": (C.c_int, [vp]),
+    "rbf_batched_sync": (C.c_int, [vp, C.POINTER(i32)]),
+    "rbf_batched_destroy": (C.c_int, [vp]),
     "rbf_profile_enable": (C.c_int, [vp, i32]),
     "rbf_profile_read": (C.c_int, [vp, i32, C.POINTER(dbl), C.POINTER(i64)]),
 }

@@ -271,6 +271,74 @@ class Context:
         return dp, d_w, d_pose
 
 
+class Batched:
+    """rbf_batched: update + evaluation of many patches as one graph launch.
+
+    Each patch is a dict with keys grid (Grid), w, P, xy, z, pts and, for
+    dim 3, pose=(R, t); outputs f (required), grad, resid, jac; optional
+    batch. The tensors are kept alive by this object."""
+
+    def __init__(self, ctx: Context, params: Params, patches: list, dim: int = 3,
+                 eval_prec="f32", gemm_prec="f64", streams: int = 4,
+                 default_batch: int = 0, z_off: float = 0.0):
+        self.ctx = ctx
+        self._keep = patches
+        arr = (L.Patch * len(patches))()
+        for i, p in enumerate(patches):
+            c = arr[i]
+            c.grid = p["grid"].h
+            c.w = _ptr(p["w"], torch.float64, "w", ctx.device)
+            P = p["P"]
+            if P.dtype != torch.float64 or P.stride(1) != 1:
+                raise ValueError("P must be row-major float64")
+            c.P = P.data_ptr()
+            c.ldp = P.stride(0)
+            c.xy = _ptr(p["xy"], torch.float64, "xy")
+            c.z = _ptr(p["z"], torch.float64, "z")
+            c.M = p["xy"].shape[0]
+            c.pts = _ptr(p["pts"], None, "pts")
+            c.Q = p["pts"].shape[0]
+            if dim == 3:
+                pc = _pose(p["pose"])
+                for k in range(12):
+                    c.pose[k] = pc[k]
+            c.f = _ptr(p["f"], p["pts"].dtype, "f")
+            c.grad = _ptr(p.get("grad"), p["pts"].dtype, "grad")
+            c.resid = _ptr(p.get("resid"), p["pts"].dtype, "resid")
+            c.jac = _ptr(p.get("jac"), p["pts"].dtype, "jac")
+            c.batch = int(p.get("batch", 0))
+        self._arr = arr
+        h = C.c_void_p()
+        pc = params.c()
+        ctx._check(ctx.lib.rbf_batched_plan(ctx.h, C.byref(pc), arr, len(patches), dim,
+                                            _prec(eval_prec), _prec(gemm_prec), streams,
+                                            default_batch, z_off, C.byref(h)),
+                   "rbf_batched_plan")
+        self.h = h
+
+    def run(self):
+        self.ctx._check(self.ctx.lib.rbf_batched_run(self.h), "rbf_batched_run")
+
+    def sync(self) -> int:
+        fp = C.c_int32()
+        st = self.ctx.lib.rbf_batched_sync(self.h, C.byref(fp))
+        if st != L.RBF_OK:
+            msg = self.ctx.lib.rbf_last_error(self.ctx.h).decode(errors="replace")
+            raise RbfError(st, msg, fp.value)
+        return fp.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rbf_batched_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _pose(pose):
     if pose is None:
         return None

@@ -276,6 +276,7 @@ rbf_status rbf_ctx_destroy(rbf_ctx* ctx) {
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
+  if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   for (int k = 0; k < RBF_PROF_KINDS; ++k) {
     if (!ctx->prof_ev[k]) continue;
     for (int e = 0; e < 2 * PROF_CAP; ++e) (void)hipEventDestroy(ctx->prof_ev[k][e]);

@@ -56,6 +56,8 @@ struct rbf_ctx {
   hipEvent_t* prof_ev[RBF_PROF_KINDS];
   int32_t prof_n[RBF_PROF_KINDS];
   int32_t prof_dropped[RBF_PROF_KINDS];
+  int32_t owns_stream;  // stream created by the library (batched branches)
+  int64_t index_base;   // added to the batch index rbf_update records
 };
 
 struct rbf_grid {

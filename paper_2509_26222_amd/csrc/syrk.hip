@@ -133,17 +133,258 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int
       }
 }
 
+// ------------------------------------------------ low-precision operands
+//
+// FP32: V^T is rounded to float (same k-major layout) and multiplied on
+// v_mfma_f32_16x16x4_f32. BF16: V = V_hi + V_lo with V_hi = bf16(V) and
+// V_lo = bf16(V - V_hi), stored i-major (N x Kp) so a lane reads its 8
+// consecutive k values with one 16-byte load, and V V^T is formed as
+// V_hi V_hi^T + V_hi V_lo^T + V_lo V_hi^T on v_mfma_f32_16x16x32_bf16. Both
+// accumulate in FP32 and subtract from the FP64 P with the same mirrored
+// write as the FP64 kernel.
+// Lane layout of both FP32-accumulating instructions (checked on gfx950):
+// D[i][j] in lane j + 16 (i / 4), item i % 4.
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__global__ void __launch_bounds__(256) k_cvt_f32(const double* __restrict__ Ut, int64_t ldu,
+                                                 int32_t K, int64_t N, float* __restrict__ Uf,
+                                                 const int32_t* __restrict__ status) {
+  if (*(volatile const int32_t*)status != 0) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)K * ldu) return;
+  const int64_t c = e % ldu;
+  Uf[e] = c < N ? (float)Ut[e] : 0.0f;
+}
+
+// Transposing split: Vhi[n][k], Vlo[n][k] (ld Kp) from U^T[k][n]; 64x64
+// tiles through LDS; k >= K and n >= N are zero.
+__global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ Ut, int64_t ldu,
+                                                    int32_t K, int64_t N, int32_t Kp,
+                                                    __bf16* __restrict__ Vhi,
+                                                    __bf16* __restrict__ Vlo,
+                                                    const int32_t* __restrict__ status) {
+  if (*(volatile const int32_t*)status != 0) return;
+  __shared__ double t[64][65];
+  const int64_t n0 = (int64_t)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int kk = e >> 6, nn = e & 63;
+    const int64_t gk = k0 + kk, gn = n0 + nn;
+    t[kk][nn] = (gk < K && gn < N) ? Ut[gk * ldu + gn] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int nn = e >> 6, kk = e & 63;
+    const int64_t gn = n0 + nn, gk = k0 + kk;
+    if (gn < N && gk < Kp) {
+      const double v = t[kk][nn];
+      const __bf16 hi = (__bf16)v;
+      const __bf16 lo = (__bf16)(v - (double)(float)hi);
+      Vhi[gn * Kp + gk] = hi;
+      Vlo[gn * Kp + gk] = lo;
+    }
+  }
+}
+
+__device__ inline void epilogue_f32acc(double* __restrict__ P, int64_t ldp, int64_t N,
+                                       int64_t I0, int64_t J0, bool diag, const v4f acc[4][4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = I0 + wm * 64 + mi * 16 + 4 * (lane >> 4) + v;
+        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+        if (gi < N && gj < N && (!diag || gi >= gj)) {
+          const double nv = P[gi * ldp + gj] - (double)acc[mi][ni][v];
+          P[gi * ldp + gj] = nv;
+          if (gi != gj) P[gj * ldp + gi] = nv;
+        }
+      }
+}
+
+constexpr int FKC = 32;  // rows of V^T per stage (FP32)
+constexpr int FLD = ST + 4;
+
+__global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
+                                                     int64_t N, const float* __restrict__ Uf,
+                                                     int64_t ldu, int32_t K, int64_t T,
+                                                     int64_t per_xcd,
+                                                     const int32_t* __restrict__ status) {
+  if (*(volatile const int32_t*)status != 0) return;
+  const int64_t t = xcd_tile(per_xcd);
+  if (t >= T) return;
+  int I, J;
+  tile_of(t, &I, &J);
+  const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
+  __shared__ float As[FKC][FLD];
+  __shared__ float Bs[FKC][FLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = tid >> 3, lc = (tid & 7) * 16;  // loader: 32 rows x 8 x 16 floats
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const int nch = (K + FKC - 1) / FKC;
+  float ra[16], rb[16];
+  auto load = [&](int ch) {
+    const int r = ch * FKC + lr;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t ca = I0 + lc + u, cb = J0 + lc + u;
+      ra[u] = (r < K && ca < N) ? Uf[(int64_t)r * ldu + ca] : 0.f;
+      rb[u] = (r < K && cb < N) ? Uf[(int64_t)r * ldu + cb] : 0.f;
+    }
+  };
+  load(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      As[lr][lc + u] = ra[u];
+      Bs[lr][lc + u] = rb[u];
+    }
+    __syncthreads();
+    if (ch + 1 < nch) load(ch + 1);
+#pragma unroll
+    for (int kk = 0; kk < FKC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      float a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kr][wm * 64 + q * 16 + (lane & 15)];
+        b[q] = Bs[kr][wn * 64 + q * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+  }
+  epilogue_f32acc(P, ldp, N, I0, J0, I == J, acc);
+}
+
+constexpr int BKC = 32;      // k per stage (one 16x16x32 MFMA)
+constexpr int BLD = BKC + 8; // LDS pitch in bf16 (80 bytes)
+
+__global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, int64_t ldp,
+                                                        int64_t N, const __bf16* __restrict__ Vhi,
+                                                        const __bf16* __restrict__ Vlo,
+                                                        int32_t Kp, int64_t T, int64_t per_xcd,
+                                                        const int32_t* __restrict__ status) {
+  if (*(volatile const int32_t*)status != 0) return;
+  const int64_t t = xcd_tile(per_xcd);
+  if (t >= T) return;
+  int I, J;
+  tile_of(t, &I, &J);
+  const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[ST][BLD];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[ST][BLD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[ST][BLD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[ST][BLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // loader: 128 rows x 32 k = 4 x 16 bytes per row; thread -> (row, quarter)
+  const int lrow = tid >> 1, lq = (tid & 1) * 16;  // 2 threads per row, 16 bf16 each
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const int nch = Kp / BKC;
+  uint4 rah[2], ral[2], rbh[2], rbl[2];
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  auto load = [&](int ch) {
+    const int64_t k0 = (int64_t)ch * BKC + lq;
+    const int64_t ga = I0 + lrow, gb = J0 + lrow;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      rah[u] = ga < N ? *reinterpret_cast<const uint4*>(Vhi + ga * Kp + k0 + 8 * u) : z4;
+      ral[u] = ga < N ? *reinterpret_cast<const uint4*>(Vlo + ga * Kp + k0 + 8 * u) : z4;
+      rbh[u] = gb < N ? *reinterpret_cast<const uint4*>(Vhi + gb * Kp + k0 + 8 * u) : z4;
+      rbl[u] = gb < N ? *reinterpret_cast<const uint4*>(Vlo + gb * Kp + k0 + 8 * u) : z4;
+    }
+  };
+  load(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      *reinterpret_cast<uint4*>(&Ah[lrow][lq + 8 * u]) = rah[u];
+      *reinterpret_cast<uint4*>(&Al[lrow][lq + 8 * u]) = ral[u];
+      *reinterpret_cast<uint4*>(&Bh[lrow][lq + 8 * u]) = rbh[u];
+      *reinterpret_cast<uint4*>(&Bl[lrow][lq + 8 * u]) = rbl[u];
+    }
+    __syncthreads();
+    if (ch + 1 < nch) load(ch + 1);
+    const int kq = 8 * (lane >> 4);
+    v8bf ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ra_ = wm * 64 + q * 16 + (lane & 15), rb_ = wn * 64 + q * 16 + (lane & 15);
+      ah[q] = *reinterpret_cast<const v8bf*>(&Ah[ra_][kq]);
+      al[q] = *reinterpret_cast<const v8bf*>(&Al[ra_][kq]);
+      bh[q] = *reinterpret_cast<const v8bf*>(&Bh[rb_][kq]);
+      bl[q] = *reinterpret_cast<const v8bf*>(&Bl[rb_][kq]);
+    }
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+      }
+  }
+  epilogue_f32acc(P, ldp, N, I0, J0, I == J, acc);
+}
+
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
                        int64_t ldu, int32_t Bc, rbf_prec prec) {
-  if (prec != RBF_F64)
-    return fail(ctx, RBF_E_INVALID_ARG, "rbf_update: gemm_prec %d not available", (int)prec);
   const int64_t nt = ceil_div(N, ST);
   const int64_t T = nt * (nt + 1) / 2;
   const int64_t per_xcd = ceil_div(T, 8);
+  rbf_status st;
+  if (prec == RBF_F64) {
+    prof_begin(ctx, RBF_PROF_SYRK);
+    k_syrk_f64<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T,
+                                                                 per_xcd, ctx->d_status);
+    RBF_LAUNCHED(ctx, "k_syrk_f64");
+    prof_end(ctx, RBF_PROF_SYRK);
+    return RBF_OK;
+  }
+  if (prec == RBF_F32) {
+    float* Uf = (float*)ws_get(ctx, WS_UPD_VLO, sizeof(float) * (size_t)Bc * ldu, &st);
+    if (!Uf) return st;
+    k_cvt_f32<<<ceil_div((int64_t)Bc * ldu, 256), 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, Uf,
+                                                                         ctx->d_status);
+    RBF_LAUNCHED(ctx, "k_cvt_f32");
+    prof_begin(ctx, RBF_PROF_SYRK);
+    k_syrk_f32<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, Uf, ldu, Bc, T,
+                                                                 per_xcd, ctx->d_status);
+    RBF_LAUNCHED(ctx, "k_syrk_f32");
+    prof_end(ctx, RBF_PROF_SYRK);
+    return RBF_OK;
+  }
+  const int32_t Kp = (int32_t)ceil_div(Bc, BKC) * BKC;
+  __bf16* V = (__bf16*)ws_get(ctx, WS_UPD_VLO, sizeof(__bf16) * 2 * (size_t)N * Kp, &st);
+  if (!V) return st;
+  __bf16* Vlo = V + (size_t)N * Kp;
+  dim3 gc((unsigned)ceil_div(N, 64), (unsigned)ceil_div(Kp, 64));
+  k_cvt_bf16x2<<<gc, 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, Kp, V, Vlo, ctx->d_status);
+  RBF_LAUNCHED(ctx, "k_cvt_bf16x2");
   prof_begin(ctx, RBF_PROF_SYRK);
-  k_syrk_f64<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T,
-                                                               per_xcd, ctx->d_status);
-  RBF_LAUNCHED(ctx, "k_syrk_f64");
+  k_syrk_bf16x3<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, V, Vlo, Kp, T,
+                                                                  per_xcd, ctx->d_status);
+  RBF_LAUNCHED(ctx, "k_syrk_bf16x3");
   prof_end(ctx, RBF_PROF_SYRK);
   return RBF_OK;
 }

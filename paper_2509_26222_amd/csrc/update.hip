@@ -531,21 +531,27 @@ __global__ void __launch_bounds__(256) k_trsm_blocks(double* __restrict__ Ut, in
     const bool nvalid = ni >= 0 && ni < nblk;
     const bool late = diag && nj == i;
     if (nvalid && !late) trsm_fetch<TRANS>(pf, ni, nj, Ut, ldu, ncols, col0, Lb, ldl, Linv);
-    v4d out[2] = {(v4d){0.0, 0.0, 0.0, 0.0}, (v4d){0.0, 0.0, 0.0, 0.0}};
+    if (!diag) {
 #pragma unroll 4
-    for (int k = 0; k < NB; k += 4) {
-      const int kk = k + (lane >> 4);
-      const double a = TRANS ? Lt[kk][rr + (lane & 15)] : Lt[rr + (lane & 15)][kk];
+      for (int k = 0; k < NB; k += 4) {
+        const int kk = k + (lane >> 4);
+        const double a = TRANS ? Lt[kk][rr + (lane & 15)] : Lt[rr + (lane & 15)][kk];
 #pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const double b = X[kk][16 * n + (lane & 15)];
-        if (diag)
-          out[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, out[n], 0, 0, 0);
-        else
-          acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
+        for (int n = 0; n < 2; ++n)
+          acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, X[kk][16 * n + (lane & 15)], acc[n],
+                                                        0, 0, 0);
       }
-    }
-    if (diag) {
+    } else {
+      v4d out[2] = {(v4d){0.0, 0.0, 0.0, 0.0}, (v4d){0.0, 0.0, 0.0, 0.0}};
+#pragma unroll 4
+      for (int k = 0; k < NB; k += 4) {
+        const int kk = k + (lane >> 4);
+        const double a = TRANS ? Lt[kk][rr + (lane & 15)] : Lt[rr + (lane & 15)][kk];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          out[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, X[kk][16 * n + (lane & 15)], out[n],
+                                                        0, 0, 0);
+      }
 #pragma unroll
       for (int n = 0; n < 2; ++n)
 #pragma unroll
@@ -597,6 +603,34 @@ __global__ void __launch_bounds__(256) k_upd_w_sum(double* __restrict__ w,
   double s = 0.0;
   for (int g = 0; g < ngroups; ++g) s += part[(int64_t)g * N + n];
   w[n] += s;
+}
+
+rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
+                            rbf_prec gemm_prec, UpdWs* ws) {
+  const int32_t Bp = (int32_t)ceil_div(Bmax > 0 ? Bmax : 1, NB) * NB;
+  const int32_t nblk_max = Bp / NB;
+  const int64_t ldu = ceil_div(N + 1, 32) * 32;
+  rbf_status st;
+  char* ell = (char*)ws_get(ctx, WS_UPD_ELL, (size_t)Bp * kmax * 12 + (size_t)Bp * 4 + 256, &st);
+  if (!ell) return st;
+  ws->vals = (double*)ell;
+  ws->cols = (int32_t*)(ell + (size_t)Bp * kmax * 8);
+  ws->nnz = ws->cols + (size_t)Bp * kmax;
+  ws->Ut = (double*)ws_get(ctx, WS_UPD_UT, sizeof(double) * (size_t)Bp * ldu, &st);
+  if (!ws->Ut) return st;
+  ws->S = (double*)ws_get(ctx, WS_UPD_S, sizeof(double) * (size_t)Bp * Bp * 2, &st);
+  if (!ws->S) return st;
+  ws->Lb = ws->S + (size_t)Bp * Bp;
+  ws->Linv = (double*)ws_get(ctx, WS_UPD_LINV, sizeof(double) * (size_t)nblk_max * NB * NB, &st);
+  if (!ws->Linv) return st;
+  ws->wpart = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (size_t)nblk_max * N, &st);
+  if (!ws->wpart) return st;
+  if (gemm_prec == RBF_F32) {
+    if (!ws_get(ctx, WS_UPD_VLO, sizeof(float) * (size_t)Bp * ldu, &st)) return st;
+  } else if (gemm_prec == RBF_BF16) {
+    if (!ws_get(ctx, WS_UPD_VLO, 2 * 2 * (size_t)N * Bp, &st)) return st;
+  }
+  return RBF_OK;
 }
 
 rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
@@ -653,27 +687,18 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
   if (M == 0) return RBF_OK;
   RBF_TRY(set_device(ctx));
   const int64_t B = batch > 0 ? batch : UPDATE_DEFAULT_BATCH;
-  const int32_t Bmax = (int32_t)(B < M ? B : M);
-  const int32_t Bp = (int32_t)ceil_div(Bmax, NB) * NB;
-  const int32_t nblk_max = Bp / NB;
-  const int64_t ldu = ceil_div(N + 1, 32) * 32;
   const int32_t kmax = g->max_cand > 0 ? g->max_cand : 1;
-  rbf_status st;
-  char* ell = (char*)ws_get(ctx, WS_UPD_ELL, (size_t)Bp * kmax * 12 + (size_t)Bp * 4 + 256, &st);
-  if (!ell) return st;
-  double* vals = (double*)ell;
-  int32_t* cols = (int32_t*)(ell + (size_t)Bp * kmax * 8);
-  int32_t* nnz = cols + (size_t)Bp * kmax;
-  double* Ut = (double*)ws_get(ctx, WS_UPD_UT, sizeof(double) * (size_t)Bp * ldu, &st);
-  if (!Ut) return st;
-  double* S = (double*)ws_get(ctx, WS_UPD_S, sizeof(double) * (size_t)Bp * Bp * 2, &st);
-  if (!S) return st;
-  double* Lb = S + (size_t)Bp * Bp;
-  double* Linv = (double*)ws_get(ctx, WS_UPD_LINV, sizeof(double) * (size_t)nblk_max * NB * NB,
-                                 &st);
-  if (!Linv) return st;
-  double* wpart = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (size_t)nblk_max * N, &st);
-  if (!wpart) return st;
+  const int64_t ldu = ceil_div(N + 1, 32) * 32;
+  UpdWs ws;
+  RBF_TRY(update_workspace(ctx, N, kmax, B < M ? B : M, gemm_prec, &ws));
+  double* vals = ws.vals;
+  int32_t* cols = ws.cols;
+  int32_t* nnz = ws.nnz;
+  double* Ut = ws.Ut;
+  double* S = ws.S;
+  double* Lb = ws.Lb;
+  double* Linv = ws.Linv;
+  double* wpart = ws.wpart;
   const double st_ = std::sqrt(p->sigma * p->sigma + p->sigma_eps * p->sigma_eps);
   RegKU rk;
   rk.rc2 = (p->cutoff * st_) * (p->cutoff * st_);
@@ -687,7 +712,7 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
     const int32_t nblk = Bpc / NB;
     k_upd_rows<<<ceil_div(Bpc, 256), 256, 0, ctx->stream>>>(
         xy + 2 * s0, z + s0, Bc, Bpc, g->d_cxy, g->d_idx, g->d_start, geom(g), rk, kmax, w,
-        vals, cols, nnz, Ut, ldu, N, ctx->d_status, bi);
+        vals, cols, nnz, Ut, ldu, N, ctx->d_status, ctx->index_base + bi);
     RBF_LAUNCHED(ctx, "k_upd_rows");
     prof_begin(ctx, RBF_PROF_GATHER);
     dim3 gg((unsigned)ceil_div(N, 1024), (unsigned)ceil_div(Bpc, 8));
@@ -700,7 +725,7 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
                                          ctx->d_status);
     RBF_LAUNCHED(ctx, "k_upd_S");
     prof_begin(ctx, RBF_PROF_CHOL);
-    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, bi));
+    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi));
     prof_end(ctx, RBF_PROF_CHOL);
     prof_begin(ctx, RBF_PROF_TRSM);
     RBF_TRY(trsm_blocks(ctx, Ut, ldu, N + 1, nblk, Lb, Bpc, Linv, false));
@@ -721,7 +746,7 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
     if (h[0] != 0) {
       int64_t idx;
       memcpy(&idx, h + 2, sizeof(idx));
-      const int64_t done = idx * B;
+      const int64_t done = (idx - ctx->index_base) * B;
       *n_done = done < M ? done : M;
       return rbf_sync_status(ctx);
     }

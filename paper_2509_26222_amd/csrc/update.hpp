@@ -15,6 +15,22 @@ constexpr int64_t UPDATE_DEFAULT_BATCH = 1024;
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
                        int64_t ldu, int32_t Bc, rbf_prec prec);
 
+// Device workspace of rbf_update for N centers, kmax candidates per point
+// and batches of at most Bmax points (all slots grown up front, so later
+// calls with these sizes allocate nothing).
+struct UpdWs {
+  double* vals;
+  int32_t* cols;
+  int32_t* nnz;
+  double* Ut;
+  double* S;
+  double* Lb;
+  double* Linv;
+  double* wpart;
+};
+rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
+                            rbf_prec gemm_prec, UpdWs* ws);
+
 // FP64 blocked Cholesky of the n x n (n a multiple of 64, row-major,
 // leading dimension n) symmetric matrix S, lower triangle used. S is
 // overwritten with intermediate trailing blocks; the factor is returned as

@@ -1,0 +1,93 @@
+"""Batched form: many patches of uneven size updated and evaluated by one
+hipGraph launch. The kernels are deterministic (no atomics on this path), so
+the batched results must equal the sequential plain calls bit for bit; the
+plain calls are themselves parity-tested against the oracle, and two
+patches are also checked directly against the oracle here."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import dev, host
+from paper_2509_26222_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def make_patches(ctx, p, count, seed=4, n_range=(200, 1200), m_range=(1000, 5000),
+                 nan_patch=None):
+    _, raw = synth.patches_case(seed=seed, count=count, n_range=n_range, m_range=m_range)
+    out = []
+    for i, r in enumerate(raw):
+        grid = ctx.grid(p, dev(r.centers))
+        N = grid.N
+        z = r.z.copy()
+        if i == nan_patch:
+            z[len(z) // 2] = np.nan
+        pts = np.concatenate([r.xy, z[:, None]], 1)
+        Q = pts.shape[0]
+        out.append(dict(
+            grid=grid, raw=r,
+            w=torch.zeros(N, dtype=torch.float64, device="cuda"),
+            P=torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam),
+            xy=dev(r.xy), z=dev(z),
+            pts=dev(pts, torch.float32), pose=(np.eye(3), np.zeros(3)),
+            f=torch.empty(Q, dtype=torch.float32, device="cuda"),
+            grad=torch.empty((Q, 2), dtype=torch.float32, device="cuda"),
+            resid=torch.empty(Q, dtype=torch.float32, device="cuda"),
+            jac=torch.empty((Q, 6), dtype=torch.float32, device="cuda"),
+            batch=512 if i % 2 else 0))
+    return out
+
+
+def run_sequential(ctx, p, patches, gemm_prec="f64", default_batch=1024):
+    for q in patches:
+        ctx.update(p, q["grid"], q["w"], q["P"], q["xy"], q["z"],
+                   batch=q["batch"] or default_batch, gemm_prec=gemm_prec, sync=False)
+        o = ctx.eval(p, q["grid"], q["w"], q["pts"], pose=q["pose"])
+        for k in ("f", "grad", "resid", "jac"):
+            q[k].copy_(o[k])
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("streams", [1, 4])
+def test_batched_equals_sequential(ctx, streams):
+    p = api.Params()
+    A = make_patches(ctx, p, 12)
+    B = make_patches(ctx, p, 12)
+    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", streams=streams)
+    for rep in range(2):  # capture, then replay on the updated state
+        plan.run()
+        assert plan.sync() == -1
+        run_sequential(ctx, p, B)
+        for a, b in zip(A, B):
+            for k in ("w", "P", "f", "grad", "resid", "jac"):
+                assert torch.equal(a[k], b[k]), (rep, k)
+    plan.close()
+    # direct oracle check of two patches after the first run's state: redo one run
+    C = make_patches(ctx, p, 12)
+    plan = api.Batched(ctx, p, C, dim=3, eval_prec="f32", gemm_prec="f64", streams=streams)
+    plan.run()
+    plan.sync()
+    for q in (C[0], C[7]):
+        r = q["raw"]
+        wb, _ = O.ridge_batch(r.xy, r.z, r.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R,
+                              with_P=False)
+        assert np.linalg.norm(host(q["w"]) - wb) / np.linalg.norm(wb) <= 1e-9
+    plan.close()
+
+
+def test_batched_reports_failed_patch(ctx):
+    p = api.Params()
+    A = make_patches(ctx, p, 8, nan_patch=5)
+    plan = api.Batched(ctx, p, A, dim=3, streams=8)
+    plan.run()
+    with pytest.raises(api.RbfError) as e:
+        plan.sync()
+    assert e.value.status == 4 and e.value.index == 5
+    # patches on other branches completed
+    B = make_patches(ctx, p, 8, nan_patch=5)
+    run_sequential(ctx, p, [B[0]])
+    assert torch.equal(A[0]["w"], B[0]["w"])
+    plan.close()
+    ctx.sync_status()
