@@ -40,7 +40,75 @@ def parse():
     ap.add_argument("--frames", type=int, default=4, help="distinct frames generated")
     ap.add_argument("--eval-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--patches", type=int, default=32,
+                    help="patches in the batched-form leg (0 = skip; 256 = full workload)")
+    ap.add_argument("--tune", action="store_true", help="autotune the batched plan")
     return ap.parse_args()
+
+
+def batched_leg(ctx, api, synth, n_patches, tune):
+    """Many uneven patches: one hipGraph launch of the batched plan vs the
+    same update + evaluation calls issued one patch after another."""
+    import torch
+    from paper_2509_26222_amd import tune as T
+
+    p = api.Params()
+    _, raw = synth.patches_case(seed=4, count=n_patches)
+
+    def build():
+        out = []
+        for r in raw:
+            grid = ctx.grid(p, torch.from_numpy(r.centers).cuda())
+            N = grid.N
+            pts = torch.from_numpy(
+                __import__("numpy").concatenate([r.xy, r.z[:, None]], 1)).float().cuda()
+            Q = pts.shape[0]
+            out.append(dict(grid=grid,
+                            w=torch.zeros(N, dtype=torch.float64, device="cuda"),
+                            P=torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam),
+                            xy=torch.from_numpy(r.xy).cuda(), z=torch.from_numpy(r.z).cuda(),
+                            pts=pts, pose=(__import__("numpy").eye(3),
+                                           __import__("numpy").zeros(3)),
+                            f=torch.empty(Q, dtype=torch.float32, device="cuda"),
+                            grad=torch.empty((Q, 2), dtype=torch.float32, device="cuda"),
+                            resid=torch.empty(Q, dtype=torch.float32, device="cuda"),
+                            jac=torch.empty((Q, 6), dtype=torch.float32, device="cuda")))
+        return out
+
+    patches = build()
+    streams, batch = 4, 1024
+    table = None
+    if tune:
+        sample = patches[:: max(1, len(patches) // 16)]
+        (streams, batch), table = T.tune_batched(ctx, p, sample, streams=(1, 2, 4, 8),
+                                                 batches=(512, 1024, 2048), reps=1)
+    # sequential plain calls, one patch after another
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in patches:
+        ctx.update(p, q["grid"], q["w"], q["P"], q["xy"], q["z"], batch=batch, sync=False)
+        ctx.eval(p, q["grid"], q["w"], q["pts"], pose=q["pose"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    ctx.sync_status()
+    plan = api.Batched(ctx, p, patches, dim=3, eval_prec="f32", gemm_prec="f64",
+                       streams=streams, default_batch=batch)
+    plan.run()  # capture + first run
+    plan.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run()
+    plan.sync()
+    t_graph = time.perf_counter() - t0
+    plan.close()
+    out = {"patches": len(patches), "streams": streams, "batch": batch,
+           "sequential_s": t_seq, "graph_s": t_graph, "speedup": t_seq / t_graph,
+           "update_points": int(sum(q["xy"].shape[0] for q in patches))}
+    if table:
+        out["tuning"] = {f"{s}x{b}": round(v, 4) for (s, b), v in table.items()}
+    del patches
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(od, centers_np, p, batches=3, eval_pts=2000):
@@ -111,31 +179,52 @@ def main():
         frames.append((torch.from_numpy(xy).to(dev), torch.from_numpy(z).to(dev),
                        torch.from_numpy(pts).to(dev), (R, t)))
     w = torch.zeros(N, dtype=torch.float64, device=dev)
-    P = torch.eye(N, dtype=torch.float64, device=dev) * (p.R / p.lam)
+    P = torch.empty((N, N), dtype=torch.float64, device=dev)
 
-    def step(k):
-        xy, z, pts, pose = frames[k % nfr]
-        xs, zs, _ = ctx.sort_points(grid, xy, z)
-        ctx.update(p, grid, w, P, xs, zs, batch=args.batch, sync=False)
-        return ctx.eval(p, grid, w, pts, pose=pose)
+    def run_sequence(gemm_prec):
+        """Warmup + timed frames from the prior (w = 0, P = (R/lambda) I)."""
+        w.zero_()
+        P.zero_()
+        P.diagonal().fill_(p.R / p.lam)
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    ctx.sync_status()
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(args.warmup + k)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.sync_status()
-    dt = t1 - t0
-    prof = {name: ctx.profile_read(kind) for name, kind in
-            (("syrk", L.PROF_SYRK), ("trsm", L.PROF_TRSM), ("chol", L.PROF_CHOL),
-             ("gather", L.PROF_GATHER), ("eval", L.PROF_EVAL))}
-    ctx.profile(False)
+        def step(k):
+            xy, z, pts, pose = frames[k % nfr]
+            xs, zs, _ = ctx.sort_points(grid, xy, z)
+            ctx.update(p, grid, w, P, xs, zs, batch=args.batch, gemm_prec=gemm_prec,
+                       sync=False)
+            return ctx.eval(p, grid, w, pts, pose=pose)
+
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        ctx.sync_status()
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(args.warmup + k)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.sync_status()
+        prof = {name: ctx.profile_read(kind) for name, kind in
+                (("syrk", L.PROF_SYRK), ("trsm", L.PROF_TRSM), ("chol", L.PROF_CHOL),
+                 ("gather", L.PROF_GATHER), ("eval", L.PROF_EVAL))}
+        ctx.profile(False)
+        return t1 - t0, prof
+
+    # mixed-precision covariance products first, FP64 last (its w is kept)
+    mixed = {}
+    last = frames[(args.warmup + args.steps - 1) % nfr]
+    for mp in ("bf16", "f32"):
+        dtm, profm = run_sequence(mp)
+        fm = ctx.eval(p, grid, w, last[2], pose=last[3])["f"].clone()
+        mixed[mp] = {"value": args.steps / dtm, "ms_per_step": dtm / args.steps * 1e3,
+                     "syrk_ms_per_step": profm["syrk"][0] / args.steps, "_f": fm}
+    dt, prof = run_sequence("f64")
+    f64 = ctx.eval(p, grid, w, last[2], pose=last[3])["f"]
+    for mp in mixed:
+        mixed[mp]["max_height_dev_vs_f64_m"] = float((mixed[mp].pop("_f") - f64).abs().max())
+        mixed[mp]["speedup_vs_f64"] = mixed[mp]["value"] / (args.steps / dt)
     pts_per_frame = od.GROUND_PER_FRAME
     syrk_ms, syrk_n = prof["syrk"]
     # algorithmic work of P -= V V^T with symmetry: N(N+1)/2 entries, 2 flops
@@ -209,8 +298,13 @@ def main():
             "flops_per_launch": N * (N + 1) * args.batch,
         },
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "mixed_precision": mixed,
         "eval": ev,
     }
+    if args.patches > 0:
+        del P, frames
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(ctx, api, synth, args.patches, args.tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(od, centers.cpu().numpy(), p)
     print(json.dumps(out), flush=True)

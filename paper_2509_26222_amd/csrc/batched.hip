@@ -22,6 +22,8 @@
 
 struct rbf_batched {
   rbf_ctx* parent;
+  rbf_ctx* cap;  // owns the capture / launch stream (never the legacy null stream)
+  hipEvent_t ev_in, ev_out;
   rbf_params params;
   int32_t dim;
   rbf_prec eval_prec, gemm_prec;
@@ -46,14 +48,18 @@ static rbf_status batched_free(rbf_batched* b) {
   for (auto e : b->joins)
     if (e) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   for (auto k : b->kids)
     if (k) rbf_ctx_destroy(k);
+  if (b->cap) rbf_ctx_destroy(b->cap);
   delete b;
   return RBF_OK;
 }
 
+// Everything below is enqueued on the plan's own stream (captured).
 static rbf_status enqueue_all(rbf_batched* b) {
-  rbf_ctx* ctx = b->parent;
+  rbf_ctx* ctx = b->cap;
   for (auto k : b->kids) RBF_TRY(fill_zero(ctx, k->d_status, 4 * sizeof(int32_t)));
   RBF_HIP(ctx, hipEventRecord(b->fork, ctx->stream));
   for (size_t q = 0; q < b->kids.size(); ++q) {
@@ -132,7 +138,20 @@ rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params, const rbf_pa
   }
   for (int32_t q = 0; q < K; ++q) std::sort(b->assign[q].begin(), b->assign[q].end());
   rbf_status st = RBF_OK;
-  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) st = RBF_E_HIP;
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+    st = RBF_E_HIP;
+  if (st == RBF_OK) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      st = RBF_E_HIP;
+    } else if ((st = rbf_ctx_create(&b->cap, ctx->device, s)) != RBF_OK) {
+      (void)hipStreamDestroy(s);
+    } else {
+      b->cap->owns_stream = 1;
+    }
+  }
   for (int32_t q = 0; q < K && st == RBF_OK; ++q) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
@@ -177,15 +196,16 @@ rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params, const rbf_pa
 rbf_status rbf_batched_run(rbf_batched* b) {
   if (!b) return RBF_E_INVALID_ARG;
   rbf_ctx* ctx = b->parent;
+  rbf_ctx* cap = b->cap;
   RBF_TRY(set_device(ctx));
   if (!b->captured) {
-    RBF_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    RBF_HIP(ctx, hipStreamBeginCapture(cap->stream, hipStreamCaptureModeThreadLocal));
     rbf_status st = enqueue_all(b);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    hipError_t e = hipStreamEndCapture(cap->stream, &g);
     if (st != RBF_OK) {
       if (g) (void)hipGraphDestroy(g);
-      return st;
+      return fail(ctx, st, "rbf_batched_run: %s", cap->err);
     }
     if (e != hipSuccess)
       return fail(ctx, RBF_E_HIP, "rbf_batched_run: capture failed: %s", hipGetErrorString(e));
@@ -193,7 +213,12 @@ rbf_status rbf_batched_run(rbf_batched* b) {
     RBF_HIP(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->captured = true;
   }
-  RBF_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
+  // ordered after earlier work on the caller's stream, and before later work
+  RBF_HIP(ctx, hipEventRecord(b->ev_in, ctx->stream));
+  RBF_HIP(ctx, hipStreamWaitEvent(cap->stream, b->ev_in, 0));
+  RBF_HIP(ctx, hipGraphLaunch(b->exec, cap->stream));
+  RBF_HIP(ctx, hipEventRecord(b->ev_out, cap->stream));
+  RBF_HIP(ctx, hipStreamWaitEvent(ctx->stream, b->ev_out, 0));
   return RBF_OK;
 }
 
@@ -202,6 +227,7 @@ rbf_status rbf_batched_sync(rbf_batched* b, int32_t* failed_patch) {
   if (failed_patch) *failed_patch = -1;
   rbf_ctx* ctx = b->parent;
   RBF_TRY(set_device(ctx));
+  if (b->cap) RBF_HIP(ctx, hipStreamSynchronize(b->cap->stream));
   RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   rbf_status first = RBF_OK;
   int32_t worst = -1;
@@ -230,6 +256,7 @@ rbf_status rbf_batched_sync(rbf_batched* b, int32_t* failed_patch) {
 rbf_status rbf_batched_destroy(rbf_batched* b) {
   if (!b) return RBF_E_INVALID_ARG;
   (void)hipSetDevice(b->parent->device);
+  if (b->cap) (void)hipStreamSynchronize(b->cap->stream);
   (void)hipStreamSynchronize(b->parent->stream);
   return batched_free(b);
 }

@@ -7,11 +7,12 @@
 // J = [(p x R^T g)^T, g^T], g = (-f_x, -f_y, 1) (eqs. manifold_derivative,
 // manifold_grad_2, right perturbation, body-frame point).
 //
-// One lane per point. A point's candidates are the centers of its 3x3 bin
-// neighbourhood, read as three contiguous runs of a packed, bin-sorted
-// table (x, y, w) that stays resident in L2. Each lane accumulates its own
-// sums in registers, so no cross-lane reduction is needed and the output is
-// written once, coalesced.
+// A point's candidates are the centers of its 3x3 bin neighbourhood, read as
+// three contiguous runs of a packed, bin-sorted table (x, y, w) that stays
+// resident in L2. The forward kernel gives each point four lanes that take
+// every fourth candidate and combine their partial sums with lane shuffles
+// (four times the waves to hide the table's load latency, a quarter of the
+// loop); the adjoint keeps one lane per point.
 #include <cmath>
 
 #include "internal.hpp"
@@ -58,11 +59,14 @@ __global__ void __launch_bounds__(256) k_pack_centers(const T* __restrict__ cxy,
 }
 
 // Accumulate f, sum w phi dx, sum w phi dy over the 3x3 neighbourhood of
-// (x, y). Returns false if no bin is in range.
+// (x, y), taking every LPP-th candidate starting at `part` (the lanes of one
+// point split the candidates; their sums are combined by the caller).
+constexpr int LPP = 4;  // lanes per point
+
 template <typename T>
 __device__ inline void accumulate(T x, T y, const typename Vec4<T>::type* __restrict__ tab,
                                   const int32_t* __restrict__ start, const GridGeom& g,
-                                  const EvalK<T>& k, T& f, T& sx, T& sy) {
+                                  const EvalK<T>& k, int part, T& f, T& sx, T& sy) {
   f = sx = sy = (T)0;
   int bx0, bx1, by0, by1;
   if (!bin_range((double)x, g.x0, g.inv_h, g.nbx, &bx0, &bx1)) return;
@@ -70,7 +74,7 @@ __device__ inline void accumulate(T x, T y, const typename Vec4<T>::type* __rest
   for (int by = by0; by <= by1; ++by) {
     const int row = by * g.nbx;
     const int s0 = start[row + bx0], s1 = start[row + bx1 + 1];
-    for (int s = s0; s < s1; ++s) {
+    for (int s = s0 + part; s < s1; s += LPP) {
       const typename Vec4<T>::type c = tab[s];
       const T dx = x - c.x, dy = y - c.y;
       const T d2 = dx * dx + dy * dy;
@@ -91,8 +95,11 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
                                               EvalK<T> k, T* __restrict__ f_out,
                                               T* __restrict__ grad_out, T* __restrict__ r_out,
                                               T* __restrict__ jac_out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= Q) return;
+  // LPP lanes per point: they share the point, split its candidates and
+  // combine the partial sums with lane shuffles
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPP;
+  const int part = threadIdx.x % LPP;
+  if (i >= Q) return;  // the LPP lanes of a point exit together
   T x, y, zw, px = 0, py = 0, pz = 0;
   if (POSE) {
     px = pts[3 * i];
@@ -107,16 +114,23 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
     zw = 0;
   }
   T f, sx, sy;
-  accumulate<T>(x, y, tab, start, g, k, f, sx, sy);
+  accumulate<T>(x, y, tab, start, g, k, part, f, sx, sy);
+#pragma unroll
+  for (int m = 1; m < LPP; m <<= 1) {
+    f += __shfl_xor(f, m, 64);
+    sx += __shfl_xor(sx, m, 64);
+    sy += __shfl_xor(sy, m, 64);
+  }
   const T fx = -sx * k.inv_s2, fy = -sy * k.inv_s2;
-  f_out[i] = f;
-  if (grad_out) {
+  // the lanes of a point share the stores
+  if (part == 0) f_out[i] = f;
+  if (grad_out && part == 1) {
     grad_out[2 * i] = fx;
     grad_out[2 * i + 1] = fy;
   }
   if (POSE) {
-    if (r_out) r_out[i] = zw - k.z_off - f;
-    if (jac_out) {
+    if (r_out && part == 2) r_out[i] = zw - k.z_off - f;
+    if (jac_out && part == 3) {
       // g = (-fx, -fy, 1); q = R^T g; J_rot = p x q
       const T g0 = -fx, g1 = -fy, g2 = (T)1;
       const T q0 = k.R[0] * g0 + k.R[3] * g1 + k.R[6] * g2;
@@ -280,7 +294,7 @@ static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, c
   typename Vec4<T>::type* tab;
   RBF_TRY(pack<T>(ctx, g, w, &tab));
   EvalK<T> k = make_consts<T>(p, pose, z_off);
-  const int64_t blocks = ceil_div(Q, 256);
+  const int64_t blocks = ceil_div(Q * LPP, 256);
   prof_begin(ctx, RBF_PROF_EVAL);
   if (dim == 3)
     k_eval<T, true><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->d_start, geom(g),

@@ -211,100 +211,9 @@ __device__ inline void acc_to_lds(const Acc64& A, double (*T)[LDT]) {
       for (int v = 0; v < 4; ++v) T[acc_row(mi, v)][acc_col(ni)] = A.c[mi][ni][v];
 }
 
-// In-place Cholesky of the lower triangle of T (64x64) and Tinv = L^{-1}.
-// Lane group g = tid / 4 (four lanes, part p = tid % 4) owns row g of L and
-// column g of L^{-1}, the entries with index = p mod 4 held in registers
-// (a[k] = L[g][4k+p], x[k] = Linv[4k+p][g]). Step j (fully unrolled):
-//   groups g >  j: L[g][j] = (A[g][j] - sum_{q<j} L[g][q] L[j][q]) / L[j][j]
-//                  (left-looking; row j is read from LDS), and group j+1
-//                  takes its pivot from its running remainder
-//                  r_g = A[g][g] - sum_q L[g][q]^2;
-//   groups c <= j: Linv[j][c] = (delta_jc - sum_{c<=q<j} L[j][q] Linv[q][c])
-//                  / L[j][j].
-// Partial sums of the four lanes meet through two lane shuffles; one
-// barrier per step. A non-positive or non-finite pivot records
-// RBF_E_NOT_SPD with `index` (the factor then continues with pivot 1).
-__device__ __noinline__ void chol64(double (*T)[LDT], double (*Tinv)[LDT], int32_t* status,
-                                    int64_t index) {
-  const int tid = threadIdx.x;
-  const int g = tid >> 2, p = tid & 3;
-  __shared__ int bad;
-  // v: row g of A / L while j < g, then (once row g is in LDS) column g of
-  // the inverse
-  double v[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = T[g][4 * k + p];
-  double r = T[g][g];
-  __syncthreads();
-  if (tid == 0) bad = 0;
-  if (g == 0) {
-    const bool ok = r > 0.0 && isfinite(r);
-    const double d = ok ? sqrt(r) : 1.0;
-    if (p == 0) {
-      if (!ok) bad = 1;
-      T[0][0] = d;
-    }
-  }
-  __syncthreads();
-#pragma clang loop unroll(full)
-  for (int j = 0; j < NB; ++j) {
-    const double ljj = T[j][j];
-    if (g > j) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int k = 0; 4 * k < j; ++k) {
-        const int q = 4 * k + p;
-        const double t = (q < j) ? v[k] * T[j][q] : 0.0;
-        if (k & 1) s1 += t; else s0 += t;
-      }
-      double sd = s0 + s1;
-      sd += __shfl_xor(sd, 1, 64);
-      sd += __shfl_xor(sd, 2, 64);
-      const double agj = __shfl(v[j >> 2], (tid & ~3) | (j & 3), 64);
-      const double l = (agj - sd) / ljj;
-      if (p == (j & 3)) {
-        v[j >> 2] = l;
-        T[g][j] = l;
-      }
-      r -= l * l;
-      if (g == j + 1) {
-        const bool ok = r > 0.0 && isfinite(r);
-        const double d = ok ? sqrt(r) : 1.0;
-        if (p == ((j + 1) & 3)) {
-          if (!ok) bad = 1;
-          T[g][g] = d;
-        }
-      }
-    } else {
-      if (g == j) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = 0.0;
-      }
-      // column c = g <= j of the inverse, row j
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int k = 0; 4 * k < j; ++k) {
-        const int q = 4 * k + p;
-        const double t = (q < j && q >= g) ? T[j][q] * v[k] : 0.0;
-        if (k & 1) s1 += t; else s0 += t;
-      }
-      double sd = s0 + s1;
-      sd += __shfl_xor(sd, 1, 64);
-      sd += __shfl_xor(sd, 2, 64);
-      const double xv = ((g == j ? 1.0 : 0.0) - sd) / ljj;
-      if (p == (j & 3)) v[j >> 2] = xv;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int q = 4 * k + p;
-    Tinv[q][g] = (q >= g) ? v[k] : 0.0;
-    if (q > g) T[g][q] = 0.0;
-  }
-  __syncthreads();
-  if (tid == 0 && bad) set_status(status, RBF_E_NOT_SPD, index);
-}
+// In-place Cholesky of the lower triangle of T (64x64) and Tinv = L^{-1}:
+// chol64() in chol64.hpp.
+#include "chol64.hpp"
 
 // Factor diagonal block 0.
 __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S, int32_t Bp,
