@@ -43,7 +43,30 @@ def parse():
     ap.add_argument("--patches", type=int, default=32,
                     help="patches in the batched-form leg (0 = skip; 256 = full workload)")
     ap.add_argument("--tune", action="store_true", help="autotune the batched plan")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32/BF16 covariance-product legs")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 launches), the "
+                         "reference for scaling HBM byte counters, and exit")
     return ap.parse_args()
+
+
+def log(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def copy_calibrate(mib):
+    """A plain copy of known size: each launch reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n * 4, "copy_bytes_written_per_launch": n * 4,
+                      "launches": 5}), flush=True)
 
 
 def batched_leg(ctx, api, synth, n_patches, tune):
@@ -153,6 +176,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
                                    "sharding of the path is a design note, not built"}))
         sys.exit(2)
+    if args.copy_calibrate:
+        copy_calibrate(args.copy_calibrate)
+        return
     import numpy as np
     import torch
 
@@ -180,18 +206,37 @@ def main():
                        torch.from_numpy(pts).to(dev), (R, t)))
     w = torch.zeros(N, dtype=torch.float64, device=dev)
     P = torch.empty((N, N), dtype=torch.float64, device=dev)
+    log(f"setup done: {N} centers, {nfr} frames")
+
+    # information form (center-pair pattern) for the refinement of the
+    # mixed-precision legs; depends only on the centers
+    rowptr, colidx = ctx.gram_pattern(p, grid)
+    hvals = torch.zeros(colidx.shape[0], dtype=torch.float64, device=dev)
+    hb = torch.zeros(N, dtype=torch.float64, device=dev)
+    refine_log = {}
 
     def run_sequence(gemm_prec):
-        """Warmup + timed frames from the prior (w = 0, P = (R/lambda) I)."""
+        """Warmup + timed frames from the prior (w = 0, P = (R/lambda) I).
+        Low-precision covariance products are followed by the FP64
+        refinement of w against the accumulated information form."""
         w.zero_()
         P.zero_()
         P.diagonal().fill_(p.R / p.lam)
+        hvals.zero_()
+        hb.zero_()
+        sweeps = []
 
         def step(k):
             xy, z, pts, pose = frames[k % nfr]
             xs, zs, _ = ctx.sort_points(grid, xy, z)
             ctx.update(p, grid, w, P, xs, zs, batch=args.batch, gemm_prec=gemm_prec,
                        sync=False)
+            if gemm_prec != "f64":
+                ctx.assemble_gram(p, grid, xs, zs, rowptr, colidx, hvals, hb,
+                                  add_lambda=(k == 0))
+                rel, it, _ = ctx.refine(p, rowptr, colidx, hvals, hb, P, w, rtol=1e-10,
+                                        max_iter=30)
+                sweeps.append(it)
             return ctx.eval(p, grid, w, pts, pose=pose)
 
         for k in range(args.warmup):
@@ -210,17 +255,21 @@ def main():
                 (("syrk", L.PROF_SYRK), ("trsm", L.PROF_TRSM), ("chol", L.PROF_CHOL),
                  ("gather", L.PROF_GATHER), ("eval", L.PROF_EVAL))}
         ctx.profile(False)
+        refine_log[gemm_prec] = sweeps
         return t1 - t0, prof
 
     # mixed-precision covariance products first, FP64 last (its w is kept)
     mixed = {}
     last = frames[(args.warmup + args.steps - 1) % nfr]
-    for mp in ("bf16", "f32"):
+    for mp in (() if args.no_mixed else ("bf16", "f32")):
         dtm, profm = run_sequence(mp)
+        log(f"{mp} covariance-product leg: {dtm / args.steps * 1e3:.1f} ms/step")
         fm = ctx.eval(p, grid, w, last[2], pose=last[3])["f"].clone()
         mixed[mp] = {"value": args.steps / dtm, "ms_per_step": dtm / args.steps * 1e3,
-                     "syrk_ms_per_step": profm["syrk"][0] / args.steps, "_f": fm}
+                     "syrk_ms_per_step": profm["syrk"][0] / args.steps,
+                     "refine_sweeps_per_step": refine_log[mp][args.warmup:], "_f": fm}
     dt, prof = run_sequence("f64")
+    log(f"f64 leg: {dt / args.steps * 1e3:.1f} ms/step")
     f64 = ctx.eval(p, grid, w, last[2], pose=last[3])["f"]
     for mp in mixed:
         mixed[mp]["max_height_dev_vs_f64_m"] = float((mixed[mp].pop("_f") - f64).abs().max())
@@ -301,11 +350,13 @@ def main():
         "mixed_precision": mixed,
         "eval": ev,
     }
+    log("eval leg done")
     if args.patches > 0:
         del P, frames
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(ctx, api, synth, args.patches, args.tune)
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(od, centers.cpu().numpy(), p)
     print(json.dumps(out), flush=True)
 

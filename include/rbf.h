@@ -219,6 +219,28 @@ rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
                      int64_t nrhs, double rtol, int32_t max_iter,
                      rbf_prec inner, double* relres, int32_t* iters);
 
+/* FP64 iterative refinement of the weights of the recursive update against
+ * the information form of the ridge estimator (subsection "The RBF Weight
+ * Estimate by Ridge Regression", eqs. RBF_estimator, H_update and
+ * H_inverse_update: after any sequence of batches the recursion's weights
+ * equal calH^{-1} b, calH = lambda I + sum m m^T, b = sum m z, and its
+ * covariance is P = R calH^{-1}). With the recursion's P (from covariance
+ * products of any precision) as the preconditioner, each sweep does
+ *   r = b - calH w   (CSR, FP64),   w += P r / R   (dense FP64, N^2 reads)
+ * until ||r||_2 <= rtol ||b||_2 or max_iter sweeps (0 = only report).
+ * rowptr (N+1 int64), colidx (int32), vals (f64): calH in CSR with both
+ * triangles and lambda on the diagonal, as rbf_gram_pattern +
+ * rbf_assemble_gram (add_lambda once) build it over all absorbed points;
+ * b: N f64; P: N x N f64, leading dimension ldp >= N, symmetric; w: N f64,
+ * refined in place. relres (host, may be NULL) receives the final
+ * ||r|| / ||b||, iters (host, may be NULL) the sweeps done; the call
+ * synchronises. Returns RBF_E_NO_CONVERGE (w holds the last sweep) if rtol
+ * was not met: the preconditioner is too far from R calH^{-1}. */
+rbf_status rbf_refine(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
+                      const int32_t* colidx, const double* vals, const double* b,
+                      const double* P, int64_t ldp, double R, double* w, double rtol,
+                      int32_t max_iter, double* relres, int32_t* iters);
+
 /* ------------------------------------------------------------ evaluation */
 
 /* Evaluate the terrain model at Q points.

@@ -62,6 +62,8 @@ SIGNATURES = {
                              C.POINTER(i64)]),
     "rbf_solve": (C.c_int, [vp, i64, vp, vp, vp, vp, i64, vp, i64, i64, dbl, i32,
                             C.c_int, C.POINTER(dbl), C.POINTER(i32)]),
+    "rbf_refine": (C.c_int, [vp, i64, vp, vp, vp, vp, vp, i64, dbl, vp, dbl, i32,
+                             C.POINTER(dbl), C.POINTER(i32)]),
     "rbf_eval": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl), dbl,
                            C.c_int, vp, vp, vp, vp]),
     "rbf_eval_adjoint": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl),

@@ -217,7 +217,7 @@ class Context:
         return nd.value if sync else None
 
     def solve(self, rowptr, colidx, vals, B: torch.Tensor, rtol: float = 1e-10,
-              max_iter: int = 50, inner="f32", X: torch.Tensor | None = None):
+              max_iter: int = 50, inner="f64", X: torch.Tensor | None = None):
         N = rowptr.shape[0] - 1
         Bm = B if B.dim() == 2 else B.view(-1, 1)
         nrhs = Bm.shape[1]
@@ -235,6 +235,25 @@ class Context:
             self._check(st, "rbf_solve")
         out = X if B.dim() == 2 else X.view(-1)
         return out, relres, it.value, st
+
+    def refine(self, params: Params, rowptr, colidx, vals, b, P: torch.Tensor,
+               w: torch.Tensor, rtol: float = 1e-12, max_iter: int = 20, check=True):
+        """FP64 refinement of w against calH = (rowptr, colidx, vals), b with
+        the recursion's P as preconditioner. Returns (relres, sweeps, status);
+        raises unless check is False."""
+        N = rowptr.shape[0] - 1
+        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] != N or P.shape[1] != N:
+            raise ValueError("P must be an N x N row-major tensor")
+        rel = C.c_double()
+        it = C.c_int32()
+        st = self.lib.rbf_refine(
+            self.h, N, _ptr(rowptr, torch.int64, "rowptr", self.device),
+            _ptr(colidx, torch.int32, "colidx"), _ptr(vals, torch.float64, "vals"),
+            _ptr(b, torch.float64, "b"), _ptr(P, torch.float64, "P"), P.stride(0),
+            params.R, _ptr(w, torch.float64, "w"), rtol, max_iter, C.byref(rel), C.byref(it))
+        if check:
+            self._check(st, "rbf_refine")
+        return rel.value, it.value, st
 
     def eval(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
              pose=None, z_off: float = 0.0, grad=True, resid=True, jac=True):

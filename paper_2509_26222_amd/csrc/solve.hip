@@ -221,9 +221,80 @@ static rbf_status col_norms(rbf_ctx* ctx, const double* A, int64_t lda, int64_t 
   return RBF_OK;
 }
 
+// w_i += (1/R) sum_j P_ij r_j: one wave per row of P (coalesced row reads,
+// four loads in flight per lane), fixed-order shuffle reduction.
+__global__ void __launch_bounds__(256) k_refine_symv(const double* __restrict__ P, int64_t ldp,
+                                                     int64_t N, const double* __restrict__ r,
+                                                     double inv_R, double* __restrict__ w) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const double* __restrict__ row = P + i * ldp;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t j = lane;
+  for (; j + 192 < N; j += 256) {
+    s0 += row[j] * r[j];
+    s1 += row[j + 64] * r[j + 64];
+    s2 += row[j + 128] * r[j + 128];
+    s3 += row[j + 192] * r[j + 192];
+  }
+  for (; j < N; j += 64) s0 += row[j] * r[j];
+  double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) w[i] += s * inv_R;
+}
+
 }  // namespace rbf
 
 using namespace rbf;
+
+extern "C" rbf_status rbf_refine(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
+                                 const int32_t* colidx, const double* vals, const double* b,
+                                 const double* P, int64_t ldp, double R, double* w, double rtol,
+                                 int32_t max_iter, double* relres, int32_t* iters) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  if (iters) *iters = 0;
+  if (relres) *relres = NAN;
+  if (N <= 0 || !rowptr || !colidx || !vals || !b || !P || !w || ldp < N || !(R > 0) ||
+      !(rtol > 0) || max_iter < 0)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_refine: bad arguments");
+  RBF_TRY(set_device(ctx));
+  RBF_TRY(rbf_sync_status(ctx));
+  rbf_status st;
+  double* r = (double*)ws_get(ctx, WS_SOLVE5, sizeof(double) * N, &st);
+  if (!r) return st;
+  const int32_t ngroups = (int32_t)ceil_div(N, NRG);
+  double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (ngroups + 1), &st);
+  if (!part) return st;
+  double* dnorm = (double*)ws_get(ctx, WS_TMP2, sizeof(double), &st);
+  if (!dnorm) return st;
+  std::vector<double> bn, rn;
+  RBF_TRY(col_norms(ctx, b, 1, N, 1, part, dnorm, bn));
+  auto residual = [&](double* rel) -> rbf_status {
+    k_residual<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, b, 1, w, 1,
+                                                         1, r);
+    RBF_LAUNCHED(ctx, "k_residual");
+    RBF_TRY(col_norms(ctx, r, 1, N, 1, part, dnorm, rn));
+    *rel = bn[0] > 0 ? rn[0] / bn[0] : rn[0];
+    return RBF_OK;
+  };
+  double rel = 0.0;
+  RBF_TRY(residual(&rel));
+  int32_t it = 0;
+  while (!(rel <= rtol) && it < max_iter && std::isfinite(rel)) {
+    k_refine_symv<<<ceil_div(N, 4), 256, 0, ctx->stream>>>(P, ldp, N, r, 1.0 / R, w);
+    RBF_LAUNCHED(ctx, "k_refine_symv");
+    ++it;
+    RBF_TRY(residual(&rel));
+  }
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  if (!(rel <= rtol))
+    return fail(ctx, RBF_E_NO_CONVERGE, "rbf_refine: relres %g above %g after %d sweeps", rel,
+                rtol, it);
+  return RBF_OK;
+}
 
 extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
                                 const int32_t* colidx, const double* vals, const double* B,

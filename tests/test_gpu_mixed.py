@@ -1,9 +1,13 @@
-"""Mixed-precision covariance product (FP32 / split-BF16 operands, FP32
-accumulation into the FP64 P) against the FP64 oracle.
+"""Mixed-precision form of the recursive update: covariance product V V^T in
+FP32 or split-BF16 operands with FP32 accumulation into the FP64 P, then
+FP64 refinement of w (rbf_refine) against the information form assembled by
+rbf_assemble_gram, with that P as preconditioner.
 
-Bound (stated target of the mixed path): heights of the fitted terrain within
-1e-4 m of the FP64 oracle's at the queries, and the weights error is
-reported. P stays exactly symmetric and S stays positive definite."""
+Bounds (stated targets of the mixed path): heights within 1e-4 m and height
+gradients within 1e-3 (relative to the largest gradient) of the FP64
+oracle's at the queries. The error of the low-precision recursion before
+refinement, of w and of P are printed for the record. P stays exactly
+symmetric."""
 import numpy as np
 import pytest
 import torch
@@ -13,6 +17,21 @@ from helpers import dev, host
 from paper_2509_26222_amd import api, synth
 
 pytestmark = pytest.mark.gpu
+
+
+def _errors(q, centers, w, wb, p):
+    f_gpu, g_gpu = O.eval_height_grad(q, centers, w, p.sigma, p.cutoff)
+    f_ref, g_ref = O.eval_height_grad(q, centers, wb, p.sigma, p.cutoff)
+    ef = np.abs(f_gpu - f_ref).max()
+    eg = np.linalg.norm(g_gpu - g_ref, axis=1).max() / np.linalg.norm(g_ref, axis=1).max()
+    ew = np.linalg.norm(w - wb) / np.linalg.norm(wb)
+    return ef, eg, ew
+
+
+def _refine(ctx, p, grid, xy, z, w, P):
+    rowptr, colidx = ctx.gram_pattern(p, grid)
+    vals, b = ctx.assemble_gram(p, grid, xy, z, rowptr, colidx)
+    return ctx.refine(p, rowptr, colidx, vals, b, P, w, rtol=1e-12, max_iter=30)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
@@ -25,15 +44,17 @@ def test_mixed_update_heights(ctx, prec, batch):
     w = torch.zeros(N, dtype=torch.float64, device="cuda")
     P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
     ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=batch, gemm_prec=prec)
-    wb, Pb = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R)
-    f_gpu, _ = O.eval_height_grad(s.queries, s.centers, host(w), p.sigma, p.cutoff)
-    f_ref, _ = O.eval_height_grad(s.queries, s.centers, wb, p.sigma, p.cutoff)
-    ew = np.linalg.norm(host(w) - wb) / np.linalg.norm(wb)
-    ef = np.abs(f_gpu - f_ref).max()
-    eP = np.abs(host(P) - Pb).max() / np.abs(Pb).max()
-    print(f"{prec} batch {batch}: w rel {ew:.2e}, max |df| {ef:.2e} m, P rel {eP:.2e}")
-    assert ef <= 1e-4
     assert torch.equal(P, P.T)
+    wb, Pb = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R)
+    eP = np.abs(host(P) - Pb).max() / np.abs(Pb).max()
+    ef0, eg0, ew0 = _errors(s.queries, s.centers, host(w), wb, p)
+    rel, sweeps, _ = _refine(ctx, p, grid, dev(s.xy), dev(s.z), w, P)
+    ef, eg, ew = _errors(s.queries, s.centers, host(w), wb, p)
+    print(f"{prec} batch {batch}: P rel {eP:.2e}; recursion only: max|df| {ef0:.2e} m, "
+          f"grad rel {eg0:.2e}, w rel {ew0:.2e}; refined ({sweeps} sweeps, relres "
+          f"{rel:.1e}): max|df| {ef:.2e} m, grad rel {eg:.2e}, w rel {ew:.2e}")
+    assert ef <= 1e-4
+    assert eg <= 1e-3
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
@@ -55,9 +76,37 @@ def test_mixed_update_odometry_frame(ctx, prec):
     H, b = O.gram(xy, z, centers, p.sigma, p.cutoff, 0.0, p.lam, sparse=True)
     wb = O.spd_solve(H, b)
     q = np.random.default_rng(0).uniform(0, 50, size=(5000, 2))
-    f_gpu, _ = O.eval_height_grad(q, centers, host(w), p.sigma, p.cutoff)
-    f_ref, _ = O.eval_height_grad(q, centers, wb, p.sigma, p.cutoff)
-    ef = np.abs(f_gpu - f_ref).max()
-    print(f"{prec} odometry 2 frames: w rel "
-          f"{np.linalg.norm(host(w) - wb) / np.linalg.norm(wb):.2e}, max |df| {ef:.2e} m")
+    ef0, eg0, ew0 = _errors(q, centers, host(w), wb, p)
+    rel, sweeps, _ = _refine(ctx, p, grid, dev(xy), dev(z), w, P)
+    ef, eg, ew = _errors(q, centers, host(w), wb, p)
+    print(f"{prec} odometry 2 frames: recursion only: max|df| {ef0:.2e} m, grad rel "
+          f"{eg0:.2e}, w rel {ew0:.2e}; refined ({sweeps} sweeps, relres {rel:.1e}): "
+          f"max|df| {ef:.2e} m, grad rel {eg:.2e}, w rel {ew:.2e}")
     assert ef <= 1e-4
+    assert eg <= 1e-3
+
+
+def test_refine_reports_and_rejects(ctx):
+    s = synth.small_case(0)
+    p = api.Params()
+    grid = ctx.grid(p, dev(s.centers))
+    N = grid.N
+    w = torch.zeros(N, dtype=torch.float64, device="cuda")
+    P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
+    ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=256, gemm_prec="f64")
+    rowptr, colidx = ctx.gram_pattern(p, grid)
+    vals, b = ctx.assemble_gram(p, grid, dev(s.xy), dev(s.z), rowptr, colidx)
+    # the FP64 recursion already solves the information form
+    rel, sweeps, st = ctx.refine(p, rowptr, colidx, vals, b, P, w, rtol=1e-9, max_iter=0)
+    assert st == 0 and sweeps == 0 and rel <= 1e-9
+    # from w = 0 with max_iter = 0: reported, not converged, w untouched
+    w0 = torch.zeros_like(w)
+    rel, sweeps, st = ctx.refine(p, rowptr, colidx, vals, b, P, w0, rtol=1e-9, max_iter=0,
+                                 check=False)
+    assert st == 5 and sweeps == 0 and abs(rel - 1.0) < 1e-12
+    assert int(torch.count_nonzero(w0)) == 0
+    # a preconditioner of the right scale from the FP64 recursion converges fast
+    rel, sweeps, st = ctx.refine(p, rowptr, colidx, vals, b, P, w0, rtol=1e-10, max_iter=5)
+    assert st == 0 and 1 <= sweeps <= 3
+    with pytest.raises(api.RbfError):
+        ctx.refine(p, rowptr, colidx, vals, b, P, w, rtol=0.0)
