@@ -29,6 +29,11 @@ METRIC = ("rbf_eval Mpts/s + scan updates/s (10k centers) at stated err; "
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes of one k_syrk_f64 launch (all lower tiles) at N = 10,000, batch 1024,
+# from rocprofv3 FETCH_SIZE (x2.0, the copy-kernel calibration) + WRITE_SIZE (x1.0);
+# summary in profiles/k_syrk_f64_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid
+# only for that kernel version and shape (None otherwise).
+SYRK_F64_TRAFFIC = {(10000, 1024): 3.1872e9 + 0.8047e9}
 
 
 def parse():
@@ -38,11 +43,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--frames", type=int, default=4, help="distinct frames generated")
-    ap.add_argument("--eval-reps", type=int, default=200)
+    ap.add_argument("--eval-reps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--patches", type=int, default=32,
                     help="patches in the batched-form leg (0 = skip; 256 = full workload)")
     ap.add_argument("--tune", action="store_true", help="autotune the batched plan")
+    ap.add_argument("--streams", type=int, default=1, choices=(1, 2),
+                    help="schedule of the update (2: next batch's chain overlaps the "
+                         "covariance product on a second stream)")
+    ap.add_argument("--no-other-schedule", action="store_true",
+                    help="skip the FP64 leg with the other update schedule")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32/BF16 covariance-product legs")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -215,10 +225,11 @@ def main():
     hb = torch.zeros(N, dtype=torch.float64, device=dev)
     refine_log = {}
 
-    def run_sequence(gemm_prec):
+    def run_sequence(gemm_prec, streams=args.streams):
         """Warmup + timed frames from the prior (w = 0, P = (R/lambda) I).
         Low-precision covariance products are followed by the FP64
         refinement of w against the accumulated information form."""
+        ctx.set_update_streams(streams)
         w.zero_()
         P.zero_()
         P.diagonal().fill_(p.R / p.lam)
@@ -268,8 +279,17 @@ def main():
         mixed[mp] = {"value": args.steps / dtm, "ms_per_step": dtm / args.steps * 1e3,
                      "syrk_ms_per_step": profm["syrk"][0] / args.steps,
                      "refine_sweeps_per_step": refine_log[mp][args.warmup:], "_f": fm}
+    other = 3 - args.streams
+    other_schedule = None
+    if not args.no_other_schedule:
+        dt_o, prof_o = run_sequence("f64", streams=other)
+        log(f"f64 leg, {other} stream(s): {dt_o / args.steps * 1e3:.1f} ms/step")
+        other_schedule = {"update_streams": other, "value": args.steps / dt_o,
+                          "ms_per_step": dt_o / args.steps * 1e3,
+                          "kernel_ms_per_step": {k: v[0] / args.steps
+                                                 for k, v in prof_o.items()}}
     dt, prof = run_sequence("f64")
-    log(f"f64 leg: {dt / args.steps * 1e3:.1f} ms/step")
+    log(f"f64 leg, {args.streams} stream(s): {dt / args.steps * 1e3:.1f} ms/step")
     f64 = ctx.eval(p, grid, w, last[2], pose=last[3])["f"]
     for mp in mixed:
         mixed[mp]["max_height_dev_vs_f64_m"] = float((mixed[mp].pop("_f") - f64).abs().max())
@@ -281,7 +301,7 @@ def main():
     syrk_flops = N * (N + 1) * pts_per_frame * args.steps
     syrk_tfs = syrk_flops / (syrk_ms * 1e-3) / 1e12 if syrk_ms > 0 else 0.0
 
-    # ---- rbf_eval throughput at >= 1e7 points per timed region
+    # ---- rbf_eval throughput: 500 launches of 200k points (1e8) per timed region
     ev = {}
     xy0, z0, pts0, pose0 = frames[0]
     for name, dt_ in (("f64", torch.float64), ("f32", torch.float32)):
@@ -341,12 +361,18 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": syrk_tfs / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": (SYRK_F64_TRAFFIC.get((N, args.batch)) if args.streams == 1 else None),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE)",
             "launches": syrk_n,
             "avg_launch_ms": syrk_ms / max(syrk_n, 1),
-            "flops_per_launch": N * (N + 1) * args.batch,
+            "flops_per_launch": syrk_flops / max(syrk_n, 1),
+            "launches_note": ("each batch's product is two launches (tiles in the next "
+                              "batch's touched row blocks first, then the rest); "
+                              "achieved = all SYRK flops / all SYRK launch time"),
         },
+        "update_streams": args.streams,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "other_schedule": other_schedule,
         "mixed_precision": mixed,
         "eval": ev,
     }

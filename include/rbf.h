@@ -86,6 +86,14 @@ rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream);
 rbf_status rbf_ctx_destroy(rbf_ctx* ctx);
 /* Re-bind the context to another stream of the same device. */
 rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream);
+/* Schedule of rbf_update on this context: streams = 1 (the default) runs
+ * everything on the context's stream; streams = 2 runs each batch's
+ * covariance product on the context's stream while the next batch's
+ * regressor rows, gather, Cholesky and triangular solve run on a second
+ * stream of the library's. Results are bitwise the same. (On one MI355X
+ * the two streams contend for CUs and the two-stream schedule measured
+ * slower.) Under stream capture rbf_update always uses one stream. */
+rbf_status rbf_ctx_set_update_streams(rbf_ctx* ctx, int32_t streams);
 /* Synchronise the stream, return the first device-side error recorded
  * since the last call (RBF_OK if none) and clear it. */
 rbf_status rbf_sync_status(rbf_ctx* ctx);
@@ -224,18 +232,21 @@ rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
  * Estimate by Ridge Regression", eqs. RBF_estimator, H_update and
  * H_inverse_update: after any sequence of batches the recursion's weights
  * equal calH^{-1} b, calH = lambda I + sum m m^T, b = sum m z, and its
- * covariance is P = R calH^{-1}). With the recursion's P (from covariance
- * products of any precision) as the preconditioner, each sweep does
- *   r = b - calH w   (CSR, FP64),   w += P r / R   (dense FP64, N^2 reads)
- * until ||r||_2 <= rtol ||b||_2 or max_iter sweeps (0 = only report).
- * rowptr (N+1 int64), colidx (int32), vals (f64): calH in CSR with both
- * triangles and lambda on the diagonal, as rbf_gram_pattern +
- * rbf_assemble_gram (add_lambda once) build it over all absorbed points;
- * b: N f64; P: N x N f64, leading dimension ldp >= N, symmetric; w: N f64,
- * refined in place. relres (host, may be NULL) receives the final
- * ||r|| / ||b||, iters (host, may be NULL) the sweeps done; the call
- * synchronises. Returns RBF_E_NO_CONVERGE (w holds the last sweep) if rtol
- * was not met: the preconditioner is too far from R calH^{-1}. */
+ * covariance is P = R calH^{-1}). Conjugate gradients (Hestenes-Stiefel) on
+ * calH w = b from the given w, preconditioned by the recursion's P / R
+ * (from covariance products of any precision): per iteration one FP64 CSR
+ * product with calH, one FP64 pass over P and three dot products; the
+ * residual r = b - calH w is recomputed from w before the result is
+ * accepted. Stops when ||r||_2 <= rtol ||b||_2 or after max_iter iterations
+ * (0 = only report). rowptr (N+1 int64), colidx (int32), vals (f64): calH
+ * in CSR with both triangles and lambda on the diagonal, as
+ * rbf_gram_pattern + rbf_assemble_gram (add_lambda once) build it over all
+ * absorbed points; b: N f64; P: N x N f64, leading dimension ldp >= N,
+ * symmetric positive definite; w: N f64, refined in place. relres (host,
+ * may be NULL) receives the final ||r|| / ||b||, iters (host, may be NULL)
+ * the iterations done; the call synchronises. Returns RBF_E_NO_CONVERGE (w
+ * holds the last iterate) if rtol was not met, also when P / R or calH
+ * showed a non-positive curvature. */
 rbf_status rbf_refine(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
                       const int32_t* colidx, const double* vals, const double* b,
                       const double* P, int64_t ldp, double R, double* w, double rtol,

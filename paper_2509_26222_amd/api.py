@@ -236,6 +236,12 @@ class Context:
         out = X if B.dim() == 2 else X.view(-1)
         return out, relres, it.value, st
 
+    def set_update_streams(self, streams: int):
+        """Schedule of update(): 1 (default) uses one stream, 2 overlaps the
+        next batch's chain with the covariance product on a second stream."""
+        self._check(self.lib.rbf_ctx_set_update_streams(self.h, streams),
+                    "rbf_ctx_set_update_streams")
+
     def refine(self, params: Params, rowptr, colidx, vals, b, P: torch.Tensor,
                w: torch.Tensor, rtol: float = 1e-12, max_iter: int = 20, check=True):
         """FP64 refinement of w against calH = (rowptr, colidx, vals), b with

@@ -60,7 +60,7 @@ static rbf_status batched_free(rbf_batched* b) {
 // Everything below is enqueued on the plan's own stream (captured).
 static rbf_status enqueue_all(rbf_batched* b) {
   rbf_ctx* ctx = b->cap;
-  for (auto k : b->kids) RBF_TRY(fill_zero(ctx, k->d_status, 4 * sizeof(int32_t)));
+  for (auto k : b->kids) RBF_TRY(fill_zero(ctx, k->d_status, STATUS_WORDS * sizeof(int32_t)));
   RBF_HIP(ctx, hipEventRecord(b->fork, ctx->stream));
   for (size_t q = 0; q < b->kids.size(); ++q) {
     rbf_ctx* k = b->kids[q];
@@ -165,6 +165,7 @@ rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params, const rbf_pa
       break;
     }
     k->owns_stream = 1;
+    k->single_stream = 1;
     b->kids.push_back(k);
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
@@ -201,6 +202,18 @@ rbf_status rbf_batched_run(rbf_batched* b) {
   if (!b->captured) {
     RBF_HIP(ctx, hipStreamBeginCapture(cap->stream, hipStreamCaptureModeThreadLocal));
     rbf_status st = enqueue_all(b);
+    if (st != RBF_OK) {
+      // rejoin every forked stream so that the capture can end
+      for (size_t q = 0; q < b->kids.size(); ++q) {
+        rbf_ctx* k = b->kids[q];
+        if (k->aux) {
+          (void)hipEventRecord(k->ev_back, k->aux);
+          (void)hipStreamWaitEvent(k->stream, k->ev_back, 0);
+        }
+        (void)hipEventRecord(b->joins[q], k->stream);
+        (void)hipStreamWaitEvent(cap->stream, b->joins[q], 0);
+      }
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cap->stream, &g);
     if (st != RBF_OK) {

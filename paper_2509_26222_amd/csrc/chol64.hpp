@@ -17,7 +17,7 @@
 // where the f64 MFMA output layout (lane j + 16 (i % 4), item i / 4) is the
 // B-operand layout of the next product's k-steps, so the two products chain
 // in registers. A non-positive or non-finite pivot records RBF_E_NOT_SPD
-// with `index` (the factor continues with pivot 1).
+// with `index` for launch group `seq` (the factor continues with pivot 1).
 #pragma once
 
 // 16x16 product tile on FP64 MFMA: acc += A[r0.., a0..] * B where B[k][j] is
@@ -35,7 +35,7 @@ __device__ inline v4d mma16_nt(const double (*A)[LDT], int r0, int a0, const dou
 }
 
 __device__ __noinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int32_t* status,
-                                    int64_t index) {
+                                    int64_t index, int64_t seq) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int bad;
   if (tid == 0) bad = 0;
@@ -167,6 +167,6 @@ __device__ __noinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int32_t
     }
     __syncthreads();
   }
-  if (tid == 0 && bad) set_status(status, RBF_E_NOT_SPD, index);
+  if (tid == 0 && bad) set_status(status, RBF_E_NOT_SPD, index, seq);
 }
 

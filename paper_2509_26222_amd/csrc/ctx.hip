@@ -28,7 +28,8 @@ void* ws_get(rbf_ctx* ctx, int slot, size_t bytes, rbf_status* st) {
   if (ctx->ws_bytes[slot] >= bytes) return ctx->ws[slot];
   if (ctx->ws[slot]) {
     // the old buffer may still be read by queued kernels
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess ||
+    if ((ctx->aux && hipStreamSynchronize(ctx->aux) != hipSuccess) ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess ||
         hipFree(ctx->ws[slot]) != hipSuccess) {
       *st = fail(ctx, RBF_E_HIP, "workspace release failed");
       return nullptr;
@@ -233,6 +234,14 @@ rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
   return RBF_OK;
 }
 
+rbf_status ensure_aux(rbf_ctx* ctx) {
+  if (ctx->aux) return RBF_OK;
+  RBF_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fwd, hipEventDisableTiming));
+  RBF_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_back, hipEventDisableTiming));
+  RBF_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  return RBF_OK;
+}
+
 }  // namespace rbf
 
 using namespace rbf;
@@ -252,15 +261,17 @@ rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;
   c->last_index = -1;
   c->tiles_key = -1;
+  c->seq = 1;
+  c->single_stream = 1;  // rbf_update on one stream unless asked for two
   if (hipSetDevice(device) != hipSuccess) {
     delete c;
     return RBF_E_HIP;
   }
-  if (hipMalloc(&c->d_status, 4 * sizeof(int32_t)) != hipSuccess) {
+  if (hipMalloc(&c->d_status, STATUS_WORDS * sizeof(int32_t)) != hipSuccess) {
     delete c;
     return RBF_E_NOMEM;
   }
-  if (hipMemset(c->d_status, 0, 4 * sizeof(int32_t)) != hipSuccess) {
+  if (hipMemset(c->d_status, 0, STATUS_WORDS * sizeof(int32_t)) != hipSuccess) {
     (void)hipFree(c->d_status);
     delete c;
     return RBF_E_HIP;
@@ -273,16 +284,28 @@ rbf_status rbf_ctx_destroy(rbf_ctx* ctx) {
   if (!ctx) return RBF_E_INVALID_ARG;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  if (ctx->ev_fwd) (void)hipEventDestroy(ctx->ev_fwd);
+  if (ctx->ev_back) (void)hipEventDestroy(ctx->ev_back);
   for (int k = 0; k < RBF_PROF_KINDS; ++k) {
     if (!ctx->prof_ev[k]) continue;
     for (int e = 0; e < 2 * PROF_CAP; ++e) (void)hipEventDestroy(ctx->prof_ev[k][e]);
     delete[] ctx->prof_ev[k];
   }
   delete ctx;
+  return RBF_OK;
+}
+
+rbf_status rbf_ctx_set_update_streams(rbf_ctx* ctx, int32_t streams) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  if (streams != 1 && streams != 2)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_ctx_set_update_streams: streams must be 1 or 2");
+  ctx->single_stream = streams == 1;
   return RBF_OK;
 }
 
@@ -303,7 +326,7 @@ rbf_status rbf_sync_status(rbf_ctx* ctx) {
     int64_t idx;
     memcpy(&idx, h + 2, sizeof(idx));
     ctx->last_index = idx;
-    RBF_TRY(fill_zero(ctx, ctx->d_status, 4 * sizeof(int32_t)));
+    RBF_TRY(fill_zero(ctx, ctx->d_status, STATUS_WORDS * sizeof(int32_t)));
     RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return fail(ctx, (rbf_status)h[0], "device error %d (%s) at index %lld", h[0],
                 rbf_status_string((rbf_status)h[0]), (long long)idx);

@@ -27,6 +27,8 @@ enum WsSlot {
   WS_UPD_LINV,  // update: inverses of the diagonal blocks of L
   WS_UPD_VLO,   // update: low-precision copy of V^T
   WS_UPD_TILES, // update: SYRK tile schedule
+  WS_UPD_UT2,   // update: second U^T / V^T buffer (batches alternate)
+  WS_UPD_FLAGS, // update: touched 128-row blocks of P, two batches
   WS_SOLVE0,
   WS_SOLVE1,
   WS_SOLVE2,
@@ -42,9 +44,20 @@ enum WsSlot {
 struct rbf_ctx {
   int device;
   hipStream_t stream;
-  // d_status[0]: first error code, d_status[1]: unused,
-  // d_status[2..3]: int64 index attached to the error.
+  // d_status (STATUS_WORDS int32): [0] first error code, [1] unused,
+  // [2..3] int64 index attached to that error, [4..5] uint64 skip key
+  // (see set_status / seq_skip).
   int32_t* d_status;
+  // sequence number of the next sequenced launch group (a batch of
+  // rbf_update, one rbf_solve); starts at 1
+  int64_t seq;
+  // second stream of rbf_update (created on first use, non-blocking,
+  // default priority) and the two events that order it with `stream`
+  hipStream_t aux;
+  hipEvent_t ev_fwd, ev_back;
+  // rbf_update keeps to one stream (set for the batched form's branches,
+  // whose graph capture does not take the two-stream schedule)
+  int32_t single_stream;
   void* ws[rbf::WS_COUNT];
   size_t ws_bytes[rbf::WS_COUNT];
   int64_t last_index;
@@ -97,11 +110,27 @@ inline GridGeom geom(const rbf_grid* g) {
   return r;
 }
 
+constexpr int STATUS_WORDS = 8;
+constexpr uint64_t SEQ_TOP = 1ull << 62;
+
 // Record a device-side error: the first error wins, its index is kept.
-__device__ inline void set_status(int32_t* st, int code, int64_t index) {
+// `seq` is the sequence number of the failing launch group (0: an error
+// outside any group). The skip key keeps the smallest failing sequence
+// number, as SEQ_TOP - seq under an atomic max, so that seq_skip() lets
+// the launches of earlier groups still in flight on another stream finish.
+__device__ inline void set_status(int32_t* st, int code, int64_t index, int64_t seq = 0) {
+  atomicMax(reinterpret_cast<unsigned long long*>(st + 4),
+            (unsigned long long)(SEQ_TOP - (uint64_t)seq));
   if (atomicCAS(st, 0, code) == 0) {
     *reinterpret_cast<int64_t*>(st + 2) = index;
   }
+}
+
+// True if an error is pending from launch group `seq` or an earlier one
+// (or from outside any group): the launches of group `seq` then do nothing.
+__device__ inline bool seq_skip(const int32_t* st, int64_t seq) {
+  const uint64_t key = *reinterpret_cast<const volatile unsigned long long*>(st + 4);
+  return key != 0 && key >= SEQ_TOP - (uint64_t)seq;
 }
 
 // Bin range [lo, hi] of the 3x3 neighbourhood of coordinate v, clipped to
@@ -138,6 +167,20 @@ void prof_end(rbf_ctx* ctx, int kind);
 // Zero device memory with a kernel (no memset node, so the call is safe
 // inside stream capture).
 rbf_status fill_zero(rbf_ctx* ctx, void* p, size_t bytes);
+
+// Create the context's second stream and its two events if not yet done.
+rbf_status ensure_aux(rbf_ctx* ctx);
+
+// Enqueue on another stream of the context for the lifetime of the guard:
+// every helper launches on ctx->stream, which the guard swaps and restores.
+struct StreamSwap {
+  rbf_ctx* ctx;
+  hipStream_t saved;
+  StreamSwap(rbf_ctx* c, hipStream_t s) : ctx(c), saved(c->stream) { c->stream = s; }
+  ~StreamSwap() { ctx->stream = saved; }
+  StreamSwap(const StreamSwap&) = delete;
+  StreamSwap& operator=(const StreamSwap&) = delete;
+};
 
 // Stable counting sort by a precomputed key in [0, nkeys): writes perm
 // (sorted position -> item) and start (nkeys + 1 offsets).

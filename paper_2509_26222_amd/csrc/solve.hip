@@ -22,7 +22,6 @@ namespace rbf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__device__ inline bool sfailed(const int32_t* st) { return *(volatile const int32_t*)st != 0; }
 
 __global__ void __launch_bounds__(256) k_csr_bandwidth(const int64_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ colidx,
@@ -74,8 +73,9 @@ __global__ void __launch_bounds__(256) k_gemm_sub(int64_t M, int64_t Nc, int64_t
                                                   const double* __restrict__ A, int64_t lda,
                                                   const double* __restrict__ B, int64_t ldb,
                                                   double* __restrict__ C, int64_t ldc,
-                                                  const int32_t* __restrict__ status) {
-  if (sfailed(status)) return;
+                                                  const int32_t* __restrict__ status,
+                                                  int64_t seq) {
+  if (seq_skip(status, seq)) return;
   __shared__ double As[GK][GT + 1];  // As[k][m]
   __shared__ double Bs[GK][GT + 1];  // Bs[k][n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -131,14 +131,14 @@ __global__ void __launch_bounds__(256) k_gemm_sub(int64_t M, int64_t Nc, int64_t
 
 static rbf_status gemm_sub(rbf_ctx* ctx, bool ta, int64_t M, int64_t Nc, int64_t K,
                            const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                           int64_t ldc) {
+                           int64_t ldc, int64_t seq) {
   dim3 grid((unsigned)ceil_div(Nc, GT), (unsigned)ceil_div(M, GT));
   if (ta)
     k_gemm_sub<true><<<grid, 256, 0, ctx->stream>>>(M, Nc, K, A, lda, B, ldb, C, ldc,
-                                                    ctx->d_status);
+                                                    ctx->d_status, seq);
   else
     k_gemm_sub<false><<<grid, 256, 0, ctx->stream>>>(M, Nc, K, A, lda, B, ldb, C, ldc,
-                                                     ctx->d_status);
+                                                     ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_gemm_sub");
   return RBF_OK;
 }
@@ -221,11 +221,15 @@ static rbf_status col_norms(rbf_ctx* ctx, const double* A, int64_t lda, int64_t 
   return RBF_OK;
 }
 
-// w_i += (1/R) sum_j P_ij r_j: one wave per row of P (coalesced row reads,
-// four loads in flight per lane), fixed-order shuffle reduction.
-__global__ void __launch_bounds__(256) k_refine_symv(const double* __restrict__ P, int64_t ldp,
-                                                     int64_t N, const double* __restrict__ r,
-                                                     double inv_R, double* __restrict__ w) {
+// ---- refinement of the recursive update's weights (rbf_refine): conjugate
+// gradients on calH w = b preconditioned by P / R, the Hestenes-Stiefel
+// method with the preconditioner applied as z = M r.
+
+// y_i = s sum_j P_ij x_j: one wave per row of P (coalesced row reads, four
+// loads in flight per lane), fixed-order shuffle reduction.
+__global__ void __launch_bounds__(256) k_pcg_symv(const double* __restrict__ P, int64_t ldp,
+                                                  int64_t N, const double* __restrict__ x,
+                                                  double s, double* __restrict__ y) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= N) return;
@@ -233,17 +237,93 @@ __global__ void __launch_bounds__(256) k_refine_symv(const double* __restrict__ 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t j = lane;
   for (; j + 192 < N; j += 256) {
-    s0 += row[j] * r[j];
-    s1 += row[j + 64] * r[j + 64];
-    s2 += row[j + 128] * r[j + 128];
-    s3 += row[j + 192] * r[j + 192];
+    s0 += row[j] * x[j];
+    s1 += row[j + 64] * x[j + 64];
+    s2 += row[j + 128] * x[j + 128];
+    s3 += row[j + 192] * x[j + 192];
   }
-  for (; j < N; j += 64) s0 += row[j] * r[j];
-  double s = (s0 + s1) + (s2 + s3);
+  for (; j < N; j += 64) s0 += row[j] * x[j];
+  double t = (s0 + s1) + (s2 + s3);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) w[i] += s * inv_R;
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (lane == 0) y[i] = s * t;
 }
+
+// y = A x for the CSR matrix, one thread per row.
+__global__ void __launch_bounds__(256) k_csr_mv(const int64_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ colidx,
+                                                const double* __restrict__ vals, int64_t N,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= N) return;
+  double t = 0.0;
+  for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) t += vals[k] * x[colidx[k]];
+  y[r] = t;
+}
+
+// Dot product in two fixed-order stages: part[g] over 2048-element group g,
+// then out = sum_g part[g] (one workgroup).
+constexpr int DOT_G = 2048;
+__device__ inline double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) sh[tid] += sh[tid + o];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_part(const double* __restrict__ x,
+                                                  const double* __restrict__ y, int64_t N,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int64_t g0 = (int64_t)blockIdx.x * DOT_G;
+  double v = 0.0;
+  for (int u = 0; u < DOT_G / 256; ++u) {
+    const int64_t e = g0 + u * 256 + threadIdx.x;
+    if (e < N) v += x[e] * y[e];
+  }
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_dot_sum(const double* __restrict__ part, int32_t ng,
+                                                 double* __restrict__ out) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int g = threadIdx.x; g < ng; g += 256) v += part[g];
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) *out = t;
+}
+
+// Scalars of the iteration (device): rz = r.z, rz_new, pq = p.(calH p), rr.
+enum { SC_RZ = 0, SC_RZN = 1, SC_PQ = 2, SC_RR = 3, SC_N = 4 };
+
+// w += alpha p, r -= alpha q, alpha = rz / pq
+__global__ void __launch_bounds__(256) k_pcg_step(double* __restrict__ w, double* __restrict__ r,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ q, int64_t N,
+                                                  const double* __restrict__ sc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N) return;
+  const double alpha = sc[SC_RZ] / sc[SC_PQ];
+  w[e] += alpha * p[e];
+  r[e] -= alpha * q[e];
+}
+
+// p = z + beta p with beta = rz_new / rz (p = z when first != 0)
+__global__ void __launch_bounds__(256) k_pcg_dir(double* __restrict__ p,
+                                                 const double* __restrict__ z, int64_t N,
+                                                 const double* __restrict__ sc, int first) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N) return;
+  p[e] = first ? z[e] : z[e] + (sc[SC_RZN] / sc[SC_RZ]) * p[e];
+}
+
+__global__ void k_pcg_shift(double* __restrict__ sc) { sc[SC_RZ] = sc[SC_RZN]; }
 
 }  // namespace rbf
 
@@ -262,37 +342,86 @@ extern "C" rbf_status rbf_refine(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
   RBF_TRY(set_device(ctx));
   RBF_TRY(rbf_sync_status(ctx));
   rbf_status st;
-  double* r = (double*)ws_get(ctx, WS_SOLVE5, sizeof(double) * N, &st);
-  if (!r) return st;
-  const int32_t ngroups = (int32_t)ceil_div(N, NRG);
-  double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (ngroups + 1), &st);
+  double* vec = (double*)ws_get(ctx, WS_SOLVE5, sizeof(double) * 4 * (size_t)N, &st);
+  if (!vec) return st;
+  double *r = vec, *z = vec + N, *pd = vec + 2 * N, *q = vec + 3 * N;
+  const int32_t ng = (int32_t)ceil_div(N, DOT_G);
+  double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (ng + 1), &st);
   if (!part) return st;
-  double* dnorm = (double*)ws_get(ctx, WS_TMP2, sizeof(double), &st);
-  if (!dnorm) return st;
-  std::vector<double> bn, rn;
-  RBF_TRY(col_norms(ctx, b, 1, N, 1, part, dnorm, bn));
+  double* sc = (double*)ws_get(ctx, WS_TMP2, sizeof(double) * 8, &st);
+  if (!sc) return st;
+  const unsigned gN = (unsigned)ceil_div(N, 256);
+  auto dot = [&](const double* x, const double* y, int slot) -> rbf_status {
+    k_dot_part<<<ng, 256, 0, ctx->stream>>>(x, y, N, part);
+    RBF_LAUNCHED(ctx, "k_dot_part");
+    k_dot_sum<<<1, 256, 0, ctx->stream>>>(part, ng, sc + slot);
+    RBF_LAUNCHED(ctx, "k_dot_sum");
+    return RBF_OK;
+  };
+  double h[SC_N];
+  auto read = [&]() -> rbf_status {
+    RBF_HIP(ctx, hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return RBF_OK;
+  };
+  // ||b||
+  RBF_TRY(dot(b, b, SC_RR));
+  RBF_TRY(read());
+  const double bn = std::sqrt(h[SC_RR]);
+  auto rel_of = [&](double rr) { return bn > 0 ? std::sqrt(rr) / bn : std::sqrt(rr); };
+  // true residual r = b - calH w and its norm
   auto residual = [&](double* rel) -> rbf_status {
-    k_residual<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, b, 1, w, 1,
-                                                         1, r);
+    k_residual<<<gN, 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, b, 1, w, 1, 1, r);
     RBF_LAUNCHED(ctx, "k_residual");
-    RBF_TRY(col_norms(ctx, r, 1, N, 1, part, dnorm, rn));
-    *rel = bn[0] > 0 ? rn[0] / bn[0] : rn[0];
+    RBF_TRY(dot(r, r, SC_RR));
+    RBF_TRY(read());
+    *rel = rel_of(h[SC_RR]);
     return RBF_OK;
   };
   double rel = 0.0;
   RBF_TRY(residual(&rel));
   int32_t it = 0;
-  while (!(rel <= rtol) && it < max_iter && std::isfinite(rel)) {
-    k_refine_symv<<<ceil_div(N, 4), 256, 0, ctx->stream>>>(P, ldp, N, r, 1.0 / R, w);
-    RBF_LAUNCHED(ctx, "k_refine_symv");
-    ++it;
+  bool breakdown = false;
+  // restart from the true residual whenever the recursive one says done
+  while (!(rel <= rtol) && it < max_iter && std::isfinite(rel) && !breakdown) {
+    k_pcg_symv<<<(unsigned)ceil_div(N, 4), 256, 0, ctx->stream>>>(P, ldp, N, r, 1.0 / R, z);
+    RBF_LAUNCHED(ctx, "k_pcg_symv");
+    RBF_TRY(dot(r, z, SC_RZN));
+    k_pcg_dir<<<gN, 256, 0, ctx->stream>>>(pd, z, N, sc, 1);
+    RBF_LAUNCHED(ctx, "k_pcg_dir");
+    k_pcg_shift<<<1, 1, 0, ctx->stream>>>(sc);
+    RBF_LAUNCHED(ctx, "k_pcg_shift");
+    double rec = rel;
+    while (it < max_iter) {
+      k_csr_mv<<<gN, 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, pd, q);
+      RBF_LAUNCHED(ctx, "k_csr_mv");
+      RBF_TRY(dot(pd, q, SC_PQ));
+      k_pcg_step<<<gN, 256, 0, ctx->stream>>>(w, r, pd, q, N, sc);
+      RBF_LAUNCHED(ctx, "k_pcg_step");
+      ++it;
+      RBF_TRY(dot(r, r, SC_RR));
+      RBF_TRY(read());
+      if (!(h[SC_RZ] > 0.0) || !(h[SC_PQ] > 0.0)) {  // P / R or calH not positive definite
+        breakdown = true;
+        break;
+      }
+      rec = rel_of(h[SC_RR]);
+      if (rec <= rtol || !std::isfinite(rec)) break;
+      k_pcg_symv<<<(unsigned)ceil_div(N, 4), 256, 0, ctx->stream>>>(P, ldp, N, r, 1.0 / R, z);
+      RBF_LAUNCHED(ctx, "k_pcg_symv");
+      RBF_TRY(dot(r, z, SC_RZN));
+      k_pcg_dir<<<gN, 256, 0, ctx->stream>>>(pd, z, N, sc, 0);
+      RBF_LAUNCHED(ctx, "k_pcg_dir");
+      k_pcg_shift<<<1, 1, 0, ctx->stream>>>(sc);
+      RBF_LAUNCHED(ctx, "k_pcg_shift");
+    }
     RBF_TRY(residual(&rel));
   }
   if (iters) *iters = it;
   if (relres) *relres = rel;
   if (!(rel <= rtol))
-    return fail(ctx, RBF_E_NO_CONVERGE, "rbf_refine: relres %g above %g after %d sweeps", rel,
-                rtol, it);
+    return fail(ctx, RBF_E_NO_CONVERGE, "rbf_refine: relres %g above %g after %d iterations%s",
+                rel, rtol, it, breakdown ? " (lost positive definiteness)" : "");
   return RBF_OK;
 }
 
@@ -310,6 +439,7 @@ extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_solve: inner precision %d not available",
                 (int)inner);
   RBF_TRY(set_device(ctx));
+  const int64_t seq = ctx->seq++;  // one launch group for the whole solve
   rbf_status st;
   // ---- bandwidth -> block size
   int32_t* d_bw = (int32_t*)ws_get(ctx, WS_SOLVE6, 256, &st);
@@ -356,11 +486,13 @@ extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
   // ---- block Cholesky
   for (int64_t i = 0; i < nblk; ++i) {
     double* Di = D + i * ss;
-    if (i > 0) RBF_TRY(gemm_sub(ctx, true, s, s, s, Ub + (i - 1) * ss, s, Ub + (i - 1) * ss, s, Di, s));
-    RBF_TRY(chol_blocked(ctx, Di, (int32_t)s, Lb + i * ss, Linv + i * nsub * 4096, i));
+    if (i > 0)
+      RBF_TRY(gemm_sub(ctx, true, s, s, s, Ub + (i - 1) * ss, s, Ub + (i - 1) * ss, s, Di, s,
+                       seq));
+    RBF_TRY(chol_blocked(ctx, Di, (int32_t)s, Lb + i * ss, Linv + i * nsub * 4096, i, seq));
     if (i + 1 < nblk)
       RBF_TRY(trsm_blocks(ctx, Ub + i * ss, s, s, (int32_t)nsub, Lb + i * ss, s,
-                          Linv + i * nsub * 4096, false));
+                          Linv + i * nsub * 4096, false, seq));
   }
   {
     int32_t h[4];
@@ -382,16 +514,17 @@ extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
       double* Yi = Y + i * s * nrhs;
       if (i > 0)
         RBF_TRY(gemm_sub(ctx, true, s, nrhs, s, Ub + (i - 1) * ss, s, Yi - s * nrhs, nrhs, Yi,
-                         nrhs));
+                         nrhs, seq));
       RBF_TRY(trsm_blocks(ctx, Yi, nrhs, nrhs, (int32_t)nsub, Lb + i * ss, s,
-                          Linv + i * nsub * 4096, false));
+                          Linv + i * nsub * 4096, false, seq));
     }
     for (int64_t i = nblk - 1; i >= 0; --i) {
       double* Yi = Y + i * s * nrhs;
       if (i + 1 < nblk)
-        RBF_TRY(gemm_sub(ctx, false, s, nrhs, s, Ub + i * ss, s, Yi + s * nrhs, nrhs, Yi, nrhs));
+        RBF_TRY(gemm_sub(ctx, false, s, nrhs, s, Ub + i * ss, s, Yi + s * nrhs, nrhs, Yi, nrhs,
+                         seq));
       RBF_TRY(trsm_blocks(ctx, Yi, nrhs, nrhs, (int32_t)nsub, Lb + i * ss, s,
-                          Linv + i * nsub * 4096, true));
+                          Linv + i * nsub * 4096, true, seq));
     }
     k_accum<<<ceil_div(N * nrhs, 256), 256, 0, ctx->stream>>>(X, ldx, Y, N, nrhs, it == 0);
     RBF_LAUNCHED(ctx, "k_accum");

@@ -16,7 +16,7 @@ namespace rbf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int ST = 128;     // output tile
+constexpr int ST = SYRK_TILE;  // output tile
 constexpr int SKC = 16;     // rows of V^T per LDS stage
 constexpr int SLD = ST + 8; // LDS pitch (doubles)
 
@@ -26,6 +26,14 @@ __device__ inline void tile_of(int64_t t, int* I, int* J) {
   while ((int64_t)i * (i + 1) / 2 > t) --i;
   *I = i;
   *J = (int)(t - (int64_t)i * (i + 1) / 2);
+}
+
+// Tile filter of a split product: part 0 all tiles, part 1 the tiles in a
+// flagged block row or column, part 2 the others.
+__device__ inline bool tile_in_part(const int32_t* __restrict__ flags, int part, int I, int J) {
+  if (part == 0) return true;
+  const bool f = flags[I] != 0 || flags[J] != 0;
+  return part == 1 ? f : !f;
 }
 
 __device__ inline int64_t xcd_tile(int64_t per_xcd) {
@@ -56,12 +64,15 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int
                                                      int64_t N, const double* __restrict__ Ut,
                                                      int64_t ldu, int32_t K, int64_t T,
                                                      int64_t per_xcd,
-                                                     const int32_t* __restrict__ status) {
-  if (*(volatile const int32_t*)status != 0) return;
+                                                     const int32_t* __restrict__ flags, int part,
+                                                     const int32_t* __restrict__ status,
+                                                     int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
   int I, J;
   tile_of(t, &I, &J);
+  if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
   __shared__ double As[2][SKC][SLD];
   __shared__ double Bs[2][SKC][SLD];
@@ -150,8 +161,9 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 __global__ void __launch_bounds__(256) k_cvt_f32(const double* __restrict__ Ut, int64_t ldu,
                                                  int32_t K, int64_t N, float* __restrict__ Uf,
-                                                 const int32_t* __restrict__ status) {
-  if (*(volatile const int32_t*)status != 0) return;
+                                                 const int32_t* __restrict__ status,
+                                                 int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)K * ldu) return;
   const int64_t c = e % ldu;
@@ -164,8 +176,9 @@ __global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ U
                                                     int32_t K, int64_t N, int32_t Kp,
                                                     __bf16* __restrict__ Vhi,
                                                     __bf16* __restrict__ Vlo,
-                                                    const int32_t* __restrict__ status) {
-  if (*(volatile const int32_t*)status != 0) return;
+                                                    const int32_t* __restrict__ status,
+                                                    int64_t seq) {
+  if (seq_skip(status, seq)) return;
   __shared__ double t[64][65];
   const int64_t n0 = (int64_t)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
@@ -215,12 +228,15 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int
                                                      int64_t N, const float* __restrict__ Uf,
                                                      int64_t ldu, int32_t K, int64_t T,
                                                      int64_t per_xcd,
-                                                     const int32_t* __restrict__ status) {
-  if (*(volatile const int32_t*)status != 0) return;
+                                                     const int32_t* __restrict__ flags, int part,
+                                                     const int32_t* __restrict__ status,
+                                                     int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
   int I, J;
   tile_of(t, &I, &J);
+  if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
   __shared__ float As[FKC][FLD];
   __shared__ float Bs[FKC][FLD];
@@ -279,12 +295,16 @@ __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, 
                                                         int64_t N, const __bf16* __restrict__ Vhi,
                                                         const __bf16* __restrict__ Vlo,
                                                         int32_t Kp, int64_t T, int64_t per_xcd,
-                                                        const int32_t* __restrict__ status) {
-  if (*(volatile const int32_t*)status != 0) return;
+                                                        const int32_t* __restrict__ flags,
+                                                        int part,
+                                                        const int32_t* __restrict__ status,
+                                                        int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
   int I, J;
   tile_of(t, &I, &J);
+  if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[ST][BLD];
   __shared__ __attribute__((aligned(16))) __bf16 Al[ST][BLD];
@@ -348,15 +368,18 @@ __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, 
 }
 
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
-                       int64_t ldu, int32_t Bc, rbf_prec prec) {
+                       int64_t ldu, int32_t Bc, rbf_prec prec, const int32_t* flags,
+                       int part, int64_t seq) {
+  if (part != 0 && !flags) return fail(ctx, RBF_E_INVALID_ARG, "syrk_update: part without flags");
   const int64_t nt = ceil_div(N, ST);
   const int64_t T = nt * (nt + 1) / 2;
   const int64_t per_xcd = ceil_div(T, 8);
+  const unsigned grid = (unsigned)(per_xcd * 8);
   rbf_status st;
   if (prec == RBF_F64) {
     prof_begin(ctx, RBF_PROF_SYRK);
-    k_syrk_f64<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T,
-                                                                 per_xcd, ctx->d_status);
+    k_syrk_f64<<<grid, 256, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T, per_xcd, flags, part,
+                                              ctx->d_status, seq);
     RBF_LAUNCHED(ctx, "k_syrk_f64");
     prof_end(ctx, RBF_PROF_SYRK);
     return RBF_OK;
@@ -364,12 +387,14 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
   if (prec == RBF_F32) {
     float* Uf = (float*)ws_get(ctx, WS_UPD_VLO, sizeof(float) * (size_t)Bc * ldu, &st);
     if (!Uf) return st;
-    k_cvt_f32<<<ceil_div((int64_t)Bc * ldu, 256), 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, Uf,
-                                                                         ctx->d_status);
-    RBF_LAUNCHED(ctx, "k_cvt_f32");
+    if (part != 2) {
+      k_cvt_f32<<<ceil_div((int64_t)Bc * ldu, 256), 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, Uf,
+                                                                           ctx->d_status, seq);
+      RBF_LAUNCHED(ctx, "k_cvt_f32");
+    }
     prof_begin(ctx, RBF_PROF_SYRK);
-    k_syrk_f32<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, Uf, ldu, Bc, T,
-                                                                 per_xcd, ctx->d_status);
+    k_syrk_f32<<<grid, 256, 0, ctx->stream>>>(P, ldp, N, Uf, ldu, Bc, T, per_xcd, flags, part,
+                                              ctx->d_status, seq);
     RBF_LAUNCHED(ctx, "k_syrk_f32");
     prof_end(ctx, RBF_PROF_SYRK);
     return RBF_OK;
@@ -378,12 +403,14 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
   __bf16* V = (__bf16*)ws_get(ctx, WS_UPD_VLO, sizeof(__bf16) * 2 * (size_t)N * Kp, &st);
   if (!V) return st;
   __bf16* Vlo = V + (size_t)N * Kp;
-  dim3 gc((unsigned)ceil_div(N, 64), (unsigned)ceil_div(Kp, 64));
-  k_cvt_bf16x2<<<gc, 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, Kp, V, Vlo, ctx->d_status);
-  RBF_LAUNCHED(ctx, "k_cvt_bf16x2");
+  if (part != 2) {
+    dim3 gc((unsigned)ceil_div(N, 64), (unsigned)ceil_div(Kp, 64));
+    k_cvt_bf16x2<<<gc, 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, Kp, V, Vlo, ctx->d_status, seq);
+    RBF_LAUNCHED(ctx, "k_cvt_bf16x2");
+  }
   prof_begin(ctx, RBF_PROF_SYRK);
-  k_syrk_bf16x3<<<(unsigned)(per_xcd * 8), 256, 0, ctx->stream>>>(P, ldp, N, V, Vlo, Kp, T,
-                                                                  per_xcd, ctx->d_status);
+  k_syrk_bf16x3<<<grid, 256, 0, ctx->stream>>>(P, ldp, N, V, Vlo, Kp, T, per_xcd, flags, part,
+                                               ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_syrk_bf16x3");
   prof_end(ctx, RBF_PROF_SYRK);
   return RBF_OK;

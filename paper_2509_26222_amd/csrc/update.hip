@@ -29,7 +29,6 @@ struct RegKU {
   double rc2, den, scale;
 };
 
-__device__ inline bool failed(const int32_t* st) { return *(volatile const int32_t*)st != 0; }
 
 // ------------------------------------------------------------ batch rows
 
@@ -41,9 +40,9 @@ __global__ void __launch_bounds__(256) k_upd_rows(
     const int32_t* __restrict__ start, GridGeom g, RegKU k, int32_t kmax,
     const double* __restrict__ w, double* __restrict__ vals, int32_t* __restrict__ cols,
     int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu, int64_t N,
-    int32_t* __restrict__ status, int64_t batch) {
+    int32_t* __restrict__ status, int64_t batch, int64_t seq) {
   const int b = blockIdx.x * 256 + threadIdx.x;
-  if (b >= Bp || failed(status)) return;
+  if (b >= Bp || seq_skip(status, seq)) return;
   if (b >= Bc) {
     nnz[b] = 0;
     Ut[(int64_t)b * ldu + N] = 0.0;
@@ -76,7 +75,7 @@ __global__ void __launch_bounds__(256) k_upd_rows(
   const double zb = z[b];
   const double yb = zb - hw;
   if (!isfinite(zb) || !isfinite(yb) || !isfinite(x) || !isfinite(y))
-    set_status(status, RBF_E_NONFINITE, batch);
+    set_status(status, RBF_E_NONFINITE, batch, seq);
   Ut[(int64_t)b * ldu + N] = yb;
 }
 
@@ -86,8 +85,8 @@ __global__ void __launch_bounds__(256) k_upd_gather_u(
     const double* __restrict__ P, int64_t ldp, int64_t N, int32_t Bc, int32_t Bp,
     const double* __restrict__ vals, const int32_t* __restrict__ cols,
     const int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu,
-    const int32_t* __restrict__ status) {
-  if (failed(status)) return;
+    const int32_t* __restrict__ status, int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t n0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   const int b0 = blockIdx.y * 8;
   for (int r = 0; r < 8; ++r) {
@@ -121,8 +120,9 @@ __global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
                                                const double* __restrict__ Ut, int64_t ldu,
                                                int32_t Bc, int32_t Bp, double R,
                                                double* __restrict__ S,
-                                               const int32_t* __restrict__ status) {
-  if (failed(status)) return;
+                                               const int32_t* __restrict__ status,
+                                               int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int b = blockIdx.y;
   const int a = blockIdx.x * 256 + threadIdx.x;
   if (a >= Bp || a < b) return;
@@ -219,12 +219,13 @@ __device__ inline void acc_to_lds(const Acc64& A, double (*T)[LDT]) {
 __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S, int32_t Bp,
                                                     double* __restrict__ Lb,
                                                     double* __restrict__ Linv,
-                                                    int32_t* __restrict__ status, int64_t batch) {
-  if (failed(status)) return;
+                                                    int32_t* __restrict__ status, int64_t batch,
+                                                    int64_t seq) {
+  if (seq_skip(status, seq)) return;
   __shared__ double T[NB][LDT], Ti[NB][LDT];
   load_tile(T, S, Bp);
   __syncthreads();
-  chol64(T, Ti, status, batch);
+  chol64(T, Ti, status, batch, seq);
   store_tile(T, Lb, Bp);
   store_tile(Ti, Linv, NB);
 }
@@ -238,8 +239,9 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
                                                    int32_t nblk, int32_t kb,
                                                    double* __restrict__ Lb,
                                                    double* __restrict__ Linv,
-                                                   int32_t* __restrict__ status, int64_t batch) {
-  if (failed(status)) return;
+                                                   int32_t* __restrict__ status, int64_t batch,
+                                                   int64_t seq) {
+  if (seq_skip(status, seq)) return;
   __shared__ double Li[NB][LDT], T1[NB][LDT], T2[NB][LDT];
   const int m = nblk - kb - 1;
   const int t = blockIdx.x;
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
           Li[r][c] = Aij[(int64_t)r * Bp + c] - U.c[mi][ni][v];
         }
     __syncthreads();
-    chol64(Li, T2, status, batch);
+    chol64(Li, T2, status, batch, seq);
     store_tile(Li, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
     store_tile(T2, Linv + (int64_t)i * NB * NB, NB);
     return;
@@ -398,8 +400,9 @@ __global__ void __launch_bounds__(256) k_trsm_blocks(double* __restrict__ Ut, in
                                                      int64_t ncols, int32_t nblk,
                                                      const double* __restrict__ Lb, int64_t ldl,
                                                      const double* __restrict__ Linv,
-                                                     const int32_t* __restrict__ status) {
-  if (failed(status)) return;
+                                                     const int32_t* __restrict__ status,
+                                                     int64_t seq) {
+  if (seq_skip(status, seq)) return;
   __shared__ double Lt[NB][LDT];
   __shared__ double X[NB][LDX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -486,8 +489,9 @@ __global__ void __launch_bounds__(256) k_trsm_blocks(double* __restrict__ Ut, in
 __global__ void __launch_bounds__(256) k_upd_w_part(const double* __restrict__ Ut, int64_t ldu,
                                                     int64_t N, int32_t Bc,
                                                     double* __restrict__ part,
-                                                    const int32_t* __restrict__ status) {
-  if (failed(status)) return;
+                                                    const int32_t* __restrict__ status,
+                                                    int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   const int b0 = blockIdx.y * 64;
@@ -505,13 +509,31 @@ __global__ void __launch_bounds__(256) k_upd_w_part(const double* __restrict__ U
 __global__ void __launch_bounds__(256) k_upd_w_sum(double* __restrict__ w,
                                                    const double* __restrict__ part, int64_t N,
                                                    int32_t ngroups,
-                                                   const int32_t* __restrict__ status) {
-  if (failed(status)) return;
+                                                   const int32_t* __restrict__ status,
+                                                   int64_t seq) {
+  if (seq_skip(status, seq)) return;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   double s = 0.0;
   for (int g = 0; g < ngroups; ++g) s += part[(int64_t)g * N + n];
   w[n] += s;
+}
+
+// Touched row blocks of P: flags[c / SYRK_TILE] = 1 for every center c in
+// the batch's regressor rows (flags cleared beforehand). The covariance
+// product of the previous batch computes the tiles in these block rows and
+// columns first, so the gather of this batch can start while it finishes
+// the rest.
+__global__ void __launch_bounds__(256) k_upd_flags(const int32_t* __restrict__ cols,
+                                                   const int32_t* __restrict__ nnz, int32_t Bc,
+                                                   int32_t Bp, int32_t* __restrict__ flags,
+                                                   const int32_t* __restrict__ status,
+                                                   int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= Bc) return;
+  const int nz = nnz[b];
+  for (int q = 0; q < nz; ++q) flags[cols[(int64_t)q * Bp + b] / SYRK_TILE] = 1;
 }
 
 rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
@@ -527,6 +549,11 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
   ws->nnz = ws->cols + (size_t)Bp * kmax;
   ws->Ut = (double*)ws_get(ctx, WS_UPD_UT, sizeof(double) * (size_t)Bp * ldu, &st);
   if (!ws->Ut) return st;
+  ws->Ut2 = (double*)ws_get(ctx, WS_UPD_UT2, sizeof(double) * (size_t)Bp * ldu, &st);
+  if (!ws->Ut2) return st;
+  ws->flags = (int32_t*)ws_get(ctx, WS_UPD_FLAGS,
+                               sizeof(int32_t) * 2 * (size_t)ceil_div(N, SYRK_TILE), &st);
+  if (!ws->flags) return st;
   ws->S = (double*)ws_get(ctx, WS_UPD_S, sizeof(double) * (size_t)Bp * Bp * 2, &st);
   if (!ws->S) return st;
   ws->Lb = ws->S + (size_t)Bp * Bp;
@@ -543,29 +570,30 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
 }
 
 rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
-                        int64_t index) {
+                        int64_t index, int64_t seq) {
   const int32_t nblk = n / NB;
-  k_chol_first<<<1, 256, 0, ctx->stream>>>(S, n, Lb, Linv, ctx->d_status, index);
+  k_chol_first<<<1, 256, 0, ctx->stream>>>(S, n, Lb, Linv, ctx->d_status, index, seq);
   RBF_LAUNCHED(ctx, "k_chol_first");
   for (int32_t kb = 0; kb + 1 < nblk; ++kb) {
     const int m = nblk - kb - 1;
     k_chol_step<<<m + m * (m + 1) / 2, 256, 0, ctx->stream>>>(S, n, nblk, kb, Lb, Linv,
-                                                             ctx->d_status, index);
+                                                             ctx->d_status, index, seq);
     RBF_LAUNCHED(ctx, "k_chol_step");
   }
   return RBF_OK;
 }
 
 rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int32_t nblk,
-                       const double* Lb, int64_t ldl, const double* Linv, bool trans) {
+                       const double* Lb, int64_t ldl, const double* Linv, bool trans,
+                       int64_t seq) {
   if (ncols <= 0 || nblk <= 0) return RBF_OK;
   const unsigned grid = (unsigned)ceil_div(ncols, TW);
   if (trans)
     k_trsm_blocks<true><<<grid, 256, 0, ctx->stream>>>(X, ldx, ncols, nblk, Lb, ldl, Linv,
-                                                       ctx->d_status);
+                                                       ctx->d_status, seq);
   else
     k_trsm_blocks<false><<<grid, 256, 0, ctx->stream>>>(X, ldx, ncols, nblk, Lb, ldl, Linv,
-                                                        ctx->d_status);
+                                                        ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_trsm_blocks");
   return RBF_OK;
 }
@@ -603,7 +631,6 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
   double* vals = ws.vals;
   int32_t* cols = ws.cols;
   int32_t* nnz = ws.nnz;
-  double* Ut = ws.Ut;
   double* S = ws.S;
   double* Lb = ws.Lb;
   double* Linv = ws.Linv;
@@ -614,38 +641,134 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
   rk.den = 2.0 * st_ * st_;
   rk.scale = (p->sigma * p->sigma) / (st_ * st_);
   const int64_t nb_total = ceil_div(M, B);
-  for (int64_t bi = 0; bi < nb_total; ++bi) {
+  // Launch group (sequence number) of batch bi: seq0 + bi. A failure in
+  // batch bi stops the launches of batches >= bi only.
+  const int64_t seq0 = ctx->seq;
+  ctx->seq += nb_total;
+  // Two streams when there is more than one batch: `ms` (the context's
+  // stream) runs the covariance products, `as` the chain of the next batch
+  // (regressor rows, U, S, Cholesky, V, w). Batch bi+1's gather reads only
+  // the rows of P in its touched blocks, which part 1 of batch bi's product
+  // finishes first; part 2 (all other tiles) overlaps the chain.
+  // Under stream capture (the batched form's graph, or a caller's) the
+  // update keeps to the single-stream schedule: a process crash was seen
+  // while capturing the two-stream one, with its cause not established.
+  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusActive;
+  if (hipStreamIsCapturing(ctx->stream, &cap_st) != hipSuccess) {
+    (void)hipGetLastError();  // not left for the next launch check
+    cap_st = hipStreamCaptureStatusActive;
+  }
+  const bool two =
+      nb_total > 1 && !ctx->single_stream && cap_st == hipStreamCaptureStatusNone;
+  if (two) RBF_TRY(ensure_aux(ctx));
+  hipStream_t ms = ctx->stream;
+  hipStream_t as = two ? ctx->aux : ctx->stream;
+  const int64_t nfl = ceil_div(N, SYRK_TILE);
+  double* UtB[2] = {ws.Ut, ws.Ut2};
+  int32_t* Fl[2] = {ws.flags, ws.flags + nfl};
+  auto sizes = [&](int64_t bi, int32_t* Bc, int32_t* Bpc) {
     const int64_t s0 = bi * B;
-    const int32_t Bc = (int32_t)((M - s0) < B ? (M - s0) : B);
-    const int32_t Bpc = (int32_t)ceil_div(Bc, NB) * NB;
-    const int32_t nblk = Bpc / NB;
+    *Bc = (int32_t)((M - s0) < B ? (M - s0) : B);
+    *Bpc = (int32_t)ceil_div(*Bc, NB) * NB;
+  };
+  // regressor rows, innovation y = z - H w and touched blocks of batch bi
+  auto rows = [&](int64_t bi) -> rbf_status {
+    int32_t Bc, Bpc;
+    sizes(bi, &Bc, &Bpc);
+    const int64_t s0 = bi * B;
     k_upd_rows<<<ceil_div(Bpc, 256), 256, 0, ctx->stream>>>(
         xy + 2 * s0, z + s0, Bc, Bpc, g->d_cxy, g->d_idx, g->d_start, geom(g), rk, kmax, w,
-        vals, cols, nnz, Ut, ldu, N, ctx->d_status, ctx->index_base + bi);
+        vals, cols, nnz, UtB[bi & 1], ldu, N, ctx->d_status, ctx->index_base + bi, seq0 + bi);
     RBF_LAUNCHED(ctx, "k_upd_rows");
+    RBF_TRY(fill_zero(ctx, Fl[bi & 1], sizeof(int32_t) * nfl));
+    k_upd_flags<<<ceil_div(Bc, 256), 256, 0, ctx->stream>>>(cols, nnz, Bc, Bpc, Fl[bi & 1],
+                                                             ctx->d_status, seq0 + bi);
+    RBF_LAUNCHED(ctx, "k_upd_flags");
+    return RBF_OK;
+  };
+  // U^T = H P, S = H U + R I, L L^T = S, V^T = L^{-1} U^T (with t), w += V t
+  auto chain = [&](int64_t bi) -> rbf_status {
+    int32_t Bc, Bpc;
+    sizes(bi, &Bc, &Bpc);
+    const int32_t nblk = Bpc / NB;
+    double* Ut = UtB[bi & 1];
+    const int64_t sq = seq0 + bi;
     prof_begin(ctx, RBF_PROF_GATHER);
     dim3 gg((unsigned)ceil_div(N, 1024), (unsigned)ceil_div(Bpc, 8));
     k_upd_gather_u<<<gg, 256, 0, ctx->stream>>>(P, ldp, N, Bc, Bpc, vals, cols, nnz, Ut, ldu,
-                                                 ctx->d_status);
+                                                 ctx->d_status, sq);
     RBF_LAUNCHED(ctx, "k_upd_gather_u");
     prof_end(ctx, RBF_PROF_GATHER);
     dim3 gs((unsigned)ceil_div(Bpc, 256), (unsigned)Bpc);
     k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,
-                                         ctx->d_status);
+                                         ctx->d_status, sq);
     RBF_LAUNCHED(ctx, "k_upd_S");
     prof_begin(ctx, RBF_PROF_CHOL);
-    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi));
+    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi, sq));
     prof_end(ctx, RBF_PROF_CHOL);
     prof_begin(ctx, RBF_PROF_TRSM);
-    RBF_TRY(trsm_blocks(ctx, Ut, ldu, N + 1, nblk, Lb, Bpc, Linv, false));
+    RBF_TRY(trsm_blocks(ctx, Ut, ldu, N + 1, nblk, Lb, Bpc, Linv, false, sq));
     prof_end(ctx, RBF_PROF_TRSM);
     dim3 gw((unsigned)ceil_div(N, 256), (unsigned)ceil_div(Bc, 64));
-    k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Ut, ldu, N, Bc, wpart, ctx->d_status);
+    k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Ut, ldu, N, Bc, wpart, ctx->d_status, sq);
     RBF_LAUNCHED(ctx, "k_upd_w_part");
     k_upd_w_sum<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(w, wpart, N, (int32_t)gw.y,
-                                                           ctx->d_status);
+                                                           ctx->d_status, sq);
     RBF_LAUNCHED(ctx, "k_upd_w_sum");
-    RBF_TRY(syrk_update(ctx, P, ldp, N, Ut, ldu, Bc, gemm_prec));
+    return RBF_OK;
+  };
+  // whatever path leaves this function, `ms` ends up ordered after `as`
+  struct Join {
+    rbf_ctx* c;
+    hipStream_t m, a;
+    bool on;
+    ~Join() {
+      if (!on) return;
+      (void)hipEventRecord(c->ev_back, a);
+      (void)hipStreamWaitEvent(m, c->ev_back, 0);
+    }
+  } join{ctx, ms, as, two};
+  if (!two) {
+    for (int64_t bi = 0; bi < nb_total; ++bi) {
+      int32_t Bc, Bpc;
+      sizes(bi, &Bc, &Bpc);
+      RBF_TRY(rows(bi));
+      RBF_TRY(chain(bi));
+      RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec, nullptr, 0,
+                          seq0 + bi));
+    }
+  } else {
+    RBF_HIP(ctx, hipEventRecord(ctx->ev_fwd, ms));
+    RBF_HIP(ctx, hipStreamWaitEvent(as, ctx->ev_fwd, 0));
+  }
+  if (two) {
+    StreamSwap sw(ctx, as);
+    RBF_TRY(rows(0));
+    RBF_TRY(chain(0));
+    RBF_TRY(rows(1));
+    RBF_HIP(ctx, hipEventRecord(ctx->ev_back, as));
+  }
+  for (int64_t bi = 0; two && bi < nb_total; ++bi) {
+    int32_t Bc, Bpc;
+    sizes(bi, &Bc, &Bpc);
+    const bool more = bi + 1 < nb_total;
+    RBF_HIP(ctx, hipStreamWaitEvent(ms, ctx->ev_back, 0));
+    // part 1: tiles in the row/column blocks batch bi+1 touches (all tiles
+    // for the last batch)
+    RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec,
+                        more ? Fl[(bi + 1) & 1] : nullptr, more ? 1 : 0, seq0 + bi));
+    if (!more) break;
+    RBF_HIP(ctx, hipEventRecord(ctx->ev_fwd, ms));
+    RBF_HIP(ctx, hipStreamWaitEvent(as, ctx->ev_fwd, 0));
+    {
+      StreamSwap sw(ctx, as);
+      RBF_TRY(chain(bi + 1));
+      if (bi + 2 < nb_total) RBF_TRY(rows(bi + 2));
+      RBF_HIP(ctx, hipEventRecord(ctx->ev_back, as));
+    }
+    // part 2: the remaining tiles, concurrent with the chain above
+    RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec, Fl[(bi + 1) & 1], 2,
+                        seq0 + bi));
   }
   if (n_done) {
     int32_t h[4];

@@ -9,11 +9,19 @@ namespace rbf {
 // Points absorbed per Kalman batch when the caller passes batch = 0.
 constexpr int64_t UPDATE_DEFAULT_BATCH = 1024;
 
+// Output tile of the covariance product (rows and columns of P).
+constexpr int SYRK_TILE = 128;
+
 // P -= V V^T for V^T = Ut[0:Bc, 0:N] (row-major, leading dimension ldu);
 // lower tiles are computed and written to both triangles of P, so P stays
 // exactly symmetric. prec selects the operand precision of the product.
+// part 0 computes every tile; part 1 only the tiles (I, J) with flags[I] or
+// flags[J] set (flags per SYRK_TILE block of rows), part 2 the others, with
+// the low-precision operand copy made by part 1 and reused by part 2.
+// Launches belong to launch group seq.
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
-                       int64_t ldu, int32_t Bc, rbf_prec prec);
+                       int64_t ldu, int32_t Bc, rbf_prec prec, const int32_t* flags,
+                       int part, int64_t seq);
 
 // Device workspace of rbf_update for N centers, kmax candidates per point
 // and batches of at most Bmax points (all slots grown up front, so later
@@ -23,6 +31,8 @@ struct UpdWs {
   int32_t* cols;
   int32_t* nnz;
   double* Ut;
+  double* Ut2;     // second U^T / V^T buffer (consecutive batches alternate)
+  int32_t* flags;  // 2 x ceil(N / SYRK_TILE) touched-block flags
   double* S;
   double* Lb;
   double* Linv;
@@ -36,14 +46,16 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
 // overwritten with intermediate trailing blocks; the factor is returned as
 // its off-diagonal 64x64 blocks in Lb (n x n, leading dimension n) and the
 // inverses of its diagonal blocks in Linv ((n/64) x 64 x 64). A breakdown
-// records RBF_E_NOT_SPD with `index` in the status word.
+// records RBF_E_NOT_SPD with `index` in the status word. Launches belong to
+// launch group seq.
 rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
-                        int64_t index);
+                        int64_t index, int64_t seq);
 
 // X := L^{-1} X (trans = false) or X := L^{-T} X (trans = true) in place for
 // X with nblk*64 rows, ncols columns and leading dimension ldx, with L given
 // as by chol_blocked (Lb with leading dimension ldl, Linv).
 rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int32_t nblk,
-                       const double* Lb, int64_t ldl, const double* Linv, bool trans);
+                       const double* Lb, int64_t ldl, const double* Linv, bool trans,
+                       int64_t seq);
 
 }  // namespace rbf

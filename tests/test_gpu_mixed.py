@@ -48,10 +48,10 @@ def test_mixed_update_heights(ctx, prec, batch):
     wb, Pb = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R)
     eP = np.abs(host(P) - Pb).max() / np.abs(Pb).max()
     ef0, eg0, ew0 = _errors(s.queries, s.centers, host(w), wb, p)
-    rel, sweeps, _ = _refine(ctx, p, grid, dev(s.xy), dev(s.z), w, P)
+    rel, iters, _ = _refine(ctx, p, grid, dev(s.xy), dev(s.z), w, P)
     ef, eg, ew = _errors(s.queries, s.centers, host(w), wb, p)
     print(f"{prec} batch {batch}: P rel {eP:.2e}; recursion only: max|df| {ef0:.2e} m, "
-          f"grad rel {eg0:.2e}, w rel {ew0:.2e}; refined ({sweeps} sweeps, relres "
+          f"grad rel {eg0:.2e}, w rel {ew0:.2e}; refined ({iters} CG iterations, relres "
           f"{rel:.1e}): max|df| {ef:.2e} m, grad rel {eg:.2e}, w rel {ew:.2e}")
     assert ef <= 1e-4
     assert eg <= 1e-3
@@ -77,10 +77,10 @@ def test_mixed_update_odometry_frame(ctx, prec):
     wb = O.spd_solve(H, b)
     q = np.random.default_rng(0).uniform(0, 50, size=(5000, 2))
     ef0, eg0, ew0 = _errors(q, centers, host(w), wb, p)
-    rel, sweeps, _ = _refine(ctx, p, grid, dev(xy), dev(z), w, P)
+    rel, iters, _ = _refine(ctx, p, grid, dev(xy), dev(z), w, P)
     ef, eg, ew = _errors(q, centers, host(w), wb, p)
     print(f"{prec} odometry 2 frames: recursion only: max|df| {ef0:.2e} m, grad rel "
-          f"{eg0:.2e}, w rel {ew0:.2e}; refined ({sweeps} sweeps, relres {rel:.1e}): "
+          f"{eg0:.2e}, w rel {ew0:.2e}; refined ({iters} CG iterations, relres {rel:.1e}): "
           f"max|df| {ef:.2e} m, grad rel {eg:.2e}, w rel {ew:.2e}")
     assert ef <= 1e-4
     assert eg <= 1e-3
@@ -110,3 +110,40 @@ def test_refine_reports_and_rejects(ctx):
     assert st == 0 and 1 <= sweeps <= 3
     with pytest.raises(api.RbfError):
         ctx.refine(p, rowptr, colidx, vals, b, P, w, rtol=0.0)
+
+
+def test_mixed_bf16_eight_frames_refined_each_frame(ctx):
+    """BF16 products over eight frames with the information form accumulated
+    and w refined after every frame (the schedule of the benchmark's mixed
+    leg); the error of P grows with the frames, the refined heights must
+    not."""
+    od = synth.OdometryCase()
+    p = api.Params()
+    allxy = np.concatenate([od.ground_xy(k) for k in range(od.N_FRAMES)])
+    centers = O.select_centers(allxy, od.roi, 0.5, 0.5, 4, O.VOXEL)
+    grid = ctx.grid(p, dev(centers))
+    N = grid.N
+    w = torch.zeros(N, dtype=torch.float64, device="cuda")
+    P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
+    rowptr, colidx = ctx.gram_pattern(p, grid)
+    vals = torch.zeros(colidx.shape[0], dtype=torch.float64, device="cuda")
+    b = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ks = list(range(10, 18))
+    its = []
+    for n, k in enumerate(ks):
+        xy, z = od.ground(k)
+        xs, zs, _ = ctx.sort_points(grid, dev(xy), dev(z))
+        ctx.update(p, grid, w, P, xs, zs, batch=1024, gemm_prec="bf16")
+        ctx.assemble_gram(p, grid, xs, zs, rowptr, colidx, vals, b, add_lambda=(n == 0))
+        rel, it, _ = ctx.refine(p, rowptr, colidx, vals, b, P, w, rtol=1e-10, max_iter=60)
+        its.append(it)
+    frames = [od.ground(k) for k in ks]
+    H, bb = O.gram(np.concatenate([f[0] for f in frames]), np.concatenate([f[1] for f in frames]),
+                   centers, p.sigma, p.cutoff, 0.0, p.lam, sparse=True)
+    wb = O.spd_solve(H, bb)
+    q = np.random.default_rng(1).uniform(0, 50, size=(5000, 2))
+    ef, eg, ew = _errors(q, centers, host(w), wb, p)
+    print(f"bf16 eight frames: CG iterations per frame {its}; max|df| {ef:.2e} m, "
+          f"grad rel {eg:.2e}, w rel {ew:.2e}")
+    assert ef <= 1e-4
+    assert eg <= 1e-3

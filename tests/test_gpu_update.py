@@ -145,3 +145,43 @@ def test_update_full_size_odometry_frame(ctx):
     Pg = host(P[:, torch.as_tensor(cols, device="cuda")])
     assert np.abs(Pg - Pc).max() <= TOL_W * (p.R / p.lam)
     assert torch.equal(P, P.T)
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_update_two_streams_bitwise_equal(ctx, small, prec):
+    """The two-stream schedule (next batch's chain beside the split
+    covariance product) computes the same arithmetic in the same order."""
+    s, p, grid, wb, Pb = small
+    out = []
+    for streams in (1, 2):
+        ctx.set_update_streams(streams)
+        try:
+            w, P = _state(grid.N, p)
+            ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=128, gemm_prec=prec)
+            out.append((w, P))
+        finally:
+            ctx.set_update_streams(1)
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+
+
+def test_update_two_streams_failure_commits_earlier_batches(ctx, small):
+    """A failure in batch k+1's chain (on the second stream) must not cut
+    short batch k's covariance product running beside it."""
+    s, p, grid, wb, Pb = small
+    B = 128
+    z = s.z.copy()
+    z[5 * B + 3] = np.inf
+    ctx.set_update_streams(2)
+    try:
+        w, P = _state(grid.N, p)
+        with pytest.raises(api.RbfError) as e:
+            ctx.update(p, grid, w, P, dev(s.xy), dev(z), batch=B)
+    finally:
+        ctx.set_update_streams(1)
+    assert e.value.status == 4 and e.value.index == 5
+    w5, P5 = O.ridge_batch(s.xy[:5 * B], s.z[:5 * B], s.centers, p.sigma, p.cutoff, 0.0,
+                           p.lam, p.R)
+    assert _rel(host(w), w5) <= TOL_W
+    assert np.abs(host(P) - P5).max() <= TOL_W * np.abs(P5).max()
+    ctx.sync_status()
