@@ -3,13 +3,13 @@
 // its tile helpers).
 //
 // Right-looking over four 16-column panels. For panel c0:
-//   A. wave 0 factors the 16x16 diagonal block and forms its inverse in the
-//      same 16 steps: lane group g = lane / 4 (part p = lane % 4) holds entries
-//      4k + p of row g of the block and of column g of its inverse; in step j
-//      the groups g > j form L[g][j] (left-looking, partial dot products of
-//      the four lanes meet through two shuffles, pivots from a running
-//      remainder r_g = a_gg - sum L[g][q]^2) and the groups g <= j form
-//      inverse row j;
+//   A. wave 0 factors the 16x16 diagonal block in registers, one row per lane
+//      (lane g, g = lane % 16, holds row g); step j takes the pivot and the
+//      column entries from their lanes with DPP row broadcasts (no LDS, no
+//      barrier)
+//      and scales by the pivot's reciprocal only, the square roots coming
+//      after the 16 steps; then the same wave forms the block's inverse by
+//      forward substitution, lane c holding column c;
 //   B. the panel rows below: L_p = A_p D^{-T} (16x16x16 FP64 MFMA per wave);
 //   C. the trailing lower blocks: A_rs -= L_r L_s^T (FP64 MFMA).
 // Then the off-diagonal 16x16 blocks of the inverse by block diagonals:
@@ -20,9 +20,39 @@
 // with `index` for launch group `seq` (the factor continues with pivot 1).
 #pragma once
 
+// Value of v in lane k of each row of 16 lanes: DPP row_newbcast (gfx90a
+// and later), two 32-bit moves per double, no LDS and no scalar registers.
+template <int K>
+__device__ __forceinline__ double dpp_bcast16(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + K, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + K, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// k must fold to a constant (unrolled loops), which leaves one case.
+__device__ __forceinline__ double row_bcast16(double v, int k) {
+  switch (k) {
+    case 0: return dpp_bcast16<0>(v);
+    case 1: return dpp_bcast16<1>(v);
+    case 2: return dpp_bcast16<2>(v);
+    case 3: return dpp_bcast16<3>(v);
+    case 4: return dpp_bcast16<4>(v);
+    case 5: return dpp_bcast16<5>(v);
+    case 6: return dpp_bcast16<6>(v);
+    case 7: return dpp_bcast16<7>(v);
+    case 8: return dpp_bcast16<8>(v);
+    case 9: return dpp_bcast16<9>(v);
+    case 10: return dpp_bcast16<10>(v);
+    case 11: return dpp_bcast16<11>(v);
+    case 12: return dpp_bcast16<12>(v);
+    case 13: return dpp_bcast16<13>(v);
+    case 14: return dpp_bcast16<14>(v);
+    default: return dpp_bcast16<15>(v);
+  }
+}
+
 // 16x16 product tile on FP64 MFMA: acc += A[r0.., a0..] * B where B[k][j] is
 // B_t[b0 + j][bk0 + k] (i.e. the operand is read transposed from LDS).
-__device__ inline v4d mma16_nt(const double (*A)[LDT], int r0, int a0, const double (*Bt)[LDT],
+__device__ __forceinline__ v4d mma16_nt(const double (*A)[LDT], int r0, int a0, const double (*Bt)[LDT],
                                int b0, int bk0, v4d acc) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -34,7 +64,70 @@ __device__ inline v4d mma16_nt(const double (*A)[LDT], int r0, int a0, const dou
   return acc;
 }
 
-__device__ __noinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int32_t* status,
+// 1/p to full FP64 accuracy: v_rcp_f64 estimate and two Newton-Raphson
+// steps r <- r + r (1 - p r) (each doubles the number of correct bits).
+__device__ __forceinline__ double rcp_nr(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return r;
+}
+
+// Phase A for the diagonal block at (c0, c0): T gets L (zero above the
+// diagonal), Ti the block's inverse (zero above); returns false if a pivot
+// was not positive and finite. Wave 0 only.
+// Step j works on the unscaled column c (c_g = a[g][j], pivot p_j = c_j):
+// a[g][k] -= c_g c_k / p_j for j < k, so the square roots are off the
+// dependent chain; afterwards L[g][j] = c_g / sqrt(p_j).
+__device__ __forceinline__ bool chol16_regs(double (*T)[LDT], double (*Ti)[LDT], int c0) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane & 15;
+  double a[16], piv[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) a[k] = T[c0 + g][c0 + k];
+  int nbad = 0;  // counted without branches: the 16 steps stay one block
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double pj = row_bcast16(a[j], j);
+    const int good = (int)(pj > 0.0) & (int)(pj < INFINITY);
+    nbad += 1 - good;
+    piv[j] = good ? pj : 1.0;
+    const double t = a[j] * rcp_nr(piv[j]);
+    // entries above the diagonal (lanes g < k) receive unused values
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) a[k] -= t * row_bcast16(a[j], k);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  double inv[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double d = sqrt(piv[j]);
+    inv[j] = 1.0 / d;
+    a[j] = (g == j) ? d : a[j] * inv[j];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // inverse by forward substitution: lane g computes column g,
+  // x_j = (delta_jg - sum_{q<j} L_jq x_q) / L_jj for j >= g
+  double x[16];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    double s = (g == jj) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < jj; ++q) s -= row_bcast16(a[q], jj) * x[q];
+    x[jj] = (jj >= g) ? s * inv[jj] : 0.0;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  if (lane < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      T[c0 + g][c0 + k] = (k <= g) ? a[k] : 0.0;
+      Ti[c0 + k][c0 + g] = x[k];
+    }
+  }
+  return nbad == 0;
+}
+
+__device__ __forceinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int32_t* status,
                                     int64_t index, int64_t seq) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int bad;
@@ -42,70 +135,11 @@ __device__ __noinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int32_t
   for (int e = tid; e < NB * NB; e += 256) Ti[e >> 6][e & 63] = 0.0;
   __syncthreads();
   const bool w0 = wave == 0;
-  const int g = lane >> 2, p = lane & 3;
   for (int c0 = 0; c0 < NB; c0 += 16) {
-    // ---- A: 16x16 diagonal block and its inverse (wave 0)
-    double a[4], x[4], r = 0.0;
+    // ---- A: 16x16 diagonal block and its inverse (wave 0, registers)
     if (w0) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        a[k] = T[c0 + g][c0 + 4 * k + p];
-        x[k] = 0.0;
-      }
-      r = T[c0 + g][c0 + g];
-      if (g == 0 && p == 0) {
-        const bool ok = r > 0.0 && isfinite(r);
-        if (!ok) bad = 1;
-        T[c0][c0] = ok ? sqrt(r) : 1.0;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      if (w0) {
-        const double ljj = T[c0 + j][c0 + j];
-        if (g > j) {
-          double s = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int q = 4 * k + p;
-            if (q < j) s += a[k] * T[c0 + j][c0 + q];
-          }
-          s += __shfl_xor(s, 1, 64);
-          s += __shfl_xor(s, 2, 64);
-          const double l = (T[c0 + g][c0 + j] - s) / ljj;
-          if (p == (j & 3)) {
-            a[j >> 2] = l;
-            T[c0 + g][c0 + j] = l;
-          }
-          r -= l * l;
-          if (g == j + 1 && p == 0) {
-            const bool ok = r > 0.0 && isfinite(r);
-            if (!ok) bad = 1;
-            T[c0 + g][c0 + g] = ok ? sqrt(r) : 1.0;
-          }
-        } else {
-          double s = 0.0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int q = 4 * k + p;
-            if (q >= g && q < j) s += T[c0 + j][c0 + q] * x[k];
-          }
-          s += __shfl_xor(s, 1, 64);
-          s += __shfl_xor(s, 2, 64);
-          const double v = ((g == j ? 1.0 : 0.0) - s) / ljj;
-          if (p == (j & 3)) x[j >> 2] = v;
-        }
-      }
-      __syncthreads();
-    }
-    if (w0) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int q = 4 * k + p;
-        Ti[c0 + q][c0 + g] = (q >= g) ? x[k] : 0.0;
-        if (q > g) T[c0 + g][c0 + q] = 0.0;
-      }
+      const bool ok = chol16_regs(T, Ti, c0);
+      if (lane == 0 && !ok) bad = 1;
     }
     __syncthreads();
     const int nrb = (NB - c0 - 16) / 16;  // row blocks below the panel
