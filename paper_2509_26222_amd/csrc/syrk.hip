@@ -41,22 +41,40 @@ __device__ inline int64_t xcd_tile(int64_t per_xcd) {
   return (bid & 7) * per_xcd + (bid >> 3);
 }
 
-// Load 8 consecutive doubles of row r of V^T starting at column c (zero
-// outside [0, N) x [0, K)).
-__device__ inline void load8(const double* __restrict__ Ut, int64_t ldu, int64_t N, int r, int K,
-                             int64_t c, double v[8]) {
-  if (r < K && c + 7 < N) {
-    const double2* p = reinterpret_cast<const double2*>(Ut + (int64_t)r * ldu + c);
+// Stage loader of the FP64 product: the 16 x 128 panel slice (rows r0.. of
+// V^T, columns c0..) as 4 double2 per thread; element pair i*256 + tid sits
+// at row (i*256 + tid) / 64, column 2 ((i*256 + tid) % 64), so one wave
+// reads one 1 KB row run and writes it to LDS with 16-byte stores that touch
+// every bank once (zero outside [0, N) x [0, K)).
+__device__ inline void load_stage(const double* __restrict__ Ut, int64_t ldu, int64_t N, int r0,
+                                  int K, int64_t c0, double2 v[4]) {
+  const int tid = threadIdx.x;
+  if (r0 + 16 <= K && c0 + 128 <= N) {  // whole slice inside: no per-load tests
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double2 q = p[u];
-      v[2 * u] = q.x;
-      v[2 * u + 1] = q.y;
+    for (int i = 0; i < 4; ++i) {
+      const int e = i * 256 + tid;
+      v[i] = *reinterpret_cast<const double2*>(Ut + (int64_t)(r0 + (e >> 6)) * ldu + c0 +
+                                               2 * (e & 63));
     }
-  } else {
+    return;
+  }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      v[u] = (r < K && c + u < N) ? Ut[(int64_t)r * ldu + c + u] : 0.0;
+  for (int i = 0; i < 4; ++i) {
+    const int e = i * 256 + tid;
+    const int r = r0 + (e >> 6);
+    const int64_t c = c0 + 2 * (e & 63);
+    v[i].x = (r < K && c < N) ? Ut[(int64_t)r * ldu + c] : 0.0;
+    v[i].y = (r < K && c + 1 < N) ? Ut[(int64_t)r * ldu + c + 1] : 0.0;
+  }
+}
+
+template <int LD>
+__device__ inline void store_stage(double (*X)[LD], const double2 v[4]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = i * 256 + tid;
+    *reinterpret_cast<double2*>(&X[e >> 6][2 * (e & 63)]) = v[i];
   }
 }
 
@@ -78,28 +96,23 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int
   __shared__ double Bs[2][SKC][SLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int lr = tid >> 4, lc = (tid & 15) * 8;  // loader: row, first column
   v4d acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
   const int nch = (K + SKC - 1) / SKC;
-  double ra[8], rb[8];
-  load8(Ut, ldu, N, lr, K, I0 + lc, ra);
-  load8(Ut, ldu, N, lr, K, J0 + lc, rb);
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    As[0][lr][lc + u] = ra[u];
-    Bs[0][lr][lc + u] = rb[u];
-  }
+  double2 ra[4], rb[4];
+  load_stage(Ut, ldu, N, 0, K, I0, ra);
+  load_stage(Ut, ldu, N, 0, K, J0, rb);
+  store_stage<SLD>(As[0], ra);
+  store_stage<SLD>(Bs[0], rb);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nch) {
-      const int r = (ch + 1) * SKC + lr;
-      load8(Ut, ldu, N, r, K, I0 + lc, ra);
-      load8(Ut, ldu, N, r, K, J0 + lc, rb);
+      load_stage(Ut, ldu, N, (ch + 1) * SKC, K, I0, ra);
+      load_stage(Ut, ldu, N, (ch + 1) * SKC, K, J0, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < SKC; kk += 4) {
@@ -117,11 +130,8 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int
           acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
     if (ch + 1 < nch) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        As[buf ^ 1][lr][lc + u] = ra[u];
-        Bs[buf ^ 1][lr][lc + u] = rb[u];
-      }
+      store_stage<SLD>(As[buf ^ 1], ra);
+      store_stage<SLD>(Bs[buf ^ 1], rb);
     }
     __syncthreads();
   }
