@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--frames", type=int, default=4, help="distinct frames generated")
     ap.add_argument("--eval-reps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--patches", type=int, default=32,
+    ap.add_argument("--patches", type=int, default=256,
                     help="patches in the batched-form leg (0 = skip; 256 = full workload)")
-    ap.add_argument("--tune", action="store_true", help="autotune the batched plan")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched leg with 4 branches and batch 1024 instead of autotuning")
     ap.add_argument("--streams", type=int, default=1, choices=(1, 2),
                     help="schedule of the update (2: next batch's chain overlaps the "
                          "covariance product on a second stream)")
@@ -380,7 +381,8 @@ def main():
     if args.patches > 0:
         del P, frames
         torch.cuda.empty_cache()
-        out["batched"] = batched_leg(ctx, api, synth, args.patches, args.tune)
+        log(f"batched leg: {args.patches} patches ...")
+        out["batched"] = batched_leg(ctx, api, synth, args.patches, not args.no_tune)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(od, centers.cpu().numpy(), p)

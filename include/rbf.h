@@ -94,6 +94,12 @@ rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream);
  * the two streams contend for CUs and the two-stream schedule measured
  * slower.) Under stream capture rbf_update always uses one stream. */
 rbf_status rbf_ctx_set_update_streams(rbf_ctx* ctx, int32_t streams);
+/* Evaluation mode of rbf_eval on this context: on = 0 (the default) reads
+ * each point's candidates from the bin-sorted center table; on != 0 groups
+ * query sets of 2048 points or more by bin (counting sort) and stages each
+ * bin's candidate centers in LDS for its points. Results agree to rounding
+ * (the candidates are summed in another order). */
+rbf_status rbf_ctx_set_eval_binned(rbf_ctx* ctx, int32_t on);
 /* Synchronise the stream, return the first device-side error recorded
  * since the last call (RBF_OK if none) and clear it. */
 rbf_status rbf_sync_status(rbf_ctx* ctx);

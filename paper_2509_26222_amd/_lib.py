@@ -45,6 +45,7 @@ SIGNATURES = {
     "rbf_ctx_destroy": (C.c_int, [vp]),
     "rbf_ctx_set_stream": (C.c_int, [vp, vp]),
     "rbf_ctx_set_update_streams": (C.c_int, [vp, i32]),
+    "rbf_ctx_set_eval_binned": (C.c_int, [vp, i32]),
     "rbf_sync_status": (C.c_int, [vp]),
     "rbf_last_error_index": (i64, [vp]),
     "rbf_last_error": (C.c_char_p, [vp]),

@@ -242,6 +242,12 @@ class Context:
         self._check(self.lib.rbf_ctx_set_update_streams(self.h, streams),
                     "rbf_ctx_set_update_streams")
 
+    def set_eval_binned(self, on: bool):
+        """eval(): group large query sets by bin and stage candidates in LDS
+        (off by default; slower on points in arbitrary order)."""
+        self._check(self.lib.rbf_ctx_set_eval_binned(self.h, int(bool(on))),
+                    "rbf_ctx_set_eval_binned")
+
     def refine(self, params: Params, rowptr, colidx, vals, b, P: torch.Tensor,
                w: torch.Tensor, rtol: float = 1e-12, max_iter: int = 20, check=True):
         """FP64 refinement of w against calH = (rowptr, colidx, vals), b with

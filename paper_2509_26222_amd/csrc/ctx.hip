@@ -309,6 +309,12 @@ rbf_status rbf_ctx_set_update_streams(rbf_ctx* ctx, int32_t streams) {
   return RBF_OK;
 }
 
+rbf_status rbf_ctx_set_eval_binned(rbf_ctx* ctx, int32_t on) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  ctx->eval_binned = on != 0;
+  return RBF_OK;
+}
+
 rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream) {
   if (!ctx) return RBF_E_INVALID_ARG;
   ctx->stream = (hipStream_t)hip_stream;

@@ -7,12 +7,15 @@
 // J = [(p x R^T g)^T, g^T], g = (-f_x, -f_y, 1) (eqs. manifold_derivative,
 // manifold_grad_2, right perturbation, body-frame point).
 //
-// A point's candidates are the centers of its 3x3 bin neighbourhood, read as
-// three contiguous runs of a packed, bin-sorted table (x, y, w) that stays
+// A point's candidates are the centers of its 3x3 bin neighbourhood: three
+// contiguous runs of a packed, bin-sorted table (x, y, w) that stays
 // resident in L2. The forward kernel gives each point four lanes that take
-// every fourth candidate and combine their partial sums with lane shuffles
-// (four times the waves to hide the table's load latency, a quarter of the
-// loop); the adjoint keeps one lane per point.
+// every fourth candidate and combine their partial sums with lane shuffles;
+// outputs are written in point order. A binned mode (per context, off by
+// default) groups the points by bin with a counting sort and gives each bin
+// a workgroup that stages the bin's candidates in LDS once; on points in
+// arbitrary order its sort atomics and scattered output writes cost more
+// than the table reads they save. The adjoint keeps one lane per point.
 #include <cmath>
 
 #include "internal.hpp"
@@ -88,19 +91,10 @@ __device__ inline void accumulate(T x, T y, const typename Vec4<T>::type* __rest
   }
 }
 
+// World coordinates of point i (POSE: xi = R p + t from the body point p).
 template <typename T, bool POSE>
-__global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t Q,
-                                              const typename Vec4<T>::type* __restrict__ tab,
-                                              const int32_t* __restrict__ start, GridGeom g,
-                                              EvalK<T> k, T* __restrict__ f_out,
-                                              T* __restrict__ grad_out, T* __restrict__ r_out,
-                                              T* __restrict__ jac_out) {
-  // LPP lanes per point: they share the point, split its candidates and
-  // combine the partial sums with lane shuffles
-  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPP;
-  const int part = threadIdx.x % LPP;
-  if (i >= Q) return;  // the LPP lanes of a point exit together
-  T x, y, zw, px = 0, py = 0, pz = 0;
+__device__ inline void world_of(const T* __restrict__ pts, int64_t i, const EvalK<T>& k, T& x,
+                                T& y, T& zw, T& px, T& py, T& pz) {
   if (POSE) {
     px = pts[3 * i];
     py = pts[3 * i + 1];
@@ -111,10 +105,17 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
   } else {
     x = pts[2 * i];
     y = pts[2 * i + 1];
-    zw = 0;
+    zw = px = py = pz = (T)0;
   }
-  T f, sx, sy;
-  accumulate<T>(x, y, tab, start, g, k, part, f, sx, sy);
+}
+
+// Combine the LPP lanes' partial sums and write point i's outputs (the
+// lanes of a point share the stores).
+template <typename T, bool POSE>
+__device__ inline void finish_point(int64_t i, int part, T f, T sx, T sy, T zw, T px, T py, T pz,
+                                    const EvalK<T>& k, T* __restrict__ f_out,
+                                    T* __restrict__ grad_out, T* __restrict__ r_out,
+                                    T* __restrict__ jac_out) {
 #pragma unroll
   for (int m = 1; m < LPP; m <<= 1) {
     f += __shfl_xor(f, m, 64);
@@ -122,7 +123,6 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
     sy += __shfl_xor(sy, m, 64);
   }
   const T fx = -sx * k.inv_s2, fy = -sy * k.inv_s2;
-  // the lanes of a point share the stores
   if (part == 0) f_out[i] = f;
   if (grad_out && part == 1) {
     grad_out[2 * i] = fx;
@@ -144,6 +144,114 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
       J[4] = g1;
       J[5] = g2;
     }
+  }
+}
+
+template <typename T, bool POSE>
+__global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t Q,
+                                              const typename Vec4<T>::type* __restrict__ tab,
+                                              const int32_t* __restrict__ start, GridGeom g,
+                                              EvalK<T> k, T* __restrict__ f_out,
+                                              T* __restrict__ grad_out, T* __restrict__ r_out,
+                                              T* __restrict__ jac_out) {
+  // LPP lanes per point: they share the point, split its candidates and
+  // combine the partial sums with lane shuffles
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPP;
+  const int part = threadIdx.x % LPP;
+  if (i >= Q) return;  // the LPP lanes of a point exit together
+  T x, y, zw, px, py, pz;
+  world_of<T, POSE>(pts, i, k, x, y, zw, px, py, pz);
+  T f, sx, sy;
+  accumulate<T>(x, y, tab, start, g, k, part, f, sx, sy);
+  finish_point<T, POSE>(i, part, f, sx, sy, zw, px, py, pz, k, f_out, grad_out, r_out, jac_out);
+}
+
+// ---- binned evaluation
+
+// Bin key of each point (the far bucket nbins if its 3x3 neighbourhood
+// misses the grid, non-finite coordinates included) and the bin counts.
+// A point just outside the grid takes the clamped bin: that bin's
+// neighbourhood contains the point's own (clipped) neighbourhood, and the
+// extra centers lie beyond the bin side, which exceeds the cutoff.
+template <typename T, bool POSE>
+__global__ void __launch_bounds__(256) k_eval_keys(const T* __restrict__ pts, int64_t Q,
+                                                   GridGeom g, EvalK<T> k, int32_t nbins,
+                                                   int32_t* __restrict__ keys,
+                                                   int32_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= Q) return;
+  T x, y, zw, px, py, pz;
+  world_of<T, POSE>(pts, i, k, x, y, zw, px, py, pz);
+  int key = nbins, lo, hi;
+  if (bin_range((double)x, g.x0, g.inv_h, g.nbx, &lo, &hi) &&
+      bin_range((double)y, g.y0, g.inv_h, g.nby, &lo, &hi))
+    key = bin_of((double)x, g.x0, g.inv_h, g.nbx) +
+          g.nbx * bin_of((double)y, g.y0, g.inv_h, g.nby);
+  keys[i] = key;
+  atomicAdd(&counts[key], 1);
+}
+
+// perm[start[key] + rank] = i, rank taken from a per-bin cursor.
+__global__ void __launch_bounds__(256) k_eval_scatter(const int32_t* __restrict__ keys,
+                                                      int64_t Q,
+                                                      const int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ cursor,
+                                                      int32_t* __restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= Q) return;
+  const int key = keys[i];
+  perm[start[key] + atomicAdd(&cursor[key], 1)] = (int32_t)i;
+}
+
+// One workgroup per bin (the last one for the far bucket): the bin's 3x3
+// neighbourhood (at most maxc centers) is staged in LDS, then its points
+// are evaluated LPP lanes each.
+template <typename T, bool POSE>
+__global__ void __launch_bounds__(256) k_eval_tiles(
+    const T* __restrict__ pts, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ pstart, int32_t nbins,
+    const typename Vec4<T>::type* __restrict__ tab, const int32_t* __restrict__ cstart,
+    GridGeom g, EvalK<T> k, T* __restrict__ f_out, T* __restrict__ grad_out,
+    T* __restrict__ r_out, T* __restrict__ jac_out) {
+  using V = typename Vec4<T>::type;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  V* cand = reinterpret_cast<V*>(smem);
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int p0 = pstart[b], p1 = pstart[b + 1];
+  if (p0 == p1) return;
+  int nc = 0;
+  if (b < nbins) {
+    const int by = b / g.nbx, bx = b - by * g.nbx;
+    const int bx0 = bx > 0 ? bx - 1 : 0, bx1 = bx + 1 < g.nbx ? bx + 1 : g.nbx - 1;
+    const int by0 = by > 0 ? by - 1 : 0, by1 = by + 1 < g.nby ? by + 1 : g.nby - 1;
+    for (int r = by0; r <= by1; ++r) {
+      const int s0 = cstart[r * g.nbx + bx0], s1 = cstart[r * g.nbx + bx1 + 1];
+      for (int s = s0 + tid; s < s1; s += 256) cand[nc + (s - s0)] = tab[s];
+      nc += s1 - s0;
+    }
+  }
+  __syncthreads();
+  const int part = tid % LPP;
+  for (int base = p0; base < p1; base += 256 / LPP) {
+    const int pi = base + tid / LPP;
+    if (pi >= p1) break;  // the LPP lanes of a point leave together
+    const int64_t i = perm[pi];
+    T x, y, zw, px, py, pz;
+    world_of<T, POSE>(pts, i, k, x, y, zw, px, py, pz);
+    T f = (T)0, sx = (T)0, sy = (T)0;
+    for (int s = part; s < nc; s += LPP) {
+      const V c = cand[s];
+      const T dx = x - c.x, dy = y - c.y;
+      const T d2 = dx * dx + dy * dy;
+      if (d2 <= k.rc2) {
+        const T we = c.z * kexp_eval(d2 * k.kexp);
+        f += we;
+        sx += we * dx;
+        sy += we * dy;
+      }
+    }
+    finish_point<T, POSE>(i, part, f, sx, sy, zw, px, py, pz, k, f_out, grad_out, r_out,
+                          jac_out);
   }
 }
 
@@ -287,6 +395,20 @@ static rbf_status pack(rbf_ctx* ctx, const rbf_grid* g, const double* w,
   return RBF_OK;
 }
 
+rbf_status eval_workspace(rbf_ctx* ctx, const rbf_grid* g, int64_t Q, EvalWs* ws) {
+  rbf_status st;
+  const int64_t nb = (int64_t)g->nbx * g->nby + 2;
+  ws->keys = (int32_t*)ws_get(ctx, WS_SORT0, sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1), &st);
+  if (!ws->keys) return st;
+  ws->perm = (int32_t*)ws_get(ctx, WS_SORT1, sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1), &st);
+  if (!ws->perm) return st;
+  ws->counts = (int32_t*)ws_get(ctx, WS_SORT2, sizeof(int32_t) * 2 * (size_t)nb, &st);
+  if (!ws->counts) return st;
+  ws->cursor = ws->counts + nb;
+  if (!ws_get(ctx, WS_TMP2, sizeof(double4) * (size_t)(g->N > 0 ? g->N : 1), &st)) return st;
+  return RBF_OK;
+}
+
 template <typename T>
 static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
                          const void* pts, int64_t Q, int32_t dim, const double* pose,
@@ -294,6 +416,37 @@ static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, c
   typename Vec4<T>::type* tab;
   RBF_TRY(pack<T>(ctx, g, w, &tab));
   EvalK<T> k = make_consts<T>(p, pose, z_off);
+  const size_t lds = sizeof(typename Vec4<T>::type) * (size_t)(g->max_cand > 0 ? g->max_cand : 1);
+  if (ctx->eval_binned && Q >= EVAL_BINNED_MIN && lds <= EVAL_LDS_MAX && Q < INT32_MAX) {
+    const int32_t nbins = g->nbx * g->nby;
+    EvalWs ws;
+    RBF_TRY(eval_workspace(ctx, g, Q, &ws));
+    RBF_TRY(fill_zero(ctx, ws.counts, sizeof(int32_t) * 2 * (size_t)(nbins + 2)));
+    const unsigned gq = (unsigned)ceil_div(Q, 256);
+    prof_begin(ctx, RBF_PROF_EVAL);
+    if (dim == 3)
+      k_eval_keys<T, true><<<gq, 256, 0, ctx->stream>>>((const T*)pts, Q, geom(g), k, nbins,
+                                                         ws.keys, ws.counts);
+    else
+      k_eval_keys<T, false><<<gq, 256, 0, ctx->stream>>>((const T*)pts, Q, geom(g), k, nbins,
+                                                          ws.keys, ws.counts);
+    RBF_LAUNCHED(ctx, "k_eval_keys");
+    k_scan_excl_i32<<<1, 1024, 0, ctx->stream>>>(ws.counts, nbins + 1);
+    RBF_LAUNCHED(ctx, "k_scan_excl_i32");
+    k_eval_scatter<<<gq, 256, 0, ctx->stream>>>(ws.keys, Q, ws.counts, ws.cursor, ws.perm);
+    RBF_LAUNCHED(ctx, "k_eval_scatter");
+    if (dim == 3)
+      k_eval_tiles<T, true><<<nbins + 1, 256, lds, ctx->stream>>>(
+          (const T*)pts, ws.perm, ws.counts, nbins, tab, g->d_start, geom(g), k, (T*)f,
+          (T*)grad, (T*)resid, (T*)jac);
+    else
+      k_eval_tiles<T, false><<<nbins + 1, 256, lds, ctx->stream>>>(
+          (const T*)pts, ws.perm, ws.counts, nbins, tab, g->d_start, geom(g), k, (T*)f,
+          (T*)grad, nullptr, nullptr);
+    RBF_LAUNCHED(ctx, "k_eval_tiles");
+    prof_end(ctx, RBF_PROF_EVAL);
+    return RBF_OK;
+  }
   const int64_t blocks = ceil_div(Q * LPP, 256);
   prof_begin(ctx, RBF_PROF_EVAL);
   if (dim == 3)

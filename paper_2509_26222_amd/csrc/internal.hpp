@@ -58,6 +58,9 @@ struct rbf_ctx {
   // rbf_update keeps to one stream (set for the batched form's branches,
   // whose graph capture does not take the two-stream schedule)
   int32_t single_stream;
+  // rbf_eval groups the points by bin and stages candidates in LDS
+  // (rbf_ctx_set_eval_binned); off by default
+  int32_t eval_binned;
   void* ws[rbf::WS_COUNT];
   size_t ws_bytes[rbf::WS_COUNT];
   int64_t last_index;
@@ -167,6 +170,22 @@ void prof_end(rbf_ctx* ctx, int kind);
 // Zero device memory with a kernel (no memset node, so the call is safe
 // inside stream capture).
 rbf_status fill_zero(rbf_ctx* ctx, void* p, size_t bytes);
+
+// Workspace of the binned evaluation of Q points on grid g (bin keys, the
+// permutation, bin offsets and cursors, and the packed center table); the
+// batched plan reserves it before capture.
+struct EvalWs {
+  int32_t* keys;
+  int32_t* perm;
+  int32_t* counts;  // nbins + 2 offsets (scanned in place)
+  int32_t* cursor;  // nbins + 2 per-bin ranks
+};
+rbf_status eval_workspace(rbf_ctx* ctx, const rbf_grid* g, int64_t Q, EvalWs* ws);
+// With the context's binned mode on, query sets of at least this size use
+// the binned evaluation (if the largest neighbourhood fits in EVAL_LDS_MAX
+// bytes of LDS).
+constexpr int64_t EVAL_BINNED_MIN = 2048;
+constexpr size_t EVAL_LDS_MAX = 48 * 1024;
 
 // Create the context's second stream and its two events if not yet done.
 rbf_status ensure_aux(rbf_ctx* ctx);
