@@ -231,8 +231,46 @@ __device__ inline void epilogue_f32acc(double* __restrict__ P, int64_t ldp, int6
       }
 }
 
-constexpr int FKC = 32;  // rows of V^T per stage (FP32)
-constexpr int FLD = ST + 4;
+constexpr int FKC = 32;      // rows of V^T per stage (FP32)
+constexpr int FLD = ST + 4;  // LDS pitch (floats)
+
+// Stage loader of the FP32 product: the 32 x 128 slice as 4 float4 per
+// thread; float4 i*256 + tid sits at row (i*256 + tid) / 32, column
+// 4 ((i*256 + tid) % 32), so half a wave reads one 512-byte row run and
+// writes it with 16-byte stores (zero outside [0, N) x [0, K)).
+__device__ inline void load_stage_f32(const float* __restrict__ Uf, int64_t ldu, int64_t N,
+                                      int r0, int K, int64_t c0, float4 v[4]) {
+  const int tid = threadIdx.x;
+  if (r0 + FKC <= K && c0 + 128 <= N) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = i * 256 + tid;
+      v[i] = *reinterpret_cast<const float4*>(Uf + (int64_t)(r0 + (e >> 5)) * ldu + c0 +
+                                              4 * (e & 31));
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = i * 256 + tid;
+    const int r = r0 + (e >> 5);
+    const int64_t c = c0 + 4 * (e & 31);
+    const float* src = Uf + (int64_t)r * ldu + c;
+    v[i].x = (r < K && c < N) ? src[0] : 0.f;
+    v[i].y = (r < K && c + 1 < N) ? src[1] : 0.f;
+    v[i].z = (r < K && c + 2 < N) ? src[2] : 0.f;
+    v[i].w = (r < K && c + 3 < N) ? src[3] : 0.f;
+  }
+}
+
+__device__ inline void store_stage_f32(float (*X)[FLD], const float4 v[4]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = i * 256 + tid;
+    *reinterpret_cast<float4*>(&X[e >> 5][4 * (e & 31)]) = v[i];
+  }
+}
 
 __global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
                                                      int64_t N, const float* __restrict__ Uf,
@@ -248,45 +286,36 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int
   tile_of(t, &I, &J);
   if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
-  __shared__ float As[FKC][FLD];
-  __shared__ float Bs[FKC][FLD];
+  __shared__ __attribute__((aligned(16))) float As[2][FKC][FLD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][FKC][FLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int lr = tid >> 3, lc = (tid & 7) * 16;  // loader: 32 rows x 8 x 16 floats
   v4f acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
   const int nch = (K + FKC - 1) / FKC;
-  float ra[16], rb[16];
-  auto load = [&](int ch) {
-    const int r = ch * FKC + lr;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int64_t ca = I0 + lc + u, cb = J0 + lc + u;
-      ra[u] = (r < K && ca < N) ? Uf[(int64_t)r * ldu + ca] : 0.f;
-      rb[u] = (r < K && cb < N) ? Uf[(int64_t)r * ldu + cb] : 0.f;
-    }
-  };
-  load(0);
+  float4 ra[4], rb[4];
+  load_stage_f32(Uf, ldu, N, 0, K, I0, ra);
+  load_stage_f32(Uf, ldu, N, 0, K, J0, rb);
+  store_stage_f32(As[0], ra);
+  store_stage_f32(Bs[0], rb);
+  __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      As[lr][lc + u] = ra[u];
-      Bs[lr][lc + u] = rb[u];
+    const int buf = ch & 1;
+    if (ch + 1 < nch) {
+      load_stage_f32(Uf, ldu, N, (ch + 1) * FKC, K, I0, ra);
+      load_stage_f32(Uf, ldu, N, (ch + 1) * FKC, K, J0, rb);
     }
-    __syncthreads();
-    if (ch + 1 < nch) load(ch + 1);
 #pragma unroll
     for (int kk = 0; kk < FKC; kk += 4) {
       const int kr = kk + (lane >> 4);
       float a[4], b[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        a[q] = As[kr][wm * 64 + q * 16 + (lane & 15)];
-        b[q] = Bs[kr][wn * 64 + q * 16 + (lane & 15)];
+        a[q] = As[buf][kr][wm * 64 + q * 16 + (lane & 15)];
+        b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
       }
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
@@ -294,6 +323,11 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int
         for (int ni = 0; ni < 4; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
+    if (ch + 1 < nch) {
+      store_stage_f32(As[buf ^ 1], ra);
+      store_stage_f32(Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
   }
   epilogue_f32acc(P, ldp, N, I0, J0, I == J, acc);
 }
