@@ -31,9 +31,9 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # HBM bytes of one k_syrk_f64 launch (all lower tiles) at N = 10,000, batch 1024,
 # from rocprofv3 FETCH_SIZE (x2.0, the copy-kernel calibration) + WRITE_SIZE (x1.0);
-# summary in profiles/k_syrk_f64_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid
+# summary in profiles/k_syrk_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid
 # only for that kernel version and shape (None otherwise).
-SYRK_F64_TRAFFIC = {(10000, 1024): 3.1872e9 + 0.8047e9}
+SYRK_F64_TRAFFIC = {(10000, 1024): 3.5606e9 + 0.8091e9}
 
 
 def parse():

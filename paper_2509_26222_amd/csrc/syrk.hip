@@ -335,6 +335,32 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int
 constexpr int BKC = 32;      // k per stage (one 16x16x32 MFMA)
 constexpr int BLD = BKC + 8; // LDS pitch in bf16 (80 bytes)
 
+// One thread's share of a BF16 stage: 2 x 16 bytes of rows ga (I panel) and
+// gb (J panel) of V_hi and V_lo from k index k0 (zero beyond N). Inlined so
+// that the four staging arrays stay in registers.
+__device__ __forceinline__ void load_bf16_stage(const __bf16* __restrict__ Vhi,
+                                                const __bf16* __restrict__ Vlo, int32_t Kp,
+                                                int64_t N, int64_t ga, int64_t gb, int64_t k0,
+                                                uint4 (&rah)[2], uint4 (&ral)[2],
+                                                uint4 (&rbh)[2], uint4 (&rbl)[2]) {
+  // rows beyond N read row N-1 (in bounds) and are zeroed by a mask, so no
+  // pointer is selected (a select between a global and a local address made
+  // the loads generic and put a zero constant on the stack)
+  const int64_t ra = ga < N ? ga : N - 1, rb = gb < N ? gb : N - 1;
+  const uint32_t ma = ga < N ? 0xffffffffu : 0u, mb = gb < N ? 0xffffffffu : 0u;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    rah[u] = *reinterpret_cast<const uint4*>(Vhi + ra * Kp + k0 + 8 * u);
+    ral[u] = *reinterpret_cast<const uint4*>(Vlo + ra * Kp + k0 + 8 * u);
+    rbh[u] = *reinterpret_cast<const uint4*>(Vhi + rb * Kp + k0 + 8 * u);
+    rbl[u] = *reinterpret_cast<const uint4*>(Vlo + rb * Kp + k0 + 8 * u);
+    rah[u].x &= ma; rah[u].y &= ma; rah[u].z &= ma; rah[u].w &= ma;
+    ral[u].x &= ma; ral[u].y &= ma; ral[u].z &= ma; ral[u].w &= ma;
+    rbh[u].x &= mb; rbh[u].y &= mb; rbh[u].z &= mb; rbh[u].w &= mb;
+    rbl[u].x &= mb; rbl[u].y &= mb; rbl[u].z &= mb; rbl[u].w &= mb;
+  }
+}
+
 __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, int64_t ldp,
                                                         int64_t N, const __bf16* __restrict__ Vhi,
                                                         const __bf16* __restrict__ Vlo,
@@ -365,19 +391,7 @@ __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, 
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
   const int nch = Kp / BKC;
   uint4 rah[2], ral[2], rbh[2], rbl[2];
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-  auto load = [&](int ch) {
-    const int64_t k0 = (int64_t)ch * BKC + lq;
-    const int64_t ga = I0 + lrow, gb = J0 + lrow;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      rah[u] = ga < N ? *reinterpret_cast<const uint4*>(Vhi + ga * Kp + k0 + 8 * u) : z4;
-      ral[u] = ga < N ? *reinterpret_cast<const uint4*>(Vlo + ga * Kp + k0 + 8 * u) : z4;
-      rbh[u] = gb < N ? *reinterpret_cast<const uint4*>(Vhi + gb * Kp + k0 + 8 * u) : z4;
-      rbl[u] = gb < N ? *reinterpret_cast<const uint4*>(Vlo + gb * Kp + k0 + 8 * u) : z4;
-    }
-  };
-  load(0);
+  load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)lq, rah, ral, rbh, rbl);
   for (int ch = 0; ch < nch; ++ch) {
     __syncthreads();
 #pragma unroll
@@ -388,7 +402,9 @@ __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, 
       *reinterpret_cast<uint4*>(&Bl[lrow][lq + 8 * u]) = rbl[u];
     }
     __syncthreads();
-    if (ch + 1 < nch) load(ch + 1);
+    if (ch + 1 < nch)
+      load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)(ch + 1) * BKC + lq, rah,
+                      ral, rbh, rbl);
     const int kq = 8 * (lane >> 4);
     v8bf ah[4], al[4], bh[4], bl[4];
 #pragma unroll
