@@ -46,21 +46,22 @@ __device__ inline int64_t xcd_tile(int64_t per_xcd) {
 // at row (i*256 + tid) / 64, column 2 ((i*256 + tid) % 64), so one wave
 // reads one 1 KB row run and writes it to LDS with 16-byte stores that touch
 // every bank once (zero outside [0, N) x [0, K)).
+template <int NT>
 __device__ inline void load_stage(const double* __restrict__ Ut, int64_t ldu, int64_t N, int r0,
-                                  int K, int64_t c0, double2 v[4]) {
+                                  int K, int64_t c0, double2 v[1024 / NT]) {
   const int tid = threadIdx.x;
   if (r0 + 16 <= K && c0 + 128 <= N) {  // whole slice inside: no per-load tests
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = i * 256 + tid;
+    for (int i = 0; i < 1024 / NT; ++i) {
+      const int e = i * NT + tid;
       v[i] = *reinterpret_cast<const double2*>(Ut + (int64_t)(r0 + (e >> 6)) * ldu + c0 +
                                                2 * (e & 63));
     }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = i * 256 + tid;
+  for (int i = 0; i < 1024 / NT; ++i) {
+    const int e = i * NT + tid;
     const int r = r0 + (e >> 6);
     const int64_t c = c0 + 2 * (e & 63);
     v[i].x = (r < K && c < N) ? Ut[(int64_t)r * ldu + c] : 0.0;
@@ -68,23 +69,29 @@ __device__ inline void load_stage(const double* __restrict__ Ut, int64_t ldu, in
   }
 }
 
-template <int LD>
-__device__ inline void store_stage(double (*X)[LD], const double2 v[4]) {
+template <int NT, int LD>
+__device__ inline void store_stage(double (*X)[LD], const double2 v[1024 / NT]) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = i * 256 + tid;
+  for (int i = 0; i < 1024 / NT; ++i) {
+    const int e = i * NT + tid;
     *reinterpret_cast<double2*>(&X[e >> 6][2 * (e & 63)]) = v[i];
   }
 }
 
-__global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int64_t ldp,
-                                                     int64_t N, const double* __restrict__ Ut,
-                                                     int64_t ldu, int32_t K, int64_t T,
-                                                     int64_t per_xcd,
-                                                     const int32_t* __restrict__ flags, int part,
-                                                     const int32_t* __restrict__ status,
-                                                     int64_t seq) {
+// 128x128 tile per workgroup of 8 waves (4 x 2, each 32 x 64 = 2 x 4 MFMA
+// blocks), two workgroups per CU: four waves per SIMD hide the LDS and
+// barrier latency of each 16-deep stage.
+constexpr int SYRK_NT = 512;
+
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P, int64_t ldp,
+                                                         int64_t N, const double* __restrict__ Ut,
+                                                         int64_t ldu, int32_t K, int64_t T,
+                                                         int64_t per_xcd,
+                                                         const int32_t* __restrict__ flags,
+                                                         int part,
+                                                         const int32_t* __restrict__ status,
+                                                         int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
@@ -95,43 +102,42 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int
   __shared__ double As[2][SKC][SLD];
   __shared__ double Bs[2][SKC][SLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  v4d acc[4][4];
+  const int wm = wave >> 1, wn = wave & 1;  // rows wm*32.., columns wn*64..
+  v4d acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
   const int nch = (K + SKC - 1) / SKC;
-  double2 ra[4], rb[4];
-  load_stage(Ut, ldu, N, 0, K, I0, ra);
-  load_stage(Ut, ldu, N, 0, K, J0, rb);
-  store_stage<SLD>(As[0], ra);
-  store_stage<SLD>(Bs[0], rb);
+  double2 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
+  load_stage<SYRK_NT>(Ut, ldu, N, 0, K, I0, ra);
+  load_stage<SYRK_NT>(Ut, ldu, N, 0, K, J0, rb);
+  store_stage<SYRK_NT, SLD>(As[0], ra);
+  store_stage<SYRK_NT, SLD>(Bs[0], rb);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nch) {
-      load_stage(Ut, ldu, N, (ch + 1) * SKC, K, I0, ra);
-      load_stage(Ut, ldu, N, (ch + 1) * SKC, K, J0, rb);
+      load_stage<SYRK_NT>(Ut, ldu, N, (ch + 1) * SKC, K, I0, ra);
+      load_stage<SYRK_NT>(Ut, ldu, N, (ch + 1) * SKC, K, J0, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < SKC; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a[4], b[4];
+      double a[2], b[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[buf][kr][wm * 64 + q * 16 + (lane & 15)];
-        b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
-      }
+      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+      for (int q = 0; q < 4; ++q) b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
     if (ch + 1 < nch) {
-      store_stage<SLD>(As[buf ^ 1], ra);
-      store_stage<SLD>(Bs[buf ^ 1], rb);
+      store_stage<SYRK_NT, SLD>(As[buf ^ 1], ra);
+      store_stage<SYRK_NT, SLD>(Bs[buf ^ 1], rb);
     }
     __syncthreads();
   }
@@ -139,12 +145,12 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f64(double* __restrict__ P, int
   // gi >= gj so each element is written once)
   const bool diag = (I == J);
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t gi = I0 + wm * 64 + mi * 16 + 4 * v + (lane >> 4);
+        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * v + (lane >> 4);
         const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
         if (gi < N && gj < N && (!diag || gi >= gj)) {
           const double nv = P[gi * ldp + gj] - acc[mi][ni][v];
@@ -438,8 +444,8 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
   rbf_status st;
   if (prec == RBF_F64) {
     prof_begin(ctx, RBF_PROF_SYRK);
-    k_syrk_f64<<<grid, 256, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T, per_xcd, flags, part,
-                                              ctx->d_status, seq);
+    k_syrk_f64<<<grid, SYRK_NT, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T, per_xcd, flags,
+                                                  part, ctx->d_status, seq);
     RBF_LAUNCHED(ctx, "k_syrk_f64");
     prof_end(ctx, RBF_PROF_SYRK);
     return RBF_OK;
