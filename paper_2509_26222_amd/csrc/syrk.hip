@@ -237,6 +237,29 @@ __device__ inline void epilogue_f32acc(double* __restrict__ P, int64_t ldp, int6
       }
 }
 
+// Epilogue of the 8-wave layout (wave: rows wm*32 + 2 x 16, columns
+// wn*64 + 4 x 16), as epilogue_f32acc.
+__device__ inline void epilogue_f32acc_w8(double* __restrict__ P, int64_t ldp, int64_t N,
+                                          int64_t I0, int64_t J0, bool diag,
+                                          const v4f acc[2][4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+        if (gi < N && gj < N && (!diag || gi >= gj)) {
+          const double nv = P[gi * ldp + gj] - (double)acc[mi][ni][v];
+          P[gi * ldp + gj] = nv;
+          if (gi != gj) P[gj * ldp + gi] = nv;
+        }
+      }
+}
+
 constexpr int FKC = 32;      // rows of V^T per stage (FP32)
 constexpr int FLD = ST + 4;  // LDS pitch (floats)
 
@@ -244,21 +267,22 @@ constexpr int FLD = ST + 4;  // LDS pitch (floats)
 // thread; float4 i*256 + tid sits at row (i*256 + tid) / 32, column
 // 4 ((i*256 + tid) % 32), so half a wave reads one 512-byte row run and
 // writes it with 16-byte stores (zero outside [0, N) x [0, K)).
+template <int NT>
 __device__ inline void load_stage_f32(const float* __restrict__ Uf, int64_t ldu, int64_t N,
-                                      int r0, int K, int64_t c0, float4 v[4]) {
+                                      int r0, int K, int64_t c0, float4 v[1024 / NT]) {
   const int tid = threadIdx.x;
   if (r0 + FKC <= K && c0 + 128 <= N) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = i * 256 + tid;
+    for (int i = 0; i < 1024 / NT; ++i) {
+      const int e = i * NT + tid;
       v[i] = *reinterpret_cast<const float4*>(Uf + (int64_t)(r0 + (e >> 5)) * ldu + c0 +
                                               4 * (e & 31));
     }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = i * 256 + tid;
+  for (int i = 0; i < 1024 / NT; ++i) {
+    const int e = i * NT + tid;
     const int r = r0 + (e >> 5);
     const int64_t c = c0 + 4 * (e & 31);
     const float* src = Uf + (int64_t)r * ldu + c;
@@ -269,16 +293,17 @@ __device__ inline void load_stage_f32(const float* __restrict__ Uf, int64_t ldu,
   }
 }
 
-__device__ inline void store_stage_f32(float (*X)[FLD], const float4 v[4]) {
+template <int NT>
+__device__ inline void store_stage_f32(float (*X)[FLD], const float4 v[1024 / NT]) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = i * 256 + tid;
+  for (int i = 0; i < 1024 / NT; ++i) {
+    const int e = i * NT + tid;
     *reinterpret_cast<float4*>(&X[e >> 5][4 * (e & 31)]) = v[i];
   }
 }
 
-__global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
                                                      int64_t N, const float* __restrict__ Uf,
                                                      int64_t ldu, int32_t K, int64_t T,
                                                      int64_t per_xcd,
@@ -295,47 +320,46 @@ __global__ void __launch_bounds__(256, 2) k_syrk_f32(double* __restrict__ P, int
   __shared__ __attribute__((aligned(16))) float As[2][FKC][FLD];
   __shared__ __attribute__((aligned(16))) float Bs[2][FKC][FLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  v4f acc[4][4];
+  const int wm = wave >> 1, wn = wave & 1;  // rows wm*32.., columns wn*64..
+  v4f acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
   const int nch = (K + FKC - 1) / FKC;
-  float4 ra[4], rb[4];
-  load_stage_f32(Uf, ldu, N, 0, K, I0, ra);
-  load_stage_f32(Uf, ldu, N, 0, K, J0, rb);
-  store_stage_f32(As[0], ra);
-  store_stage_f32(Bs[0], rb);
+  float4 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
+  load_stage_f32<SYRK_NT>(Uf, ldu, N, 0, K, I0, ra);
+  load_stage_f32<SYRK_NT>(Uf, ldu, N, 0, K, J0, rb);
+  store_stage_f32<SYRK_NT>(As[0], ra);
+  store_stage_f32<SYRK_NT>(Bs[0], rb);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nch) {
-      load_stage_f32(Uf, ldu, N, (ch + 1) * FKC, K, I0, ra);
-      load_stage_f32(Uf, ldu, N, (ch + 1) * FKC, K, J0, rb);
+      load_stage_f32<SYRK_NT>(Uf, ldu, N, (ch + 1) * FKC, K, I0, ra);
+      load_stage_f32<SYRK_NT>(Uf, ldu, N, (ch + 1) * FKC, K, J0, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < FKC; kk += 4) {
       const int kr = kk + (lane >> 4);
-      float a[4], b[4];
+      float a[2], b[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[buf][kr][wm * 64 + q * 16 + (lane & 15)];
-        b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
-      }
+      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+      for (int q = 0; q < 4; ++q) b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
     if (ch + 1 < nch) {
-      store_stage_f32(As[buf ^ 1], ra);
-      store_stage_f32(Bs[buf ^ 1], rb);
+      store_stage_f32<SYRK_NT>(As[buf ^ 1], ra);
+      store_stage_f32<SYRK_NT>(Bs[buf ^ 1], rb);
     }
     __syncthreads();
   }
-  epilogue_f32acc(P, ldp, N, I0, J0, I == J, acc);
+  epilogue_f32acc_w8(P, ldp, N, I0, J0, I == J, acc);
 }
 
 constexpr int BKC = 32;      // k per stage (one 16x16x32 MFMA)
@@ -459,7 +483,7 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
       RBF_LAUNCHED(ctx, "k_cvt_f32");
     }
     prof_begin(ctx, RBF_PROF_SYRK);
-    k_syrk_f32<<<grid, 256, 0, ctx->stream>>>(P, ldp, N, Uf, ldu, Bc, T, per_xcd, flags, part,
+    k_syrk_f32<<<grid, SYRK_NT, 0, ctx->stream>>>(P, ldp, N, Uf, ldu, Bc, T, per_xcd, flags, part,
                                               ctx->d_status, seq);
     RBF_LAUNCHED(ctx, "k_syrk_f32");
     prof_end(ctx, RBF_PROF_SYRK);
