@@ -217,28 +217,9 @@ __global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ U
   }
 }
 
-__device__ inline void epilogue_f32acc(double* __restrict__ P, int64_t ldp, int64_t N,
-                                       int64_t I0, int64_t J0, bool diag, const v4f acc[4][4]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-#pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t gi = I0 + wm * 64 + mi * 16 + 4 * (lane >> 4) + v;
-        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
-        if (gi < N && gj < N && (!diag || gi >= gj)) {
-          const double nv = P[gi * ldp + gj] - (double)acc[mi][ni][v];
-          P[gi * ldp + gj] = nv;
-          if (gi != gj) P[gj * ldp + gi] = nv;
-        }
-      }
-}
-
-// Epilogue of the 8-wave layout (wave: rows wm*32 + 2 x 16, columns
-// wn*64 + 4 x 16), as epilogue_f32acc.
+// P -= C (FP32 accumulators) for the 8-wave layout (wave: rows wm*32 +
+// 2 x 16, columns wn*64 + 4 x 16), written to both triangles as in the FP64
+// kernel.
 __device__ inline void epilogue_f32acc_w8(double* __restrict__ P, int64_t ldp, int64_t N,
                                           int64_t I0, int64_t J0, bool diag,
                                           const v4f acc[2][4]) {
@@ -365,40 +346,33 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
 constexpr int BKC = 32;      // k per stage (one 16x16x32 MFMA)
 constexpr int BLD = BKC + 8; // LDS pitch in bf16 (80 bytes)
 
-// One thread's share of a BF16 stage: 2 x 16 bytes of rows ga (I panel) and
-// gb (J panel) of V_hi and V_lo from k index k0 (zero beyond N). Inlined so
-// that the four staging arrays stay in registers.
+// One thread's share of a BF16 stage (8-wave layout: 4 threads per row of
+// 32 k values, one 16-byte piece each): row ga (I panel) and gb (J panel) of
+// V_hi and V_lo from k index k0. Rows beyond N read row N-1 (in bounds) and
+// are zeroed by a mask, so no pointer is selected (a select between a global
+// and a local address made the loads generic and put a zero on the stack).
 __device__ __forceinline__ void load_bf16_stage(const __bf16* __restrict__ Vhi,
                                                 const __bf16* __restrict__ Vlo, int32_t Kp,
                                                 int64_t N, int64_t ga, int64_t gb, int64_t k0,
-                                                uint4 (&rah)[2], uint4 (&ral)[2],
-                                                uint4 (&rbh)[2], uint4 (&rbl)[2]) {
-  // rows beyond N read row N-1 (in bounds) and are zeroed by a mask, so no
-  // pointer is selected (a select between a global and a local address made
-  // the loads generic and put a zero constant on the stack)
+                                                uint4& rah, uint4& ral, uint4& rbh,
+                                                uint4& rbl) {
   const int64_t ra = ga < N ? ga : N - 1, rb = gb < N ? gb : N - 1;
   const uint32_t ma = ga < N ? 0xffffffffu : 0u, mb = gb < N ? 0xffffffffu : 0u;
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    rah[u] = *reinterpret_cast<const uint4*>(Vhi + ra * Kp + k0 + 8 * u);
-    ral[u] = *reinterpret_cast<const uint4*>(Vlo + ra * Kp + k0 + 8 * u);
-    rbh[u] = *reinterpret_cast<const uint4*>(Vhi + rb * Kp + k0 + 8 * u);
-    rbl[u] = *reinterpret_cast<const uint4*>(Vlo + rb * Kp + k0 + 8 * u);
-    rah[u].x &= ma; rah[u].y &= ma; rah[u].z &= ma; rah[u].w &= ma;
-    ral[u].x &= ma; ral[u].y &= ma; ral[u].z &= ma; ral[u].w &= ma;
-    rbh[u].x &= mb; rbh[u].y &= mb; rbh[u].z &= mb; rbh[u].w &= mb;
-    rbl[u].x &= mb; rbl[u].y &= mb; rbl[u].z &= mb; rbl[u].w &= mb;
-  }
+  rah = *reinterpret_cast<const uint4*>(Vhi + ra * Kp + k0);
+  ral = *reinterpret_cast<const uint4*>(Vlo + ra * Kp + k0);
+  rbh = *reinterpret_cast<const uint4*>(Vhi + rb * Kp + k0);
+  rbl = *reinterpret_cast<const uint4*>(Vlo + rb * Kp + k0);
+  rah.x &= ma; rah.y &= ma; rah.z &= ma; rah.w &= ma;
+  ral.x &= ma; ral.y &= ma; ral.z &= ma; ral.w &= ma;
+  rbh.x &= mb; rbh.y &= mb; rbh.z &= mb; rbh.w &= mb;
+  rbl.x &= mb; rbl.y &= mb; rbl.z &= mb; rbl.w &= mb;
 }
 
-__global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, int64_t ldp,
-                                                        int64_t N, const __bf16* __restrict__ Vhi,
-                                                        const __bf16* __restrict__ Vlo,
-                                                        int32_t Kp, int64_t T, int64_t per_xcd,
-                                                        const int32_t* __restrict__ flags,
-                                                        int part,
-                                                        const int32_t* __restrict__ status,
-                                                        int64_t seq) {
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
+    double* __restrict__ P, int64_t ldp, int64_t N, const __bf16* __restrict__ Vhi,
+    const __bf16* __restrict__ Vlo, int32_t Kp, int64_t T, int64_t per_xcd,
+    const int32_t* __restrict__ flags, int part, const int32_t* __restrict__ status,
+    int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
@@ -411,42 +385,42 @@ __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, 
   __shared__ __attribute__((aligned(16))) __bf16 Bh[ST][BLD];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[ST][BLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  // loader: 128 rows x 32 k = 4 x 16 bytes per row; thread -> (row, quarter)
-  const int lrow = tid >> 1, lq = (tid & 1) * 16;  // 2 threads per row, 16 bf16 each
-  v4f acc[4][4];
+  const int wm = wave >> 1, wn = wave & 1;  // rows wm*32.., columns wn*64..
+  const int lrow = tid >> 2, lq = (tid & 3) * 8;  // loader: row, first k of the piece
+  v4f acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
   const int nch = Kp / BKC;
-  uint4 rah[2], ral[2], rbh[2], rbl[2];
+  uint4 rah, ral, rbh, rbl;
   load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)lq, rah, ral, rbh, rbl);
   for (int ch = 0; ch < nch; ++ch) {
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      *reinterpret_cast<uint4*>(&Ah[lrow][lq + 8 * u]) = rah[u];
-      *reinterpret_cast<uint4*>(&Al[lrow][lq + 8 * u]) = ral[u];
-      *reinterpret_cast<uint4*>(&Bh[lrow][lq + 8 * u]) = rbh[u];
-      *reinterpret_cast<uint4*>(&Bl[lrow][lq + 8 * u]) = rbl[u];
-    }
+    *reinterpret_cast<uint4*>(&Ah[lrow][lq]) = rah;
+    *reinterpret_cast<uint4*>(&Al[lrow][lq]) = ral;
+    *reinterpret_cast<uint4*>(&Bh[lrow][lq]) = rbh;
+    *reinterpret_cast<uint4*>(&Bl[lrow][lq]) = rbl;
     __syncthreads();
     if (ch + 1 < nch)
       load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)(ch + 1) * BKC + lq, rah,
                       ral, rbh, rbl);
     const int kq = 8 * (lane >> 4);
-    v8bf ah[4], al[4], bh[4], bl[4];
+    v8bf ah[2], al[2], bh[4], bl[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ra_ = wm * 64 + q * 16 + (lane & 15), rb_ = wn * 64 + q * 16 + (lane & 15);
+    for (int q = 0; q < 2; ++q) {
+      const int ra_ = wm * 32 + q * 16 + (lane & 15);
       ah[q] = *reinterpret_cast<const v8bf*>(&Ah[ra_][kq]);
       al[q] = *reinterpret_cast<const v8bf*>(&Al[ra_][kq]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rb_ = wn * 64 + q * 16 + (lane & 15);
       bh[q] = *reinterpret_cast<const v8bf*>(&Bh[rb_][kq]);
       bl[q] = *reinterpret_cast<const v8bf*>(&Bl[rb_][kq]);
     }
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
         acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
@@ -454,7 +428,7 @@ __global__ void __launch_bounds__(256, 2) k_syrk_bf16x3(double* __restrict__ P, 
         acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
       }
   }
-  epilogue_f32acc(P, ldp, N, I0, J0, I == J, acc);
+  epilogue_f32acc_w8(P, ldp, N, I0, J0, I == J, acc);
 }
 
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
@@ -499,7 +473,7 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
     RBF_LAUNCHED(ctx, "k_cvt_bf16x2");
   }
   prof_begin(ctx, RBF_PROF_SYRK);
-  k_syrk_bf16x3<<<grid, 256, 0, ctx->stream>>>(P, ldp, N, V, Vlo, Kp, T, per_xcd, flags, part,
+  k_syrk_bf16x3<<<grid, SYRK_NT, 0, ctx->stream>>>(P, ldp, N, V, Vlo, Kp, T, per_xcd, flags, part,
                                                ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_syrk_bf16x3");
   prof_end(ctx, RBF_PROF_SYRK);
