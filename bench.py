@@ -54,6 +54,8 @@ def parse():
                          "covariance product on a second stream)")
     ap.add_argument("--no-other-schedule", action="store_true",
                     help="skip the FP64 leg with the other update schedule")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip timing the rows outside the per-frame step")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32/BF16 covariance-product legs")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -142,6 +144,69 @@ def batched_leg(ctx, api, synth, n_patches, tune):
         out["tuning"] = {f"{s}x{b}": round(v, 4) for (s, b), v in table.items()}
     del patches
     torch.cuda.empty_cache()
+    return out
+
+
+def rows_leg(ctx, api, synth, L, od, allxy, centers, grid, frame, w, p, reps=3):
+    """Every hot-path row not inside the per-frame step, timed on its own at
+    its workload size (wall time of the library calls, synchronised): center
+    selection and binning over the odometry map, Phi and Gram assembly of a
+    frame, the sparse solve of the 40k-center information form (FP64 factor,
+    FP64 refinement to 1e-10) and the adjoint of the evaluation."""
+    import torch
+    import numpy as np
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    M = allxy.shape[0]
+    t = timed(lambda: ctx.select_centers(allxy, od.roi, 0.5, 0.5, 4, L.SELECT_VOXEL))
+    out["a1_select_centers_voxel"] = {"ms": t * 1e3, "points": M, "mpts_s": M / t / 1e6}
+    t = timed(lambda: ctx.select_centers(allxy, od.roi, 0.5, 0.5, 4, L.SELECT_RADIUS))
+    out["a1_select_centers_radius"] = {"ms": t * 1e3, "points": M, "mpts_s": M / t / 1e6}
+    t = timed(lambda: ctx.grid(p, centers).close())
+    out["a2_bin_centers"] = {"ms": t * 1e3, "centers": int(centers.shape[0])}
+    xy, z, pts, pose = frame
+    t = timed(lambda: ctx.assemble_phi(p, grid, xy))
+    out["a3_assemble_phi"] = {"ms": t * 1e3, "points": int(xy.shape[0])}
+    t = timed(lambda: ctx.gram_pattern(p, grid))
+    rowptr, colidx = ctx.gram_pattern(p, grid)
+    out["a3_gram_pattern"] = {"ms": t * 1e3, "nnz": int(colidx.shape[0])}
+    t = timed(lambda: ctx.assemble_gram(p, grid, xy, z, rowptr, colidx))
+    out["a3_assemble_gram"] = {"ms": t * 1e3, "points": int(xy.shape[0])}
+    gf = torch.ones(pts.shape[0], dtype=pts.dtype, device=pts.device)
+    dw = torch.zeros_like(w)
+    dpose = torch.zeros(6, dtype=torch.float64, device=pts.device)
+    t = timed(lambda: ctx.eval_adjoint(p, grid, w, pts, pose=pose, gbar_f=gf, gbar_r=gf,
+                                       d_w=dw, d_pose=dpose))
+    out["a12_adjoint"] = {"ms": t * 1e3, "points": int(pts.shape[0]),
+                          "mpts_s": pts.shape[0] / t / 1e6}
+    # a9 on the 40k-center map: information form of 800k points
+    case = synth.large_case(3)
+    g40 = ctx.grid(p, torch.from_numpy(case.centers).cuda())
+    lxy, lz = synth.large_points(case, 800_000)
+    lxy, lz = torch.from_numpy(lxy).cuda(), torch.from_numpy(lz).cuda()
+    rp, ci = ctx.gram_pattern(p, g40)
+    vals, b = ctx.assemble_gram(p, g40, lxy, lz, rp, ci)
+    t = timed(lambda: ctx.assemble_gram(p, g40, lxy, lz, rp, ci))
+    out["a3_assemble_gram_40k"] = {"ms": t * 1e3, "points": 800_000, "nnz": int(ci.shape[0])}
+    res = {}
+
+    def solve():
+        x, rel, it, st = ctx.solve(rp, ci, vals, b, rtol=1e-10, max_iter=10, inner="f64")
+        res.update(rel=rel[0], it=it)
+
+    t = timed(solve)
+    out["a9_solve_40k"] = {"ms": t * 1e3, "centers": g40.N, "relres": res["rel"],
+                           "refine_sweeps": res["it"], "inner": "f64"}
+    g40.close()
     return out
 
 
@@ -331,6 +396,12 @@ def main():
             "hbm_frac": q * bytes_pt / kern_s / 1e9 / PEAK_HBM_GBS,
         }
 
+    if not args.no_rows:
+        out_rows = rows_leg(ctx, api, synth, L, od, torch.from_numpy(allxy).to(dev), centers,
+                            grid, frames[0], w, p)
+        log("rows leg done")
+    else:
+        out_rows = None
     out = {
         "metric": METRIC,
         "value": args.steps / dt,
@@ -376,6 +447,7 @@ def main():
         "other_schedule": other_schedule,
         "mixed_precision": mixed,
         "eval": ev,
+        "rows": out_rows,
     }
     log("eval leg done")
     if args.patches > 0:
