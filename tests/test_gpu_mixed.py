@@ -147,3 +147,34 @@ def test_mixed_bf16_eight_frames_refined_each_frame(ctx):
           f"grad rel {eg:.2e}, w rel {ew:.2e}")
     assert ef <= 1e-4
     assert eg <= 1e-3
+
+
+def test_mixed_update_40k_centers_batch_4096(ctx):
+    """The 40k-center map (100 x 100 m at 0.5 m, dense P of 12.8 GB) absorbing
+    two batches of 4096 points with FP32 covariance products and FP64
+    Cholesky of S, then FP64 refinement; heights and gradients at 1000
+    sampled queries against the oracle's sparse batch solution."""
+    case = synth.large_case(3)
+    p = api.Params()
+    grid = ctx.grid(p, dev(case.centers))
+    N = grid.N
+    assert N == 40000
+    xy, z = synth.large_points(case, 8192)
+    w = torch.zeros(N, dtype=torch.float64, device="cuda")
+    P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
+    xs, zs, _ = ctx.sort_points(grid, dev(xy), dev(z))
+    assert ctx.update(p, grid, w, P, xs, zs, batch=4096, gemm_prec="f32") == 8192
+    H, b = O.gram(xy, z, case.centers, p.sigma, p.cutoff, 0.0, p.lam, sparse=True)
+    wb = O.spd_solve(H, b)
+    rng = np.random.default_rng(3)
+    q = rng.uniform(xy.min(0), xy.max(0), size=(1000, 2))
+    ef0, eg0, ew0 = _errors(q, case.centers, host(w), wb, p)
+    rel, iters, _ = _refine(ctx, p, grid, xs, zs, w, P)
+    ef, eg, ew = _errors(q, case.centers, host(w), wb, p)
+    del P
+    torch.cuda.empty_cache()
+    print(f"f32 40k centers, batch 4096: recursion only: max|df| {ef0:.2e} m, grad rel "
+          f"{eg0:.2e}; refined ({iters} CG iterations, relres {rel:.1e}): max|df| {ef:.2e} m, "
+          f"grad rel {eg:.2e}, w rel {ew:.2e}")
+    assert ef <= 1e-4
+    assert eg <= 1e-3
