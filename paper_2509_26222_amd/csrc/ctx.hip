@@ -163,38 +163,30 @@ __global__ void __launch_bounds__(256) k_sort_count(const int32_t* __restrict__ 
   atomicAdd(&counts[c * (int64_t)nkeys + keys[i]], 1);
 }
 
-// Exclusive scan of counts in (key-major, chunk-minor) order, in place,
-// by one workgroup. Also writes start[k] (first slot of key k).
-__global__ void __launch_bounds__(1024) k_sort_scan(int32_t* counts, int64_t nchunks,
-                                                    int32_t nkeys, int32_t* start) {
-  __shared__ int32_t part[1024];
-  const int tid = threadIdx.x;
-  const int64_t n = nchunks * (int64_t)nkeys;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t a = tid * per;
-  const int64_t b = a + per < n ? a + per : n;
-  int32_t s = 0;
-  for (int64_t e = a; e < b; ++e) {
-    int64_t k = e / nchunks, c = e % nchunks;
-    s += counts[c * nkeys + k];
-  }
-  part[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int32_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int32_t run = tid ? part[tid - 1] : 0;
-  for (int64_t e = a; e < b; ++e) {
-    int64_t k = e / nchunks, c = e % nchunks;
-    int32_t v = counts[c * nkeys + k];
+// Exclusive scan of counts in (key-major, chunk-minor) order, in place, in
+// three passes: each key's column over the chunks (one thread per key, reads
+// coalesced across keys) leaving the key totals in start[k]; a scan of the
+// totals; the key bases added back.
+__global__ void __launch_bounds__(256) k_sort_colscan(int32_t* __restrict__ counts,
+                                                      int64_t nchunks, int32_t nkeys,
+                                                      int32_t* __restrict__ start) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= nkeys) return;
+  int32_t run = 0;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int32_t v = counts[c * nkeys + k];
     counts[c * nkeys + k] = run;
-    if (c == 0) start[k] = run;
     run += v;
   }
-  if (tid == 1023) start[nkeys] = part[1023];
+  start[k] = run;
+}
+
+__global__ void __launch_bounds__(256) k_sort_addbase(int32_t* __restrict__ counts, int64_t n,
+                                                      int32_t nkeys,
+                                                      const int32_t* __restrict__ start) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  counts[e] += start[e % nkeys];
 }
 
 __global__ void __launch_bounds__(SORT_CHUNK) k_sort_scatter(const int32_t* __restrict__ keys,
@@ -225,8 +217,13 @@ rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
     k_sort_count<<<ceil_div(n, 256), 256, 0, ctx->stream>>>(keys, n, nkeys, counts);
     RBF_LAUNCHED(ctx, "k_sort_count");
   }
-  k_sort_scan<<<1, 1024, 0, ctx->stream>>>(counts, nchunks, nkeys, start);
-  RBF_LAUNCHED(ctx, "k_sort_scan");
+  k_sort_colscan<<<ceil_div(nkeys, 256), 256, 0, ctx->stream>>>(counts, nchunks, nkeys, start);
+  RBF_LAUNCHED(ctx, "k_sort_colscan");
+  k_scan_excl_i32<<<1, 1024, 0, ctx->stream>>>(start, nkeys);
+  RBF_LAUNCHED(ctx, "k_scan_excl_i32");
+  k_sort_addbase<<<ceil_div(nchunks * (int64_t)nkeys, 256), 256, 0, ctx->stream>>>(
+      counts, nchunks * (int64_t)nkeys, nkeys, start);
+  RBF_LAUNCHED(ctx, "k_sort_addbase");
   if (n > 0) {
     k_sort_scatter<<<nchunks, SORT_CHUNK, 0, ctx->stream>>>(keys, n, nkeys, counts, perm);
     RBF_LAUNCHED(ctx, "k_sort_scatter");

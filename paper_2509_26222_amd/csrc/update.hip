@@ -583,10 +583,84 @@ rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* 
   return RBF_OK;
 }
 
+// Single right-hand side (x of nblk*64 entries, contiguous): one workgroup
+// of 1024 threads with x in LDS walks the block rows in order. Block row i
+// first forms r = x_i - sum_{j<i} L_ij x_j (TRANS: x_i - sum_{j>i} L_ji^T
+// x_j), 16 partial sums per row combined in a fixed order, then
+// x_i = Linv_ii r (TRANS: Linv_ii^T r). L is streamed once per solve.
+template <bool TRANS>
+__global__ void __launch_bounds__(1024) k_trsv1(double* __restrict__ x, int32_t nblk,
+                                                const double* __restrict__ Lb, int64_t ldl,
+                                                const double* __restrict__ Linv,
+                                                const int32_t* __restrict__ status,
+                                                int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  extern __shared__ __attribute__((aligned(16))) double ys[];  // nblk*64 + 16*64 + 64
+  const int n = nblk * NB;
+  double* part = ys + n;       // [16][64] partial sums
+  double* rv = part + 16 * NB; // r of the current block row
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n; e += 1024) ys[e] = x[e];
+  __syncthreads();
+  for (int step = 0; step < nblk; ++step) {
+    const int i = TRANS ? nblk - 1 - step : step;
+    const int r0 = i * NB;
+    if (!TRANS) {
+      // thread (row r = tid / 16, lane cl = tid % 16): columns cl, cl+16, ... < r0
+      const int r = tid >> 4, cl = tid & 15;
+      const double* row = Lb + (int64_t)(r0 + r) * ldl;
+      double t = 0.0;
+      for (int c = cl; c < r0; c += 16) t += row[c] * ys[c];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
+      if (cl == 0) rv[r] = ys[r0 + r] - t;
+    } else {
+      // thread (row r = tid % 64, lane cl = tid / 64): L rows c = r0+64+cl,
+      // +16, ... of column r0 + r (64 consecutive columns per wave)
+      const int r = tid & 63, cl = tid >> 6;
+      double t = 0.0;
+      for (int c = r0 + NB + cl; c < n; c += 16) t += Lb[(int64_t)c * ldl + r0 + r] * ys[c];
+      part[cl * NB + r] = t;
+      __syncthreads();
+      if (tid < NB) {
+        double u = 0.0;
+        for (int q = 0; q < 16; ++q) u += part[q * NB + tid];
+        rv[tid] = ys[r0 + tid] - u;
+      }
+    }
+    __syncthreads();
+    // x_i = Linv_ii r (or its transpose): 16 lanes per output row
+    {
+      const int r = tid >> 4, cl = tid & 15;
+      const double* Li = Linv + (int64_t)i * NB * NB;
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cl + 16 * q;
+        t += (TRANS ? Li[(int64_t)c * NB + r] : Li[(int64_t)r * NB + c]) * rv[c];
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
+      if (cl == 0) ys[r0 + r] = t;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n; e += 1024) x[e] = ys[e];
+}
+
 rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int32_t nblk,
                        const double* Lb, int64_t ldl, const double* Linv, bool trans,
                        int64_t seq) {
   if (ncols <= 0 || nblk <= 0) return RBF_OK;
+  const size_t lds1 = sizeof(double) * ((size_t)nblk * NB + 17 * NB);
+  if (ncols == 1 && ldx == 1 && lds1 <= 64 * 1024) {
+    if (trans)
+      k_trsv1<true><<<1, 1024, lds1, ctx->stream>>>(X, nblk, Lb, ldl, Linv, ctx->d_status, seq);
+    else
+      k_trsv1<false><<<1, 1024, lds1, ctx->stream>>>(X, nblk, Lb, ldl, Linv, ctx->d_status, seq);
+    RBF_LAUNCHED(ctx, "k_trsv1");
+    return RBF_OK;
+  }
   const unsigned grid = (unsigned)ceil_div(ncols, TW);
   if (trans)
     k_trsm_blocks<true><<<grid, 256, 0, ctx->stream>>>(X, ldx, ncols, nblk, Lb, ldl, Linv,
