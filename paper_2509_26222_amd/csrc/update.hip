@@ -609,8 +609,18 @@ __global__ void __launch_bounds__(1024) k_trsv1(double* __restrict__ x, int32_t 
       // thread (row r = tid / 16, lane cl = tid % 16): columns cl, cl+16, ... < r0
       const int r = tid >> 4, cl = tid & 15;
       const double* row = Lb + (int64_t)(r0 + r) * ldl;
-      double t = 0.0;
-      for (int c = cl; c < r0; c += 16) t += row[c] * ys[c];
+      // four independent sums, unrolled: several loads in flight per lane
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      int c = cl;
+#pragma unroll 2
+      for (; c + 48 < r0; c += 64) {
+        t0 += row[c] * ys[c];
+        t1 += row[c + 16] * ys[c + 16];
+        t2 += row[c + 32] * ys[c + 32];
+        t3 += row[c + 48] * ys[c + 48];
+      }
+      for (; c < r0; c += 16) t0 += row[c] * ys[c];
+      double t = (t0 + t1) + (t2 + t3);
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
       if (cl == 0) rv[r] = ys[r0 + r] - t;
@@ -618,9 +628,18 @@ __global__ void __launch_bounds__(1024) k_trsv1(double* __restrict__ x, int32_t 
       // thread (row r = tid % 64, lane cl = tid / 64): L rows c = r0+64+cl,
       // +16, ... of column r0 + r (64 consecutive columns per wave)
       const int r = tid & 63, cl = tid >> 6;
-      double t = 0.0;
-      for (int c = r0 + NB + cl; c < n; c += 16) t += Lb[(int64_t)c * ldl + r0 + r] * ys[c];
-      part[cl * NB + r] = t;
+      const double* col = Lb + r0 + r;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      int c = r0 + NB + cl;
+#pragma unroll 2
+      for (; c + 48 < n; c += 64) {
+        t0 += col[(int64_t)c * ldl] * ys[c];
+        t1 += col[(int64_t)(c + 16) * ldl] * ys[c + 16];
+        t2 += col[(int64_t)(c + 32) * ldl] * ys[c + 32];
+        t3 += col[(int64_t)(c + 48) * ldl] * ys[c + 48];
+      }
+      for (; c < n; c += 16) t0 += col[(int64_t)c * ldl] * ys[c];
+      part[cl * NB + r] = (t0 + t1) + (t2 + t3);
       __syncthreads();
       if (tid < NB) {
         double u = 0.0;
