@@ -383,6 +383,15 @@ def main():
         tb = time.perf_counter()
         ems, en = ctx.profile_read(L.PROF_EVAL)
         ctx.profile(False)
+        # fused Gauss-Newton terms on the same points (J not written)
+        for _ in range(3):
+            ctx.eval_gn(p, grid, w, pts, pose=pose0)
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for _ in range(args.eval_reps):
+            ctx.eval_gn(p, grid, w, pts, pose=pose0)
+        torch.cuda.synchronize()
+        gn_s = (time.perf_counter() - tg0) / args.eval_reps
         q = pts.shape[0]
         esz = pts.element_size()
         bytes_pt = 3 * esz + 10 * esz  # read xyz, write f, grad(2), r, J(6)
@@ -394,6 +403,7 @@ def main():
             "points": q,
             "hbm_gbs": q * bytes_pt / kern_s / 1e9,
             "hbm_frac": q * bytes_pt / kern_s / 1e9 / PEAK_HBM_GBS,
+            "gauss_newton_mpts_s_wall": q / gn_s / 1e6,
         }
 
     if not args.no_rows:

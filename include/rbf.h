@@ -283,6 +283,23 @@ rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* params,
                     rbf_prec prec, void* f, void* grad, void* resid,
                     void* jac);
 
+/* Gauss-Newton terms of the manifold residual, fused into the evaluation:
+ * the Levenberg-Marquardt minimisation of eq. cost_fn (subsection "The
+ * Manifold Constraints") takes the manifold term's normal-equation blocks
+ * sum_i J_i^T J_i and sum_i J_i^T r_i (eqs. residual_manifold_left_wheel,
+ * manifold_derivative, manifold_grad_2; the penalty weight is applied by
+ * the caller):
+ * with r_i and J_i as rbf_eval computes them in the pose form (dim 3),
+ * writes JtJ = sum_i J_i^T J_i (device, 6 x 6 f64, both triangles),
+ * Jtr = sum_i J_i^T r_i (device, 6 f64) and, if rtr is not NULL,
+ * sum_i r_i^2 (device, 1 f64), without writing per-point outputs. Points
+ * in prec (F32: Q x 3 float, F64: Q x 3 double); the sums are formed in
+ * FP64 in a fixed order (per-block partials, then blocks in order), so
+ * results are reproducible. Q = 0 writes zeros. */
+rbf_status rbf_eval_gn(rbf_ctx* ctx, const rbf_params* params, const rbf_grid* grid,
+                       const double* w, const void* pts, int64_t Q, const double* pose,
+                       double z_off, rbf_prec prec, double* JtJ, double* Jtr, double* rtr);
+
 /* Adjoint of rbf_eval for L = sum_i gbar_f[i] f_i + gbar_r[i] r_i
  * (gbar_r only for dim == 3; either gbar may be NULL = zero).
  *   d_pts  (Q x dim, same precision as pts, may be NULL): dL/dpts,

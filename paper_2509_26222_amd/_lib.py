@@ -68,6 +68,8 @@ SIGNATURES = {
                              C.POINTER(dbl), C.POINTER(i32)]),
     "rbf_eval": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl), dbl,
                            C.c_int, vp, vp, vp, vp]),
+    "rbf_eval_gn": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(dbl), dbl, C.c_int, vp, vp,
+                              vp]),
     "rbf_eval_adjoint": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl),
                                    C.c_int, vp, vp, vp, vp, vp]),
     "rbf_batched_plan": (C.c_int, [vp, pp, vp, i32, i32, C.c_int, C.c_int, i32, i64,

@@ -285,6 +285,24 @@ class Context:
             _ptr(r), _ptr(J)), "rbf_eval")
         return {"f": f, "grad": g, "resid": r, "jac": J}
 
+    def eval_gn(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
+                pose, z_off: float = 0.0):
+        """Fused Gauss-Newton terms of the manifold residual over the points:
+        (J^T J (6x6), J^T r (6), r^T r) in FP64, per-point J not written."""
+        Q = pts.shape[0]
+        if pts.dim() != 2 or pts.shape[1] != 3:
+            raise ValueError("pts must be Q x 3 body-frame points")
+        prec = _PREC[pts.dtype]
+        JtJ = torch.empty((6, 6), dtype=torch.float64, device=pts.device)
+        Jtr = torch.empty(6, dtype=torch.float64, device=pts.device)
+        rtr = torch.empty(1, dtype=torch.float64, device=pts.device)
+        pc = params.c()
+        self._check(self.lib.rbf_eval_gn(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            _ptr(pts, None, "pts"), Q, _pose(pose), z_off, prec, _ptr(JtJ), _ptr(Jtr),
+            _ptr(rtr)), "rbf_eval_gn")
+        return JtJ, Jtr, rtr[0]
+
     def eval_adjoint(self, params: Params, grid: "Grid", w: torch.Tensor,
                      pts: torch.Tensor, pose=None, gbar_f=None, gbar_r=None,
                      d_pts=True, d_w: torch.Tensor | None = None,

@@ -166,6 +166,107 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
   finish_point<T, POSE>(i, part, f, sx, sy, zw, px, py, pz, k, f_out, grad_out, r_out, jac_out);
 }
 
+// ---- Gauss-Newton terms of the manifold residual (fused, J not written)
+
+constexpr int GN_TERMS = 28;  // 21 upper entries of J^T J, 6 of J^T r, r^2
+
+// Per point (pose form): r and J as in k_eval, in FP64 from here on; the
+// block's sums of the 28 products go to part[block][28] (wave shuffles,
+// then the four waves in order).
+template <typename T>
+__global__ void __launch_bounds__(256) k_eval_gn(const T* __restrict__ pts, int64_t Q,
+                                                 const typename Vec4<T>::type* __restrict__ tab,
+                                                 const int32_t* __restrict__ start, GridGeom g,
+                                                 EvalK<T> k, double* __restrict__ part) {
+  __shared__ double wsum[4][GN_TERMS];
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPP;
+  const int lp = threadIdx.x % LPP, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v[GN_TERMS];
+#pragma unroll
+  for (int q = 0; q < GN_TERMS; ++q) v[q] = 0.0;
+  if (i < Q) {  // the LPP lanes of a point share this branch
+    T x, y, zw, px, py, pz;
+    world_of<T, true>(pts, i, k, x, y, zw, px, py, pz);
+    T f, sx, sy;
+    accumulate<T>(x, y, tab, start, g, k, lp, f, sx, sy);
+#pragma unroll
+    for (int m = 1; m < LPP; m <<= 1) {
+      f += __shfl_xor(f, m, 64);
+      sx += __shfl_xor(sx, m, 64);
+      sy += __shfl_xor(sy, m, 64);
+    }
+    if (lp == 0) {
+      const double fx = -(double)sx * (double)k.inv_s2, fy = -(double)sy * (double)k.inv_s2;
+      const double r = (double)zw - (double)k.z_off - (double)f;
+      const double g0 = -fx, g1 = -fy, g2 = 1.0;
+      const double q0 = (double)k.R[0] * g0 + (double)k.R[3] * g1 + (double)k.R[6] * g2;
+      const double q1 = (double)k.R[1] * g0 + (double)k.R[4] * g1 + (double)k.R[7] * g2;
+      const double q2 = (double)k.R[2] * g0 + (double)k.R[5] * g1 + (double)k.R[8] * g2;
+      const double J[6] = {(double)py * q2 - (double)pz * q1, (double)pz * q0 - (double)px * q2,
+                           (double)px * q1 - (double)py * q0, g0, g1, g2};
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b) v[q++] = J[a] * J[b];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v[21 + a] = J[a] * r;
+      v[27] = r * r;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < GN_TERMS; ++q) {
+    double t = v[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) wsum[wave][q] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < GN_TERMS) {
+    const int q = threadIdx.x;
+    part[(int64_t)blockIdx.x * GN_TERMS + q] =
+        (wsum[0][q] + wsum[1][q]) + (wsum[2][q] + wsum[3][q]);
+  }
+}
+
+// Sum the block partials in a fixed order (lane l of term q takes blocks
+// l, l+32, ...; the 32 lane sums meet in a fixed shuffle tree); write
+// J^T J (6x6, both triangles), J^T r (6) and r^T r.
+__global__ void __launch_bounds__(1024) k_eval_gn_sum(const double* __restrict__ part,
+                                                      int64_t nblocks, double* __restrict__ JtJ,
+                                                      double* __restrict__ Jtr,
+                                                      double* __restrict__ rtr) {
+  const int q = threadIdx.x >> 5, l = threadIdx.x & 31;
+  if (q >= GN_TERMS) return;  // whole groups of 32 leave together
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t b = l;
+  for (; b + 96 < nblocks; b += 128) {
+    s0 += part[b * GN_TERMS + q];
+    s1 += part[(b + 32) * GN_TERMS + q];
+    s2 += part[(b + 64) * GN_TERMS + q];
+    s3 += part[(b + 96) * GN_TERMS + q];
+  }
+  for (; b < nblocks; b += 32) s0 += part[b * GN_TERMS + q];
+  double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+  if (l != 0) return;
+  if (q < 21) {
+    int a = 0, rem = q;
+    while (rem >= 6 - a) {
+      rem -= 6 - a;
+      ++a;
+    }
+    const int b = a + rem;
+    JtJ[a * 6 + b] = s;
+    JtJ[b * 6 + a] = s;
+  } else if (q < 27) {
+    Jtr[q - 21] = s;
+  } else if (rtr) {
+    *rtr = s;
+  }
+}
+
 // ---- binned evaluation
 
 // Bin key of each point (the far bucket nbins if its 3x3 neighbourhood
@@ -462,6 +563,25 @@ static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, c
 }
 
 template <typename T>
+static rbf_status gn_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
+                       const void* pts, int64_t Q, const double* pose, double z_off,
+                       double* JtJ, double* Jtr, double* rtr) {
+  typename Vec4<T>::type* tab;
+  RBF_TRY(pack<T>(ctx, g, w, &tab));
+  EvalK<T> k = make_consts<T>(p, pose, z_off);
+  const int64_t blocks = ceil_div(Q * LPP, 256);
+  rbf_status st;
+  double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * GN_TERMS * (size_t)blocks, &st);
+  if (!part) return st;
+  k_eval_gn<T><<<(unsigned)blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->d_start,
+                                                          geom(g), k, part);
+  RBF_LAUNCHED(ctx, "k_eval_gn");
+  k_eval_gn_sum<<<1, 1024, 0, ctx->stream>>>(part, blocks, JtJ, Jtr, rtr);
+  RBF_LAUNCHED(ctx, "k_eval_gn_sum");
+  return RBF_OK;
+}
+
+template <typename T>
 static rbf_status adjoint_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
                             const double* w, const void* pts, int64_t Q, int32_t dim,
                             const double* pose, const void* gf, const void* gr, void* d_pts,
@@ -501,6 +621,23 @@ rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const 
   if (prec == RBF_F64) return eval_t<double>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad,
                                              resid, jac);
   return eval_t<float>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac);
+}
+
+rbf_status rbf_eval_gn(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
+                       const void* pts, int64_t Q, const double* pose, double z_off,
+                       rbf_prec prec, double* JtJ, double* Jtr, double* rtr) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  RBF_TRY(check_eval_args(ctx, p, g, w, pts, Q, 3, pose, prec, "rbf_eval_gn"));
+  if (!JtJ || !Jtr) return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval_gn: JtJ and Jtr required");
+  RBF_TRY(set_device(ctx));
+  if (Q == 0) {
+    RBF_TRY(fill_zero(ctx, JtJ, 36 * sizeof(double)));
+    RBF_TRY(fill_zero(ctx, Jtr, 6 * sizeof(double)));
+    if (rtr) RBF_TRY(fill_zero(ctx, rtr, sizeof(double)));
+    return RBF_OK;
+  }
+  if (prec == RBF_F64) return gn_t<double>(ctx, p, g, w, pts, Q, pose, z_off, JtJ, Jtr, rtr);
+  return gn_t<float>(ctx, p, g, w, pts, Q, pose, z_off, JtJ, Jtr, rtr);
 }
 
 rbf_status rbf_eval_adjoint(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,

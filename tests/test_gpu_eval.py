@@ -187,3 +187,36 @@ def _binned_checks(ctx, s, p, w, grid, q, direct):
     assert fn[17] == 0.0
     keep = np.arange(q.shape[0]) != 17
     assert np.array_equal(fn[keep], host(out["f"])[keep])
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_eval_gn_matches_oracle_jacobian_sums(ctx, dt):
+    """Fused J^T J, J^T r and r^T r over 20k scan points of an odometry frame
+    against the sums of the oracle's per-point J and r; the per-point
+    outputs of rbf_eval give the same sums."""
+    od = synth.OdometryCase()
+    p = api.Params()
+    allxy = np.concatenate([od.ground_xy(k) for k in range(od.N_FRAMES)])
+    centers = O.select_centers(allxy, od.roi, 0.5, 0.5, 4, O.VOXEL)
+    rng = np.random.default_rng(5)
+    w = rng.normal(0, 0.3, size=centers.shape[0])
+    grid = ctx.grid(p, dev(centers))
+    pts, R, t = od.scan(12, n=20000)
+    f0, g0, r0, J0 = O.eval_pose(pts, R, t, 0.1, centers, w, p.sigma, p.cutoff)
+    JtJ0, Jtr0, rtr0 = J0.T @ J0, J0.T @ r0, r0 @ r0
+    JtJ, Jtr, rtr = ctx.eval_gn(p, grid, dev(w), dev(pts, dt), pose=(R, t), z_off=0.1)
+    JtJ, Jtr, rtr = host(JtJ), host(Jtr), float(rtr)
+    tol = 1e-10 if dt == torch.float64 else 2e-4
+    scale = np.abs(JtJ0).max()
+    assert np.abs(JtJ - JtJ0).max() <= tol * scale
+    assert np.array_equal(JtJ, JtJ.T)
+    assert np.abs(Jtr - Jtr0).max() <= tol * (np.abs(Jtr0).max() + np.sqrt(scale * rtr0))
+    assert abs(rtr - rtr0) <= tol * rtr0
+    if dt == torch.float64:
+        out = ctx.eval(p, grid, dev(w), dev(pts), pose=(R, t), z_off=0.1)
+        J, r = host(out["jac"]), host(out["resid"])
+        assert np.abs(J.T @ J - JtJ).max() <= 1e-12 * scale
+    # empty point set gives zeros
+    Z, z, zz = ctx.eval_gn(p, grid, dev(w), torch.zeros((0, 3), dtype=dt, device="cuda"),
+                           pose=(R, t))
+    assert float(Z.abs().sum() + z.abs().sum()) == 0.0 and float(zz) == 0.0
