@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # from rocprofv3 FETCH_SIZE (x2.0, the copy-kernel calibration) + WRITE_SIZE (x1.0);
 # summary in profiles/k_syrk_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid
 # only for that kernel version and shape (None otherwise).
-SYRK_F64_TRAFFIC = {(10000, 1024): 3.5606e9 + 0.8091e9}
+SYRK_F64_TRAFFIC = {(10000, 1024): 3.5551e9 + 0.8186e9}
 
 
 def parse():
