@@ -220,8 +220,10 @@ rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* params,
  * colidx int32, vals f64; both triangles stored), the "sparse kernel
  * matrix inversion" of the GPU-acceleration section. B and X are N x nrhs
  * (leading dimensions ldb, ldx >= nrhs). The matrix is reordered into
- * dense diagonal / sub-diagonal blocks of its bandwidth, factored in the
- * `inner` precision (RBF_F32 or RBF_F64), and refined in FP64 until
+ * dense diagonal / sub-diagonal blocks of its bandwidth, factored in FP64
+ * (`inner` must be RBF_F64; any other value returns RBF_E_INVALID_ARG:
+ * the factor's time is in dependent latency-bound block steps, which a
+ * lower precision would not shorten), and refined in FP64 until
  * ||B_k - calH X_k||_2 <= rtol ||B_k||_2 for every column k, or max_iter
  * sweeps. relres (host, nrhs doubles, may be NULL) and iters (host, may be
  * NULL) report the result; the call synchronises. Returns

@@ -89,6 +89,9 @@ def test_solve_errors(ctx, small):
         ctx.solve(rp, ci, dev(-H.tocsr().sorted_indices().data), dev(b), rtol=1e-10,
                   max_iter=3, inner="f64")
     assert e.value.status == 3
+    with pytest.raises(api.RbfError) as e:  # the factor is FP64 only
+        ctx.solve(rp, ci, v, dev(b), rtol=1e-10, max_iter=3, inner="f32")
+    assert e.value.status == 1
 
 
 def test_solve_large_grid_40k(ctx):
