@@ -228,6 +228,42 @@ def kalman_update(w, P, x, z, c, sigma, cutoff, sigma_eps, R, batch=None):
     return w, R * Hinv
 
 
+def active_set(x, c, sigma, cutoff, sigma_eps):
+    """Active rows of a scan (eq. mfk_m_approx and the remark after it): the
+    centers whose regressor entry is non-zero at one or more of the scan's
+    points, in ascending index order. With the hard truncation the other
+    rows of m are exactly zero. The paper draws them as one contiguous run
+    j1..j2; the set itself is used here, whatever its order."""
+    m = regressor_dense(x, c, sigma, cutoff, sigma_eps)  # M x N
+    return np.flatnonzero((m != 0.0).any(axis=0))
+
+
+def kalman_update_active(w, P, x, z, c, sigma, cutoff, sigma_eps, R, batch=None):
+    """Active-rows form of the recursive update (eqs.
+    active_rows_weights_update and H_inverse_update).
+
+    With A the scan's active set, the weights and the inverse are treated as
+    block diagonal with A as one block: the Kalman recursion runs on w_A and
+    the A x A block of calH^{-1} with the regressor m~ restricted to A, and
+    everything else (w outside A, and every entry of P outside A x A,
+    including the blocks that couple A to the other centers) is neither read
+    nor changed. Reading: the paper derives the form from calH being
+    block diagonal; when earlier scans coupled A to other centers, those
+    coupling entries are simply left out of this scan's update. When P has
+    no such coupling (e.g. the prior (R/lambda) I), the result equals the
+    dense update. Returns (w, P, A)."""
+    w = np.array(w, dtype=np.float64, copy=True)
+    P = np.array(P, dtype=np.float64, copy=True)
+    A = active_set(x, c, sigma, cutoff, sigma_eps)
+    if A.size == 0:
+        return w, P, A
+    wA, PA = kalman_update(w[A], P[np.ix_(A, A)], x, z, np.asarray(c)[A], sigma, cutoff,
+                           sigma_eps, R, batch=batch)
+    w[A] = wA
+    P[np.ix_(A, A)] = PA
+    return w, P, A
+
+
 def initial_state(N, lam, R):
     """Prior before any scan: w_0 = 0, calH_0 = lambda*I, so P_0 = (R/lambda) I."""
     return np.zeros(N), (R / lam) * np.eye(N)

@@ -257,6 +257,106 @@ def test_planted_weights_bias_is_linear_in_lambda():
         assert 30 < a / b < 300  # ~100x per 100x in lambda
 
 
+# ------------------------------------------------------- active-rows form
+
+def _disc_scan(rng, center, radius, M):
+    r = radius * np.sqrt(rng.uniform(0, 1, M))
+    t = rng.uniform(0, 2 * np.pi, M)
+    x = np.stack([center[0] + r * np.cos(t), center[1] + r * np.sin(t)], 1)
+    z = 0.2 * np.sin(x[:, 0]) + 0.1 * np.cos(2 * x[:, 1]) + rng.normal(0, 0.02, M)
+    return x, z
+
+
+def _scan_world(seed=11):
+    rng = np.random.default_rng(seed)
+    c = synth.grid_centers(rng, 16, 16, 0.5)  # 8 x 8 m
+    return rng, c
+
+
+def _tol(xs, c):
+    """100 cond(calH) u for the information matrix of the points xs (the
+    forward error bound of two backward-stable routes, as for chain = batch)."""
+    x = np.concatenate(xs)
+    H, _ = O.gram(x, np.zeros(x.shape[0]), c, SIG, CUT, 0.0, LAM)
+    return 100 * np.linalg.cond(H) * np.finfo(float).eps
+
+
+@pytest.mark.parametrize("se", [0.0, 0.1])
+def test_active_set_matches_kdtree(se):
+    rng, c = _scan_world()
+    x, _ = _disc_scan(rng, (3.0, 4.0), 1.2, 300)
+    rad = CUT * math.sqrt(SIG ** 2 + se ** 2)
+    hits = cKDTree(x).query_ball_point(c, rad)
+    ref = np.array([j for j, h in enumerate(hits) if len(h) > 0])
+    A = O.active_set(x, c, SIG, CUT, se)
+    assert np.array_equal(A, ref)
+    assert 0 < A.size < c.shape[0]
+
+
+def test_active_update_from_prior_equals_dense():
+    """From P_0 = (R/lambda) I nothing couples A to the other centers, so the
+    active-rows form equals the dense recursion (and the batch ridge
+    solution of the scan) everywhere."""
+    rng, c = _scan_world()
+    N = c.shape[0]
+    x, z = _disc_scan(rng, (3.0, 4.0), 1.2, 300)
+    w0, P0 = O.initial_state(N, LAM, RV)
+    wa, Pa, A = O.kalman_update_active(w0, P0, x, z, c, SIG, CUT, 0.0, RV, batch=64)
+    wd, Pd = O.kalman_update(w0, P0, x, z, c, SIG, CUT, 0.0, RV, batch=64)
+    wb, Pb = O.ridge_batch(x, z, c, SIG, CUT, 0.0, LAM, RV)
+    tol = _tol([x], c)
+    assert np.linalg.norm(wa - wd) / np.linalg.norm(wd) < tol
+    assert np.abs(Pa - Pd).max() / np.abs(Pd).max() < tol
+    assert np.linalg.norm(wa - wb) / np.linalg.norm(wb) < tol
+    out = np.setdiff1d(np.arange(N), A)
+    assert np.array_equal(wa[out], w0[out])
+    assert np.array_equal(Pa[np.ix_(out, out)], P0[np.ix_(out, out)])
+    assert np.array_equal(Pa[np.ix_(A, out)], P0[np.ix_(A, out)])
+
+
+def test_active_update_disjoint_scans_equal_dense():
+    rng, c = _scan_world()
+    N = c.shape[0]
+    w, P = O.initial_state(N, LAM, RV)
+    wd, Pd = w.copy(), P.copy()
+    xs = []
+    for ctr in ((1.5, 1.5), (6.5, 6.5), (1.5, 6.5)):
+        x, z = _disc_scan(rng, ctr, 0.6, 200)
+        xs.append(x)
+        w, P, _ = O.kalman_update_active(w, P, x, z, c, SIG, CUT, 0.0, RV, batch=50)
+        wd, Pd = O.kalman_update(wd, Pd, x, z, c, SIG, CUT, 0.0, RV, batch=50)
+    tol = _tol(xs, c)
+    assert np.linalg.norm(w - wd) / np.linalg.norm(wd) < tol
+    assert np.abs(P - Pd).max() / np.abs(Pd).max() < tol
+
+
+def test_active_update_is_dense_update_of_block_diagonal_part():
+    """Overlapping scans: the active-rows result on A equals the dense
+    recursion applied to P with its A-to-rest coupling removed (the block
+    diagonal assumption of the paper), and differs from the exact dense
+    recursion on the unmodified P."""
+    rng, c = _scan_world()
+    N = c.shape[0]
+    w, P = O.initial_state(N, LAM, RV)
+    x1, z1 = _disc_scan(rng, (3.0, 4.0), 1.5, 300)
+    w, P, _ = O.kalman_update_active(w, P, x1, z1, c, SIG, CUT, 0.0, RV)
+    x2, z2 = _disc_scan(rng, (4.5, 4.0), 1.5, 300)  # overlaps the first scan
+    wa, Pa, A = O.kalman_update_active(w, P, x2, z2, c, SIG, CUT, 0.0, RV, batch=100)
+    out = np.setdiff1d(np.arange(N), A)
+    Pblk = P.copy()
+    Pblk[np.ix_(A, out)] = 0.0
+    Pblk[np.ix_(out, A)] = 0.0
+    assert np.abs(P[np.ix_(A, out)]).max() > 1e-6  # the scans really are coupled
+    wd, Pd = O.kalman_update(w, Pblk, x2, z2, c, SIG, CUT, 0.0, RV, batch=100)
+    tol = _tol([x1, x2], c)
+    assert np.linalg.norm(wa - wd) / np.linalg.norm(wd) < tol
+    assert np.abs(Pa[np.ix_(A, A)] - Pd[np.ix_(A, A)]).max() / np.abs(Pd).max() < tol
+    assert np.array_equal(Pa[np.ix_(A, out)], P[np.ix_(A, out)])
+    assert np.array_equal(Pa, Pa.T)
+    we, _ = O.kalman_update(w, P, x2, z2, c, SIG, CUT, 0.0, RV)
+    assert np.linalg.norm(wa - we) / np.linalg.norm(we) > 1e3 * tol
+
+
 # ------------------------------------------------------------- evaluation
 
 def test_eval_single_center_closed_form():
