@@ -242,16 +242,17 @@ def kalman_update_active(w, P, x, z, c, sigma, cutoff, sigma_eps, R, batch=None)
     """Active-rows form of the recursive update (eqs.
     active_rows_weights_update and H_inverse_update).
 
-    With A the scan's active set, the weights and the inverse are treated as
-    block diagonal with A as one block: the Kalman recursion runs on w_A and
-    the A x A block of calH^{-1} with the regressor m~ restricted to A, and
-    everything else (w outside A, and every entry of P outside A x A,
-    including the blocks that couple A to the other centers) is neither read
-    nor changed. Reading: the paper derives the form from calH being
-    block diagonal; when earlier scans coupled A to other centers, those
-    coupling entries are simply left out of this scan's update. When P has
-    no such coupling (e.g. the prior (R/lambda) I), the result equals the
-    dense update. Returns (w, P, A)."""
+    With A the scan's active set, the Kalman recursion runs on w_A and the
+    A x A block of calH^{-1} (P / R) with the regressor m~ restricted to A.
+    Eq. H_inverse_update gives the new inverse in block-diagonal form: the
+    A x A block updated, the blocks of the other centers as before, and
+    nothing coupling A to the other centers. Reading: the coupling blocks
+    (rows A, columns outside A, and their mirror) are set to zero by the
+    update; w outside A and P outside the rows and columns of A are
+    unchanged. This keeps P positive semi-definite (block diagonal with PSD
+    blocks), so the S of a later scan stays positive definite. When P has no
+    such coupling (e.g. the prior (R/lambda) I), the result equals the dense
+    update. Returns (w, P, A)."""
     w = np.array(w, dtype=np.float64, copy=True)
     P = np.array(P, dtype=np.float64, copy=True)
     A = active_set(x, c, sigma, cutoff, sigma_eps)
@@ -259,8 +260,11 @@ def kalman_update_active(w, P, x, z, c, sigma, cutoff, sigma_eps, R, batch=None)
         return w, P, A
     wA, PA = kalman_update(w[A], P[np.ix_(A, A)], x, z, np.asarray(c)[A], sigma, cutoff,
                            sigma_eps, R, batch=batch)
+    out = np.setdiff1d(np.arange(P.shape[0]), A)
     w[A] = wA
     P[np.ix_(A, A)] = PA
+    P[np.ix_(A, out)] = 0.0
+    P[np.ix_(out, A)] = 0.0
     return w, P, A
 
 
