@@ -58,6 +58,8 @@ def parse():
                     help="skip timing the rows outside the per-frame step")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32/BF16 covariance-product legs")
+    ap.add_argument("--no-active", action="store_true",
+                    help="skip the active-rows update leg")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches), the "
                          "reference for scaling HBM byte counters, and exit")
@@ -290,11 +292,13 @@ def main():
     hvals = torch.zeros(colidx.shape[0], dtype=torch.float64, device=dev)
     hb = torch.zeros(N, dtype=torch.float64, device=dev)
     refine_log = {}
+    n_act = []
 
-    def run_sequence(gemm_prec, streams=args.streams):
+    def run_sequence(gemm_prec, streams=args.streams, active=False):
         """Warmup + timed frames from the prior (w = 0, P = (R/lambda) I).
         Low-precision covariance products are followed by the FP64
-        refinement of w against the accumulated information form."""
+        refinement of w against the accumulated information form. With
+        active=True each frame is absorbed by the active-rows form."""
         ctx.set_update_streams(streams)
         w.zero_()
         P.zero_()
@@ -302,12 +306,17 @@ def main():
         hvals.zero_()
         hb.zero_()
         sweeps = []
+        n_act.clear()
 
         def step(k):
             xy, z, pts, pose = frames[k % nfr]
             xs, zs, _ = ctx.sort_points(grid, xy, z)
-            ctx.update(p, grid, w, P, xs, zs, batch=args.batch, gemm_prec=gemm_prec,
-                       sync=False)
+            if active:
+                n_act.append(ctx.update_active(p, grid, w, P, xs, zs, batch=args.batch,
+                                               gemm_prec=gemm_prec)[1])
+            else:
+                ctx.update(p, grid, w, P, xs, zs, batch=args.batch, gemm_prec=gemm_prec,
+                           sync=False)
             if gemm_prec != "f64":
                 ctx.assemble_gram(p, grid, xs, zs, rowptr, colidx, hvals, hb,
                                   add_lambda=(k == 0))
@@ -354,9 +363,24 @@ def main():
                           "ms_per_step": dt_o / args.steps * 1e3,
                           "kernel_ms_per_step": {k: v[0] / args.steps
                                                  for k, v in prof_o.items()}}
+    active_rows = None
+    if not args.no_active:
+        dt_a, prof_a = run_sequence("f64", active=True)
+        log(f"active-rows leg: {dt_a / args.steps * 1e3:.1f} ms/step")
+        fa = ctx.eval(p, grid, w, last[2], pose=last[3])["f"].clone()
+        wa = w.clone()
+        active_rows = {"value": args.steps / dt_a, "ms_per_step": dt_a / args.steps * 1e3,
+                       "active_centers_per_step": n_act[args.warmup:],
+                       "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_a.items()}}
     dt, prof = run_sequence("f64")
     log(f"f64 leg, {args.streams} stream(s): {dt / args.steps * 1e3:.1f} ms/step")
     f64 = ctx.eval(p, grid, w, last[2], pose=last[3])["f"]
+    if active_rows is not None:
+        dh = (fa - f64).abs()
+        active_rows["speedup_vs_dense"] = active_rows["value"] / (args.steps / dt)
+        active_rows["max_height_dev_vs_dense_m"] = float(dh.max())
+        active_rows["mean_height_dev_vs_dense_m"] = float(dh.mean())
+        active_rows["w_rel_dev_vs_dense"] = float((wa - w).norm() / w.norm())
     for mp in mixed:
         mixed[mp]["max_height_dev_vs_f64_m"] = float((mixed[mp].pop("_f") - f64).abs().max())
         mixed[mp]["speedup_vs_f64"] = mixed[mp]["value"] / (args.steps / dt)
@@ -456,6 +480,7 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "other_schedule": other_schedule,
         "mixed_precision": mixed,
+        "active_rows": active_rows,
         "eval": ev,
         "rows": out_rows,
     }

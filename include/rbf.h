@@ -214,6 +214,33 @@ rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* params,
                       const double* xy, const double* z, int64_t M,
                       int64_t batch, rbf_prec gemm_prec, int64_t* n_done);
 
+/* Active-rows form of the update (eqs. active_rows_weights_update and
+ * H_inverse_update, with the active rows of eq. mfk_m_approx): the M points
+ * are one scan, and its active set A is every center whose regressor entry
+ * is non-zero at one or more of the points (ascending center index). The
+ * recursion of rbf_update (same batches, same arithmetic, same gemm_prec)
+ * runs on w_A and the A x A block of P only. Afterwards the entries of P
+ * coupling A to the other centers (rows A / columns not in A, and the
+ * mirror) are zero: the block-diagonal result of eq. H_inverse_update,
+ * which keeps P positive semi-definite. w outside A and P outside the rows
+ * and columns of A are neither read nor written. This equals rbf_update
+ * whenever P couples no center of A to a center outside it (e.g. from the
+ * prior (R/lambda) I); otherwise it is the paper's approximation, which
+ * drops that coupling. Arguments as for rbf_update, plus: active (device,
+ * capacity N int32, may be NULL) receives A; n_active (host, may be NULL)
+ * receives |A|. The call synchronises once to size the compact block
+ * (|A| x |A| FP64 workspace, grown as needed and kept by the context), so
+ * it cannot be captured in a graph. Batches commit one by one as in
+ * rbf_update: after a failing batch, w_A and the A x A block hold the
+ * state after the batches before it, and the coupling is cleared only if
+ * at least one batch was absorbed. */
+rbf_status rbf_update_active(rbf_ctx* ctx, const rbf_params* params,
+                             const rbf_grid* grid, double* w, double* P,
+                             int64_t ldp, const double* xy, const double* z,
+                             int64_t M, int64_t batch, rbf_prec gemm_prec,
+                             int32_t* active, int64_t* n_active,
+                             int64_t* n_done);
+
 /* ----------------------------------------------------------------- solve */
 
 /* Solve calH X = B for the sparse SPD matrix in CSR (rowptr N+1 int64,

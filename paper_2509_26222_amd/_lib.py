@@ -62,6 +62,8 @@ SIGNATURES = {
     "rbf_assemble_gram": (C.c_int, [vp, pp, vp, vp, vp, i64, vp, vp, vp, vp, i32]),
     "rbf_update": (C.c_int, [vp, pp, vp, vp, vp, i64, vp, vp, i64, i64, C.c_int,
                              C.POINTER(i64)]),
+    "rbf_update_active": (C.c_int, [vp, pp, vp, vp, vp, i64, vp, vp, i64, i64, C.c_int,
+                                    vp, C.POINTER(i64), C.POINTER(i64)]),
     "rbf_solve": (C.c_int, [vp, i64, vp, vp, vp, vp, i64, vp, i64, i64, dbl, i32,
                             C.c_int, C.POINTER(dbl), C.POINTER(i32)]),
     "rbf_refine": (C.c_int, [vp, i64, vp, vp, vp, vp, vp, i64, dbl, vp, dbl, i32,

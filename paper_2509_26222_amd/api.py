@@ -216,6 +216,28 @@ class Context:
         self._check(st, "rbf_update")
         return nd.value if sync else None
 
+    def update_active(self, params: Params, grid: "Grid", w: torch.Tensor, P: torch.Tensor,
+                      xy: torch.Tensor, z: torch.Tensor, batch: int = 0, gemm_prec="f64",
+                      active: torch.Tensor | None = None):
+        """Active-rows update of one scan; returns (points absorbed, |A|).
+        `active` (int32, N entries, optional) receives the active centers."""
+        ldp = P.stride(0)
+        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] != grid.N or P.shape[1] != grid.N:
+            raise ValueError("P must be an N x N row-major tensor")
+        if active is not None and (active.dtype != torch.int32 or active.numel() < grid.N):
+            raise ValueError("active must be an int32 tensor of N entries")
+        pc = params.c()
+        nd = C.c_int64()
+        na = C.c_int64()
+        st = self.lib.rbf_update_active(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            P.data_ptr() if P.dtype == torch.float64 and P.is_cuda else None, ldp,
+            _ptr(xy, torch.float64, "xy"), _ptr(z, torch.float64, "z"), xy.shape[0],
+            batch, _prec(gemm_prec), _ptr(active, torch.int32, "active") if active is not None
+            else None, C.byref(na), C.byref(nd))
+        self._check(st, "rbf_update_active")
+        return nd.value, na.value
+
     def solve(self, rowptr, colidx, vals, B: torch.Tensor, rtol: float = 1e-10,
               max_iter: int = 50, inner="f64", X: torch.Tensor | None = None):
         N = rowptr.shape[0] - 1

@@ -29,6 +29,8 @@ enum WsSlot {
   WS_UPD_TILES, // update: SYRK tile schedule
   WS_UPD_UT2,   // update: second U^T / V^T buffer (batches alternate)
   WS_UPD_FLAGS, // update: touched 128-row blocks of P, two batches
+  WS_ACT_IDX,   // active-rows update: flags / compact map, active list, w_A
+  WS_ACT_P,     // active-rows update: compact block P_AA
   WS_SOLVE0,
   WS_SOLVE1,
   WS_SOLVE2,

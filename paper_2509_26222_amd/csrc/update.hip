@@ -25,18 +25,17 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int NB = 64;       // Cholesky / TRSM block size
 constexpr int LDT = NB + 1;  // padded LDS row of a 64x64 tile
 
-struct RegKU {
-  double rc2, den, scale;
-};
-
 
 // ------------------------------------------------------------ batch rows
 
 // Regressor rows of the batch in column-major ELL (entry q of row b at
-// q * Bp + b), and the innovation y = z - H w into U^T[:, N].
+// q * Bp + b), and the innovation y = z - H w into U^T[:, N]. With colmap,
+// a center's column is colmap[center] (the compact index of an active
+// center), else the center's own index.
 __global__ void __launch_bounds__(256) k_upd_rows(
     const double* __restrict__ xy, const double* __restrict__ z, int32_t Bc, int32_t Bp,
     const double* __restrict__ cxy, const int32_t* __restrict__ idx,
+    const int32_t* __restrict__ colmap,
     const int32_t* __restrict__ start, GridGeom g, RegKU k, int32_t kmax,
     const double* __restrict__ w, double* __restrict__ vals, int32_t* __restrict__ cols,
     int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu, int64_t N,
@@ -62,7 +61,7 @@ __global__ void __launch_bounds__(256) k_upd_rows(
         const double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
         if (d2 <= k.rc2 && n < kmax) {
           const double v = k.scale * exp(-d2 / k.den);
-          const int32_t c = idx[s];
+          const int32_t c = colmap ? colmap[idx[s]] : idx[s];
           vals[(int64_t)n * Bp + b] = v;
           cols[(int64_t)n * Bp + b] = c;
           hw += v * w[c];
@@ -691,16 +690,9 @@ rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int3
   return RBF_OK;
 }
 
-}  // namespace rbf
-
-using namespace rbf;
-
-extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
-                                 double* w, double* P, int64_t ldp, const double* xy,
-                                 const double* z, int64_t M, int64_t batch, rbf_prec gemm_prec,
-                                 int64_t* n_done) {
-  if (!ctx) return RBF_E_INVALID_ARG;
-  if (n_done) *n_done = 0;
+rbf_status update_check(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
+                        const double* P, int64_t ldp, const double* xy, const double* z,
+                        int64_t M, int64_t batch, rbf_prec gemm_prec) {
   if (!p || !g || !w || !P)
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_update: null params/grid/w/P");
   if (g->device != ctx->device)
@@ -714,9 +706,18 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_update: R must be > 0");
   if (gemm_prec != RBF_F64 && gemm_prec != RBF_F32 && gemm_prec != RBF_BF16)
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_update: unknown gemm_prec");
-  if (M == 0) return RBF_OK;
+  return RBF_OK;
+}
+
+// Enqueue the recursive update of (w, P) (N x N, leading dimension ldp) by
+// the M points in batches of B; regressor columns go through colmap when it
+// is given (the active-rows form's compact problem). Only enqueues: the
+// caller reads the status word (update_done).
+rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                      const int32_t* colmap, int64_t N, double* w, double* P, int64_t ldp,
+                      const double* xy, const double* z, int64_t M, int64_t B,
+                      rbf_prec gemm_prec) {
   RBF_TRY(set_device(ctx));
-  const int64_t B = batch > 0 ? batch : UPDATE_DEFAULT_BATCH;
   const int32_t kmax = g->max_cand > 0 ? g->max_cand : 1;
   const int64_t ldu = ceil_div(N + 1, 32) * 32;
   UpdWs ws;
@@ -728,11 +729,7 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
   double* Lb = ws.Lb;
   double* Linv = ws.Linv;
   double* wpart = ws.wpart;
-  const double st_ = std::sqrt(p->sigma * p->sigma + p->sigma_eps * p->sigma_eps);
-  RegKU rk;
-  rk.rc2 = (p->cutoff * st_) * (p->cutoff * st_);
-  rk.den = 2.0 * st_ * st_;
-  rk.scale = (p->sigma * p->sigma) / (st_ * st_);
+  const RegKU rk = regku(p);
   const int64_t nb_total = ceil_div(M, B);
   // Launch group (sequence number) of batch bi: seq0 + bi. A failure in
   // batch bi stops the launches of batches >= bi only.
@@ -770,7 +767,7 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
     sizes(bi, &Bc, &Bpc);
     const int64_t s0 = bi * B;
     k_upd_rows<<<ceil_div(Bpc, 256), 256, 0, ctx->stream>>>(
-        xy + 2 * s0, z + s0, Bc, Bpc, g->d_cxy, g->d_idx, g->d_start, geom(g), rk, kmax, w,
+        xy + 2 * s0, z + s0, Bc, Bpc, g->d_cxy, g->d_idx, colmap, g->d_start, geom(g), rk, kmax, w,
         vals, cols, nnz, UtB[bi & 1], ldu, N, ctx->d_status, ctx->index_base + bi, seq0 + bi);
     RBF_LAUNCHED(ctx, "k_upd_rows");
     RBF_TRY(fill_zero(ctx, Fl[bi & 1], sizeof(int32_t) * nfl));
@@ -863,19 +860,41 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
     RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec, Fl[(bi + 1) & 1], 2,
                         seq0 + bi));
   }
-  if (n_done) {
-    int32_t h[4];
-    RBF_HIP(ctx, hipMemcpyAsync(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost,
-                                ctx->stream));
-    RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (h[0] != 0) {
-      int64_t idx;
-      memcpy(&idx, h + 2, sizeof(idx));
-      const int64_t done = (idx - ctx->index_base) * B;
-      *n_done = done < M ? done : M;
-      return rbf_sync_status(ctx);
-    }
-    *n_done = M;
-  }
   return RBF_OK;
+}
+
+// After update_run: wait for the stream and report the points absorbed
+// (all M, or the batches before the first failing one) and the status.
+rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t* n_done) {
+  int32_t h[4];
+  RBF_HIP(ctx, hipMemcpyAsync(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h[0] != 0) {
+    int64_t idx;
+    memcpy(&idx, h + 2, sizeof(idx));
+    const int64_t done = (idx - ctx->index_base) * B;
+    *n_done = done < M ? done : M;
+    return rbf_sync_status(ctx);
+  }
+  *n_done = M;
+  return RBF_OK;
+}
+
+}  // namespace rbf
+
+using namespace rbf;
+
+extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                                 double* w, double* P, int64_t ldp, const double* xy,
+                                 const double* z, int64_t M, int64_t batch, rbf_prec gemm_prec,
+                                 int64_t* n_done) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  if (n_done) *n_done = 0;
+  RBF_TRY(update_check(ctx, p, g, w, P, ldp, xy, z, M, batch, gemm_prec));
+  if (M == 0) return RBF_OK;
+  const int64_t B = batch > 0 ? batch : UPDATE_DEFAULT_BATCH;
+  RBF_TRY(update_run(ctx, p, g, nullptr, g->N, w, P, ldp, xy, z, M, B, gemm_prec));
+  if (!n_done) return RBF_OK;
+  return update_done(ctx, M, B, n_done);
 }

@@ -2,12 +2,28 @@
 // product kernels.
 #pragma once
 
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace rbf {
 
 // Points absorbed per Kalman batch when the caller passes batch = 0.
 constexpr int64_t UPDATE_DEFAULT_BATCH = 1024;
+
+// Regressor m(x, c) = scale * exp(-d^2 / den) for d^2 <= rc2 (moment
+// regressor with sigma_t^2 = sigma^2 + sigma_eps^2, cut at cutoff sigma_t).
+struct RegKU {
+  double rc2, den, scale;
+};
+inline RegKU regku(const rbf_params* p) {
+  const double st = std::sqrt(p->sigma * p->sigma + p->sigma_eps * p->sigma_eps);
+  RegKU k;
+  k.rc2 = (p->cutoff * st) * (p->cutoff * st);
+  k.den = 2.0 * st * st;
+  k.scale = (p->sigma * p->sigma) / (st * st);
+  return k;
+}
 
 // Output tile of the covariance product (rows and columns of P).
 constexpr int SYRK_TILE = 128;
@@ -57,5 +73,25 @@ rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* 
 rbf_status trsm_blocks(rbf_ctx* ctx, double* X, int64_t ldx, int64_t ncols, int32_t nblk,
                        const double* Lb, int64_t ldl, const double* Linv, bool trans,
                        int64_t seq);
+
+// Argument checks shared by rbf_update and rbf_update_active.
+rbf_status update_check(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
+                        const double* P, int64_t ldp, const double* xy, const double* z,
+                        int64_t M, int64_t batch, rbf_prec gemm_prec);
+
+// Enqueue the recursive update of (w, P) (N x N, leading dimension ldp) by
+// the M points xy, z in batches of B. colmap (device, one int32 per center
+// of g, or null) maps a center to its column: the active-rows form runs the
+// update on its compact block with colmap = compact index of each active
+// center. Only enqueues; update_done reads the outcome.
+rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                      const int32_t* colmap, int64_t N, double* w, double* P, int64_t ldp,
+                      const double* xy, const double* z, int64_t M, int64_t B,
+                      rbf_prec gemm_prec);
+
+// Wait for the context's stream and report the points absorbed: M, or the
+// points of the batches before the first failing one (whose error is
+// returned and cleared).
+rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t* n_done);
 
 }  // namespace rbf
