@@ -151,6 +151,35 @@ def select_centers(xy, roi, res, r_kd, thr, mode=RADIUS):
     return np.ascontiguousarray(G[cnt > thr])
 
 
+def select_centers_grow(counts, xy, roi, res, r_kd, thr, mode=RADIUS):
+    """Center selection applied frame by frame (a growing center set).
+
+    Reading: the support count of a candidate node is over every terrain
+    point seen so far, so a frame adds its own counts to the running ones
+    (counts: one integer per node, zeros before the first frame). A node
+    becomes a center in the frame whose points take its count past thr;
+    the frame's new centers are appended in mesh order. Over all frames the
+    centers are those of select_centers on all the points together.
+    Returns (counts after the frame, the frame's new centers)."""
+    G, _, _ = candidate_mesh(roi, res)
+    old = np.asarray(counts, dtype=np.int64)
+    new = old + candidate_counts(xy, roi, res, r_kd, mode)
+    return new, np.ascontiguousarray(G[(old <= thr) & (new > thr)])
+
+
+def grow_state(w, P, n_new, lam, R):
+    """Append n_new centers to the state: their weights start at the prior
+    w = 0 with the prior covariance (R/lambda) I and no coupling to the
+    existing centers, i.e. calH gains lambda on the new diagonal entries."""
+    N = w.shape[0]
+    w2 = np.zeros(N + n_new)
+    w2[:N] = w
+    P2 = np.zeros((N + n_new, N + n_new))
+    P2[:N, :N] = P
+    P2[np.arange(N, N + n_new), np.arange(N, N + n_new)] = R / lam
+    return w2, P2
+
+
 # ---------------------------------------------------------------------------
 # Ridge estimator (eq. RBF_estimator with the ridge term)
 # ---------------------------------------------------------------------------

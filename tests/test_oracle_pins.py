@@ -359,6 +359,84 @@ def test_active_update_is_dense_update_of_block_diagonal_part():
     assert np.linalg.norm(wa - we) / np.linalg.norm(we) > 1e3 * tol
 
 
+# ------------------------------------------------------ growing center set
+
+def _path_frames(seed=12, n=5):
+    rng = np.random.default_rng(seed)
+    frames = []
+    for k in range(n):
+        ctr = (1.5 + 1.2 * k, 4.0 + 0.5 * math.sin(k))
+        x, z = _disc_scan(rng, ctr, 1.6, 400)
+        frames.append((np.clip(x, 0.0, 8.0), z))
+    return frames
+
+
+@pytest.mark.parametrize("mode,r_kd,thr", [(O.RADIUS, 0.5, 6), (O.VOXEL, 0.5, 3)])
+def test_select_grow_union_equals_batch_selection(mode, r_kd, thr):
+    roi = (0.0, 0.0, 8.0, 8.0)
+    frames = _path_frames()
+    G, nx, ny = O.candidate_mesh(roi, 0.5)
+    counts = np.zeros(nx * ny, dtype=np.int64)
+    got = []
+    for x, _ in frames:
+        counts, new = O.select_centers_grow(counts, x, roi, 0.5, r_kd, thr, mode)
+        # mesh order within the frame
+        lin = np.round((new[:, 1] - 0.25) / 0.5) * nx + np.round((new[:, 0] - 0.25) / 0.5)
+        assert np.all(np.diff(lin) > 0)
+        got.append(new)
+    allx = np.concatenate([f[0] for f in frames])
+    if mode == O.RADIUS:  # independent count: k-d tree over all points
+        ref_cnt = np.array([len(h) for h in cKDTree(allx).query_ball_point(G, r_kd)])
+    else:
+        ref_cnt, _, _ = np.histogram2d(allx[:, 1], allx[:, 0], bins=[ny, nx],
+                                       range=[[0, 8], [0, 8]])
+        ref_cnt = ref_cnt.ravel().astype(np.int64)
+    assert np.array_equal(counts, ref_cnt)
+    grown = np.concatenate(got)
+    batch = G[ref_cnt > thr]
+    assert grown.shape == batch.shape and len({tuple(c) for c in grown}) == grown.shape[0]
+    key = lambda a: a[np.lexsort((a[:, 0], a[:, 1]))]
+    assert np.array_equal(key(grown), batch)
+    assert sum(g.shape[0] > 0 for g in got) >= 3  # the set really grows
+
+
+def test_grown_chain_equals_masked_batch_ridge():
+    """Growing centers with the recursion equals the ridge estimator in
+    which each point's regressor keeps only the centers that existed when
+    the point was absorbed (closed form: calH = lambda I + sum m^ m^T,
+    b = sum m^ z, with m^ the masked regressor)."""
+    roi = (0.0, 0.0, 8.0, 8.0)
+    frames = _path_frames()
+    G, nx, ny = O.candidate_mesh(roi, 0.5)
+    counts = np.zeros(nx * ny, dtype=np.int64)
+    c = np.zeros((0, 2))
+    w, P = np.zeros(0), np.zeros((0, 0))
+    born = []
+    for x, z in frames:
+        counts, new = O.select_centers_grow(counts, x, roi, 0.5, 0.5, 6, O.RADIUS)
+        w, P = O.grow_state(w, P, new.shape[0], LAM, RV)
+        c = np.concatenate([c, new])
+        born.append(c.shape[0])
+        w, P = O.kalman_update(w, P, x, z, c, SIG, CUT, 0.0, RV, batch=128)
+    N = c.shape[0]
+    H = LAM * np.eye(N)
+    b = np.zeros(N)
+    for (x, z), nb in zip(frames, born):
+        m = np.zeros((x.shape[0], N))
+        m[:, :nb] = O.regressor_dense(x, c[:nb], SIG, CUT, 0.0)
+        H += m.T @ m
+        b += m.T @ z
+    w_ref = scipy.linalg.solve(H, b, assume_a="pos")
+    tol = 100 * np.linalg.cond(H) * np.finfo(float).eps
+    assert np.linalg.norm(w - w_ref) / np.linalg.norm(w_ref) < tol
+    assert np.abs(P - RV * np.linalg.inv(H)).max() / np.abs(P).max() < tol
+    # the late centers miss earlier points: not the batch ridge of all points
+    allx = np.concatenate([f[0] for f in frames])
+    allz = np.concatenate([f[1] for f in frames])
+    wb, _ = O.ridge_batch(allx, allz, c, SIG, CUT, 0.0, LAM, RV, with_P=False)
+    assert np.linalg.norm(w - wb) / np.linalg.norm(wb) > 1e3 * tol
+
+
 # ------------------------------------------------------------- evaluation
 
 def test_eval_single_center_closed_form():
