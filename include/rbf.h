@@ -131,6 +131,38 @@ rbf_status rbf_select_centers(rbf_ctx* ctx, const double* xy, int64_t M,
                               int32_t thr, int32_t mode, double* centers_out,
                               int64_t cap, int64_t* n_out);
 
+/* The same selection applied frame by frame, for a growing center set.
+ * counts (device, nx * ny int32, zero before the first frame, kept by the
+ * caller between frames) holds each node's support count over every point
+ * passed so far; this call adds the M points' counts. A node becomes a
+ * center in the call whose points take its count past thr; those nodes are
+ * written to centers_out (cap x 2 f64) in mesh order and *n_new (host)
+ * receives their number. Over all calls the centers are exactly those of
+ * rbf_select_centers on all the points together. Synchronises. If more
+ * than cap nodes would be new, returns RBF_E_CAPACITY and leaves counts
+ * unchanged. Counts are int32 (at most 2^31 - 1 points per node). */
+rbf_status rbf_select_centers_grow(rbf_ctx* ctx, const double* xy, int64_t M,
+                                   const double* roi, double res, double r_kd,
+                                   int32_t thr, int32_t mode, int32_t* counts,
+                                   double* centers_out, int64_t cap,
+                                   int64_t* n_new);
+
+/* Grow the state of the recursive update from n_old to n_new centers (the
+ * new centers appended after the old ones): the new weights start at 0 and
+ * the new rows and columns of P at the prior (R/lambda) I with no coupling
+ * to the old centers (calH gains lambda on the new diagonal entries; the
+ * ridge estimator's prior, subsection "The RBF Weight Estimate by Ridge
+ * Regression"). In place: w (device, capacity >= n_new) and P (device,
+ * row-major, leading dimension ldp >= n_new) already hold the old state in
+ * their first n_old entries / n_old x n_old block; only the new rows and
+ * columns are written. Asynchronous. Points absorbed before a center
+ * existed do not inform its weight (the recursion then equals the ridge
+ * estimator with each point's regressor restricted to the centers that
+ * existed when it was absorbed). */
+rbf_status rbf_state_grow(rbf_ctx* ctx, const rbf_params* params, double* w,
+                          double* P, int64_t ldp, int64_t n_old,
+                          int64_t n_new);
+
 /* --------------------------------------------------------------- binning */
 
 /* Build the neighbour-binned center table used by every kernel below:

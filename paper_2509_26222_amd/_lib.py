@@ -52,6 +52,9 @@ SIGNATURES = {
     "rbf_status_string": (C.c_char_p, [C.c_int]),
     "rbf_select_centers": (C.c_int, [vp, vp, i64, C.POINTER(dbl), dbl, dbl, i32,
                                      i32, vp, i64, C.POINTER(i64)]),
+    "rbf_select_centers_grow": (C.c_int, [vp, vp, i64, C.POINTER(dbl), dbl, dbl, i32, i32,
+                                          vp, vp, i64, C.POINTER(i64)]),
+    "rbf_state_grow": (C.c_int, [vp, pp, vp, vp, i64, i64, i64]),
     "rbf_grid_create": (C.c_int, [vp, pp, vp, i64, C.POINTER(vp)]),
     "rbf_grid_destroy": (C.c_int, [vp]),
     "rbf_grid_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32),

@@ -138,6 +138,42 @@ class Context:
             "rbf_select_centers")
         return out[: n.value]
 
+    def select_centers_grow(self, xy: torch.Tensor, roi, res: float, r_kd: float, thr: int,
+                            counts: torch.Tensor, mode: int = L.SELECT_RADIUS,
+                            cap: int | None = None):
+        """Selection on running counts (int32, nx * ny, updated in place);
+        returns the nodes that became centers with this call's points."""
+        M = xy.shape[0]
+        x0, y0, x1, y1 = [float(v) for v in roi]
+        import math
+        nx = int(math.ceil((x1 - x0) / res))
+        ny = int(math.ceil((y1 - y0) / res))
+        if counts.dtype != torch.int32 or counts.numel() != nx * ny:
+            raise ValueError(f"counts must be int32 with {nx * ny} entries")
+        cap = cap if cap is not None else max(nx * ny, 1)
+        out = torch.empty((cap, 2), dtype=torch.float64, device=xy.device)
+        roi_c = (C.c_double * 4)(x0, y0, x1, y1)
+        n = C.c_int64()
+        self._check(self.lib.rbf_select_centers_grow(
+            self.h, _ptr(xy, torch.float64, "xy", self.device), M, roi_c, res, r_kd, thr,
+            mode, _ptr(counts, torch.int32, "counts"), _ptr(out, torch.float64, "centers_out"),
+            cap, C.byref(n)), "rbf_select_centers_grow")
+        return out[: n.value]
+
+    def state_grow(self, params: Params, w: torch.Tensor, P: torch.Tensor, n_old: int,
+                   n_new: int):
+        """New centers n_old..n_new-1 join (w, P) with the prior, in place;
+        w and P are the capacity-sized buffers (P row-major, stride(1) == 1)."""
+        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] < n_new or P.shape[1] < n_new:
+            raise ValueError("P must be a row-major tensor of at least n_new x n_new")
+        if w.numel() < n_new:
+            raise ValueError("w must hold n_new entries")
+        pc = params.c()
+        self._check(self.lib.rbf_state_grow(
+            self.h, C.byref(pc), _ptr(w, torch.float64, "w", self.device),
+            P.data_ptr() if P.dtype == torch.float64 and P.is_cuda else None, P.stride(0),
+            n_old, n_new), "rbf_state_grow")
+
     def grid(self, params: Params, centers: torch.Tensor) -> "Grid":
         return Grid(self, params, centers)
 

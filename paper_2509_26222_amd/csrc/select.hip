@@ -116,6 +116,103 @@ __global__ void __launch_bounds__(256) k_compact_nodes(const int32_t* __restrict
   out[2 * k + 1] = node_y(m, (int)(c / m.nx));
 }
 
+// Growing selection: flag[c] = 1 iff this call's points take the running
+// count of node c past thr (old <= thr < old + frame).
+__global__ void __launch_bounds__(256) k_grow_flags(const int32_t* __restrict__ frame,
+                                                    const int32_t* __restrict__ counts,
+                                                    int64_t n, int32_t thr,
+                                                    int64_t* __restrict__ flag) {
+  int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int32_t old = counts[c];
+  flag[c] = (old <= thr && old + frame[c] > thr) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_grow_commit(const int32_t* __restrict__ frame,
+                                                     int32_t* __restrict__ counts, int64_t n) {
+  int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < n) counts[c] += frame[c];
+}
+
+// Nodes flagged in the exclusive scan pos (pos[c + 1] > pos[c]) written in
+// mesh order.
+__global__ void __launch_bounds__(256) k_compact_flagged(const int64_t* __restrict__ pos, Mesh m,
+                                                         double* __restrict__ out, int64_t cap) {
+  int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= (int64_t)m.nx * m.ny || pos[c + 1] == pos[c]) return;
+  const int64_t k = pos[c];
+  if (k >= cap) return;
+  out[2 * k] = node_x(m, (int)(c % m.nx));
+  out[2 * k + 1] = node_y(m, (int)(c / m.nx));
+}
+
+// Argument checks of both selection entry points; the mesh on success.
+static rbf_status select_check(rbf_ctx* ctx, const char* fn, const double* xy, int64_t M,
+                               const double* roi, double res, double r_kd, int32_t mode,
+                               double* centers_out, int64_t cap, int64_t* n_out, Mesh* m) {
+  if (!roi || !n_out || M < 0 || M >= ((int64_t)1 << 31) || (M > 0 && !xy) || cap < 0 ||
+      (cap > 0 && !centers_out))
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: bad pointer or size", fn);
+  if (mode != RBF_SELECT_RADIUS && mode != RBF_SELECT_VOXEL)
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: unknown mode %d", fn, mode);
+  for (int q = 0; q < 4; ++q)
+    if (!std::isfinite(roi[q])) return fail(ctx, RBF_E_INVALID_ARG, "%s: roi", fn);
+  if (!(res > 0) || !std::isfinite(res) || (mode == RBF_SELECT_RADIUS && !(r_kd >= 0)))
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: res/r_kd", fn);
+  const double nxd = std::ceil((roi[2] - roi[0]) / res);
+  const double nyd = std::ceil((roi[3] - roi[1]) / res);
+  if (!(nxd >= 1) || !(nyd >= 1) || nxd * nyd > double(1 << 28))
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: empty or huge mesh", fn);
+  if (mode == RBF_SELECT_RADIUS && r_kd / res > 64.0)
+    return fail(ctx, RBF_E_INVALID_ARG, "%s: r_kd > 64 res", fn);
+  *m = Mesh{roi[0], roi[1], res, (int32_t)nxd, (int32_t)nyd};
+  return RBF_OK;
+}
+
+// Support counts of the mesh nodes from the M points (this call's points
+// only) into cnt (nx * ny int32, workspace).
+static rbf_status count_nodes(rbf_ctx* ctx, const double* xy, int64_t M, const Mesh& m,
+                              double r_kd, int32_t mode, int32_t* cnt) {
+  const int64_t nc = (int64_t)m.nx * m.ny;
+  rbf_status st;
+  if (mode == RBF_SELECT_VOXEL) {
+    RBF_TRY(fill_zero(ctx, cnt, sizeof(int32_t) * nc));
+    if (M > 0) {
+      k_voxel_count<<<ceil_div(M, 256), 256, 0, ctx->stream>>>(xy, M, m, cnt);
+      RBF_LAUNCHED(ctx, "k_voxel_count");
+    }
+    return RBF_OK;
+  }
+  const int32_t reach = (int32_t)std::ceil(r_kd / m.res) + 1;
+  const int32_t ext = reach;
+  const int64_t ne = (int64_t)(m.nx + 2 * ext) * (m.ny + 2 * ext);
+  int32_t* key = (int32_t*)ws_get(ctx, WS_SORT0, sizeof(int32_t) * (M > 0 ? M : 1), &st);
+  if (!key) return st;
+  int32_t* start = (int32_t*)ws_get(ctx, WS_SORT1, sizeof(int32_t) * (ne + 1), &st);
+  if (!start) return st;
+  int32_t* cursor = (int32_t*)ws_get(ctx, WS_SORT2, sizeof(int32_t) * (ne + 1), &st);
+  if (!cursor) return st;
+  double* sorted = (double*)ws_get(ctx, WS_TMP1, sizeof(double) * 2 * (M > 0 ? M : 1), &st);
+  if (!sorted) return st;
+  RBF_TRY(fill_zero(ctx, start, sizeof(int32_t) * (ne + 1)));
+  if (M > 0) {
+    k_radius_keys<<<ceil_div(M, 256), 256, 0, ctx->stream>>>(xy, M, m, ext, key, start);
+    RBF_LAUNCHED(ctx, "k_radius_keys");
+  }
+  k_scan_excl_i32<<<1, 1024, 0, ctx->stream>>>(start, ne);
+  RBF_LAUNCHED(ctx, "k_scan_excl_i32");
+  RBF_HIP(ctx, hipMemcpyAsync(cursor, start, sizeof(int32_t) * ne, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+  if (M > 0) {
+    k_radius_scatter<<<ceil_div(M, 256), 256, 0, ctx->stream>>>(xy, M, key, cursor, sorted);
+    RBF_LAUNCHED(ctx, "k_radius_scatter");
+  }
+  k_radius_count<<<ceil_div(nc, 256), 256, 0, ctx->stream>>>(sorted, start, m, ext, reach,
+                                                             r_kd * r_kd, cnt);
+  RBF_LAUNCHED(ctx, "k_radius_count");
+  return RBF_OK;
+}
+
 }  // namespace rbf
 
 using namespace rbf;
@@ -125,64 +222,16 @@ extern "C" rbf_status rbf_select_centers(rbf_ctx* ctx, const double* xy, int64_t
                                          int32_t thr, int32_t mode, double* centers_out,
                                          int64_t cap, int64_t* n_out) {
   if (!ctx) return RBF_E_INVALID_ARG;
-  if (!roi || !n_out || M < 0 || M >= ((int64_t)1 << 31) || (M > 0 && !xy) || cap < 0 ||
-      (cap > 0 && !centers_out))
-    return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers: bad pointer or size");
-  if (mode != RBF_SELECT_RADIUS && mode != RBF_SELECT_VOXEL)
-    return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers: unknown mode %d", mode);
-  for (int q = 0; q < 4; ++q)
-    if (!std::isfinite(roi[q])) return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers: roi");
-  if (!(res > 0) || !std::isfinite(res) || (mode == RBF_SELECT_RADIUS && !(r_kd >= 0)))
-    return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers: res/r_kd");
-  const double nxd = std::ceil((roi[2] - roi[0]) / res);
-  const double nyd = std::ceil((roi[3] - roi[1]) / res);
-  if (!(nxd >= 1) || !(nyd >= 1) || nxd * nyd > double(1 << 28))
-    return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers: empty or huge mesh");
+  Mesh m;
+  RBF_TRY(select_check(ctx, "rbf_select_centers", xy, M, roi, res, r_kd, mode, centers_out, cap,
+                       n_out, &m));
   *n_out = 0;
   RBF_TRY(set_device(ctx));
-  Mesh m{roi[0], roi[1], res, (int32_t)nxd, (int32_t)nyd};
   const int64_t nc = (int64_t)m.nx * m.ny;
   rbf_status st;
   int32_t* cnt = (int32_t*)ws_get(ctx, WS_TMP0, sizeof(int32_t) * nc, &st);
   if (!cnt) return st;
-  if (mode == RBF_SELECT_VOXEL) {
-    RBF_TRY(fill_zero(ctx, cnt, sizeof(int32_t) * nc));
-    if (M > 0) {
-      k_voxel_count<<<ceil_div(M, 256), 256, 0, ctx->stream>>>(xy, M, m, cnt);
-      RBF_LAUNCHED(ctx, "k_voxel_count");
-    }
-  } else {
-    const double rr = r_kd / res;
-    if (rr > 64.0)
-      return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers: r_kd > 64 res");
-    const int32_t reach = (int32_t)std::ceil(rr) + 1;
-    const int32_t ext = reach;
-    const int64_t ne = (int64_t)(m.nx + 2 * ext) * (m.ny + 2 * ext);
-    int32_t* key = (int32_t*)ws_get(ctx, WS_SORT0, sizeof(int32_t) * (M > 0 ? M : 1), &st);
-    if (!key) return st;
-    int32_t* start = (int32_t*)ws_get(ctx, WS_SORT1, sizeof(int32_t) * (ne + 1), &st);
-    if (!start) return st;
-    int32_t* cursor = (int32_t*)ws_get(ctx, WS_SORT2, sizeof(int32_t) * (ne + 1), &st);
-    if (!cursor) return st;
-    double* sorted = (double*)ws_get(ctx, WS_TMP1, sizeof(double) * 2 * (M > 0 ? M : 1), &st);
-    if (!sorted) return st;
-    RBF_TRY(fill_zero(ctx, start, sizeof(int32_t) * (ne + 1)));
-    if (M > 0) {
-      k_radius_keys<<<ceil_div(M, 256), 256, 0, ctx->stream>>>(xy, M, m, ext, key, start);
-      RBF_LAUNCHED(ctx, "k_radius_keys");
-    }
-    k_scan_excl_i32<<<1, 1024, 0, ctx->stream>>>(start, ne);
-    RBF_LAUNCHED(ctx, "k_scan_excl_i32");
-    RBF_HIP(ctx, hipMemcpyAsync(cursor, start, sizeof(int32_t) * ne, hipMemcpyDeviceToDevice,
-                                ctx->stream));
-    if (M > 0) {
-      k_radius_scatter<<<ceil_div(M, 256), 256, 0, ctx->stream>>>(xy, M, key, cursor, sorted);
-      RBF_LAUNCHED(ctx, "k_radius_scatter");
-    }
-    k_radius_count<<<ceil_div(nc, 256), 256, 0, ctx->stream>>>(sorted, start, m, ext, reach,
-                                                               r_kd * r_kd, cnt);
-    RBF_LAUNCHED(ctx, "k_radius_count");
-  }
+  RBF_TRY(count_nodes(ctx, xy, M, m, r_kd, mode, cnt));
   int64_t* pos = (int64_t*)ws_get(ctx, WS_TMP3, sizeof(int64_t) * (nc + 1), &st);
   if (!pos) return st;
   k_accept_flags<<<ceil_div(nc, 256), 256, 0, ctx->stream>>>(cnt, nc, thr, pos);
@@ -202,5 +251,45 @@ extern "C" rbf_status rbf_select_centers(rbf_ctx* ctx, const double* xy, int64_t
   if (total > cap)
     return fail(ctx, RBF_E_CAPACITY, "rbf_select_centers: %lld nodes accepted, cap %lld",
                 (long long)total, (long long)cap);
+  return RBF_OK;
+}
+
+extern "C" rbf_status rbf_select_centers_grow(rbf_ctx* ctx, const double* xy, int64_t M,
+                                              const double* roi, double res, double r_kd,
+                                              int32_t thr, int32_t mode, int32_t* counts,
+                                              double* centers_out, int64_t cap,
+                                              int64_t* n_new) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  Mesh m;
+  RBF_TRY(select_check(ctx, "rbf_select_centers_grow", xy, M, roi, res, r_kd, mode,
+                       centers_out, cap, n_new, &m));
+  if (!counts) return fail(ctx, RBF_E_INVALID_ARG, "rbf_select_centers_grow: null counts");
+  *n_new = 0;
+  RBF_TRY(set_device(ctx));
+  const int64_t nc = (int64_t)m.nx * m.ny;
+  rbf_status st;
+  int32_t* cnt = (int32_t*)ws_get(ctx, WS_TMP0, sizeof(int32_t) * nc, &st);
+  if (!cnt) return st;
+  RBF_TRY(count_nodes(ctx, xy, M, m, r_kd, mode, cnt));
+  int64_t* pos = (int64_t*)ws_get(ctx, WS_TMP3, sizeof(int64_t) * (nc + 1), &st);
+  if (!pos) return st;
+  k_grow_flags<<<ceil_div(nc, 256), 256, 0, ctx->stream>>>(cnt, counts, nc, thr, pos);
+  RBF_LAUNCHED(ctx, "k_grow_flags");
+  k_scan_excl_i64<<<1, 1024, 0, ctx->stream>>>(pos, nc);
+  RBF_LAUNCHED(ctx, "k_scan_excl_i64");
+  int64_t total = 0;
+  RBF_HIP(ctx, hipMemcpyAsync(&total, pos + nc, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (total > cap)  // nothing committed: the running counts stay as they were
+    return fail(ctx, RBF_E_CAPACITY, "rbf_select_centers_grow: %lld new nodes, cap %lld",
+                (long long)total, (long long)cap);
+  if (total > 0) {
+    k_compact_flagged<<<ceil_div(nc, 256), 256, 0, ctx->stream>>>(pos, m, centers_out, cap);
+    RBF_LAUNCHED(ctx, "k_compact_flagged");
+  }
+  k_grow_commit<<<ceil_div(nc, 256), 256, 0, ctx->stream>>>(cnt, counts, nc);
+  RBF_LAUNCHED(ctx, "k_grow_commit");
+  *n_new = total;
   return RBF_OK;
 }

@@ -54,6 +54,9 @@ def test_null_arguments_are_rejected_on_host():
                                  None, None, None) == E
     assert lib.rbf_select_centers(None, None, 0, None, 0.5, 0.5, 0, 0, None, 0,
                                   None) == E
+    assert lib.rbf_select_centers_grow(None, None, 0, None, 0.5, 0.5, 0, 0, None, None, 0,
+                                       None) == E
+    assert lib.rbf_state_grow(None, None, None, None, 0, 0, 0) == E
     assert lib.rbf_last_error_index(None) == -1
 
 
