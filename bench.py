@@ -154,7 +154,8 @@ def rows_leg(ctx, api, synth, L, od, allxy, centers, grid, frame, w, p, reps=3):
     its workload size (wall time of the library calls, synchronised): center
     selection and binning over the odometry map, Phi and Gram assembly of a
     frame, the sparse solve of the 40k-center information form (FP64 factor,
-    FP64 refinement to 1e-10) and the adjoint of the evaluation."""
+    FP64 refinement to 1e-10), the adjoint of the evaluation and the growing
+    selection on one frame."""
     import torch
     import numpy as np
 
@@ -176,6 +177,16 @@ def rows_leg(ctx, api, synth, L, od, allxy, centers, grid, frame, w, p, reps=3):
     t = timed(lambda: ctx.grid(p, centers).close())
     out["a2_bin_centers"] = {"ms": t * 1e3, "centers": int(centers.shape[0])}
     xy, z, pts, pose = frame
+    # growing center set: one frame's points added to running counts
+    nodes = int(round((od.roi[2] - od.roi[0]) / 0.5 * (od.roi[3] - od.roi[1]) / 0.5))
+    counts = torch.zeros(nodes, dtype=torch.int32, device=xy.device)
+
+    def grow_select():
+        counts.zero_()
+        ctx.select_centers_grow(xy, od.roi, 0.5, 0.5, 4, counts, mode=L.SELECT_VOXEL)
+
+    t = timed(grow_select)
+    out["next_select_centers_grow"] = {"ms": t * 1e3, "points": int(xy.shape[0])}
     t = timed(lambda: ctx.assemble_phi(p, grid, xy))
     out["a3_assemble_phi"] = {"ms": t * 1e3, "points": int(xy.shape[0])}
     t = timed(lambda: ctx.gram_pattern(p, grid))
