@@ -264,6 +264,11 @@ rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream) {
     delete c;
     return RBF_E_HIP;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
+    c->cu_count = cus;
+  else
+    (void)hipGetLastError();
   if (hipMalloc(&c->d_status, STATUS_WORDS * sizeof(int32_t)) != hipSuccess) {
     delete c;
     return RBF_E_NOMEM;

@@ -29,6 +29,7 @@ enum WsSlot {
   WS_UPD_TILES, // update: SYRK tile schedule
   WS_UPD_UT2,   // update: second U^T / V^T buffer (batches alternate)
   WS_UPD_FLAGS, // update: touched 128-row blocks of P, two batches
+  WS_UPD_GROUPS,// update: per 64-row group, the distinct rows of P and dense H
   WS_ACT_IDX,   // active-rows update: flags / compact map, active list, w_A
   WS_ACT_P,     // active-rows update: compact block P_AA
   WS_SOLVE0,
@@ -76,6 +77,7 @@ struct rbf_ctx {
   int32_t prof_dropped[RBF_PROF_KINDS];
   int32_t owns_stream;  // stream created by the library (batched branches)
   int64_t index_base;   // added to the batch index rbf_update records
+  int32_t cu_count;     // compute units of the device (0: unknown)
 };
 
 struct rbf_grid {

@@ -46,36 +46,40 @@ __device__ inline int64_t xcd_tile(int64_t per_xcd) {
 // at row (i*256 + tid) / 64, column 2 ((i*256 + tid) % 64), so one wave
 // reads one 1 KB row run and writes it to LDS with 16-byte stores that touch
 // every bank once (zero outside [0, N) x [0, K)).
-template <int NT>
+// W = 64: the 16 x 64 slice of a 64-column panel, the same way (one wave
+// covers two rows).
+template <int NT, int W = 128>
 __device__ inline void load_stage(const double* __restrict__ Ut, int64_t ldu, int64_t N, int r0,
-                                  int K, int64_t c0, double2 v[1024 / NT]) {
+                                  int K, int64_t c0, double2 v[16 * W / 2 / NT]) {
+  constexpr int H = W / 2;  // double2 per row
   const int tid = threadIdx.x;
-  if (r0 + 16 <= K && c0 + 128 <= N) {  // whole slice inside: no per-load tests
+  if (r0 + 16 <= K && c0 + W <= N) {  // whole slice inside: no per-load tests
 #pragma unroll
-    for (int i = 0; i < 1024 / NT; ++i) {
+    for (int i = 0; i < 16 * H / NT; ++i) {
       const int e = i * NT + tid;
-      v[i] = *reinterpret_cast<const double2*>(Ut + (int64_t)(r0 + (e >> 6)) * ldu + c0 +
-                                               2 * (e & 63));
+      v[i] = *reinterpret_cast<const double2*>(Ut + (int64_t)(r0 + e / H) * ldu + c0 +
+                                               2 * (e % H));
     }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 1024 / NT; ++i) {
+  for (int i = 0; i < 16 * H / NT; ++i) {
     const int e = i * NT + tid;
-    const int r = r0 + (e >> 6);
-    const int64_t c = c0 + 2 * (e & 63);
+    const int r = r0 + e / H;
+    const int64_t c = c0 + 2 * (e % H);
     v[i].x = (r < K && c < N) ? Ut[(int64_t)r * ldu + c] : 0.0;
     v[i].y = (r < K && c + 1 < N) ? Ut[(int64_t)r * ldu + c + 1] : 0.0;
   }
 }
 
-template <int NT, int LD>
-__device__ inline void store_stage(double (*X)[LD], const double2 v[1024 / NT]) {
+template <int NT, int LD, int W = 128>
+__device__ inline void store_stage(double (*X)[LD], const double2 v[16 * W / 2 / NT]) {
+  constexpr int H = W / 2;
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < 1024 / NT; ++i) {
+  for (int i = 0; i < 16 * H / NT; ++i) {
     const int e = i * NT + tid;
-    *reinterpret_cast<double2*>(&X[e >> 6][2 * (e & 63)]) = v[i];
+    *reinterpret_cast<double2*>(&X[e / H][2 * (e % H)]) = v[i];
   }
 }
 
@@ -152,6 +156,99 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P,
       for (int v = 0; v < 4; ++v) {
         const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * v + (lane >> 4);
         const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+        if (gi < N && gj < N && (!diag || gi >= gj)) {
+          const double nv = P[gi * ldp + gj] - acc[mi][ni][v];
+          P[gi * ldp + gj] = nv;
+          if (gi != gj) P[gj * ldp + gi] = nv;
+        }
+      }
+}
+
+// Tail of the FP64 product. A launch of 128x128 tiles runs in rounds of
+// (workgroups per CU x CUs per XCD) tiles per XCD; the tiles past the last
+// full round would leave most CUs idle while they finish. They are computed
+// instead as 64x64 sub-tiles by this kernel (4 waves, each 32 x 32 = 2 x 2
+// MFMA blocks), four per tile (three on the diagonal: the upper-right one
+// is the mirror of the lower-left). Every element accumulates the same
+// MFMAs over k in the same order as in the 128x128 kernel, so the result is
+// bit for bit the same. Local tiles main_per_xcd .. per_xcd - 1 of each XCD.
+constexpr int SUB = 64;
+constexpr int SUB_NT = 256;
+constexpr int SUB_LD = SUB + 8;
+
+__global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P, int64_t ldp,
+                                                          int64_t N,
+                                                          const double* __restrict__ Ut,
+                                                          int64_t ldu, int32_t K, int64_t T,
+                                                          int64_t per_xcd, int64_t main_per_xcd,
+                                                          const int32_t* __restrict__ flags,
+                                                          int part,
+                                                          const int32_t* __restrict__ status,
+                                                          int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  const int64_t bid = blockIdx.x;
+  const int64_t local = main_per_xcd + ((bid >> 3) >> 2);
+  const int sub = (int)((bid >> 3) & 3), si = sub >> 1, sj = sub & 1;
+  if (local >= per_xcd) return;
+  const int64_t t = (bid & 7) * per_xcd + local;
+  if (t >= T) return;
+  int I, J;
+  tile_of(t, &I, &J);
+  if (!tile_in_part(flags, part, I, J)) return;
+  if (I == J && si < sj) return;
+  const int64_t I0 = (int64_t)I * ST + si * SUB, J0 = (int64_t)J * ST + sj * SUB;
+  if (I0 >= N || J0 >= N) return;
+  __shared__ double As[2][SKC][SUB_LD];
+  __shared__ double Bs[2][SKC][SUB_LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // rows wm*32.., columns wn*32..
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int nch = (K + SKC - 1) / SKC;
+  double2 ra[16 * SUB / 2 / SUB_NT], rb[16 * SUB / 2 / SUB_NT];
+  load_stage<SUB_NT, SUB>(Ut, ldu, N, 0, K, I0, ra);
+  load_stage<SUB_NT, SUB>(Ut, ldu, N, 0, K, J0, rb);
+  store_stage<SUB_NT, SUB_LD, SUB>(As[0], ra);
+  store_stage<SUB_NT, SUB_LD, SUB>(Bs[0], rb);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) {
+      load_stage<SUB_NT, SUB>(Ut, ldu, N, (ch + 1) * SKC, K, I0, ra);
+      load_stage<SUB_NT, SUB>(Ut, ldu, N, (ch + 1) * SKC, K, J0, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < SKC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) b[q] = Bs[buf][kr][wn * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+    if (ch + 1 < nch) {
+      store_stage<SUB_NT, SUB_LD, SUB>(As[buf ^ 1], ra);
+      store_stage<SUB_NT, SUB_LD, SUB>(Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
+  }
+  const bool diag = (I == J && si == sj);
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * v + (lane >> 4);
+        const int64_t gj = J0 + wn * 32 + ni * 16 + (lane & 15);
         if (gi < N && gj < N && (!diag || gi >= gj)) {
           const double nv = P[gi * ldp + gj] - acc[mi][ni][v];
           P[gi * ldp + gj] = nv;
@@ -441,10 +538,22 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
   const unsigned grid = (unsigned)(per_xcd * 8);
   rbf_status st;
   if (prec == RBF_F64) {
+    // whole rounds of 128x128 tiles per XCD, the rest as 64x64 sub-tiles
+    const int64_t slots = ctx->cu_count > 0 ? (int64_t)ctx->cu_count / 8 * 2 : 64;
+    const int64_t main_per_xcd = slots > 0 ? per_xcd / slots * slots : per_xcd;
     prof_begin(ctx, RBF_PROF_SYRK);
-    k_syrk_f64<<<grid, SYRK_NT, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T, per_xcd, flags,
-                                                  part, ctx->d_status, seq);
-    RBF_LAUNCHED(ctx, "k_syrk_f64");
+    if (main_per_xcd > 0) {
+      k_syrk_f64<<<(unsigned)(main_per_xcd * 8), SYRK_NT, 0, ctx->stream>>>(
+          P, ldp, N, Ut, ldu, Bc, T, per_xcd, flags, part, ctx->d_status, seq);
+      RBF_LAUNCHED(ctx, "k_syrk_f64");
+    }
+    if (main_per_xcd < per_xcd) {
+      const unsigned gt = (unsigned)((per_xcd - main_per_xcd) * 8 * 4);
+      k_syrk_f64_tail<<<gt, SUB_NT, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T, per_xcd,
+                                                      main_per_xcd, flags, part, ctx->d_status,
+                                                      seq);
+      RBF_LAUNCHED(ctx, "k_syrk_f64_tail");
+    }
     prof_end(ctx, RBF_PROF_SYRK);
     return RBF_OK;
   }

@@ -13,6 +13,7 @@
 //
 // Every kernel returns at once if the context's status word holds an error,
 // so a failed batch leaves (w, P) as they were after the previous batch.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -109,6 +110,135 @@ __global__ void __launch_bounds__(256) k_upd_gather_u(
       if (n < N) Ut[(int64_t)b * ldu + n] = acc[u];
     }
   }
+}
+
+// Grouped gather, step 1 (one workgroup per group of 64 batch rows): the
+// distinct columns of the group's regressor rows (the rows of P it needs)
+// by an LDS bitmap over the N centers, ranked in ascending order by a
+// popcount scan. Writes the list (padded to a multiple of 4 with row 0) and
+// the dense block H_g[rank][row] (zero where a row has no entry).
+__global__ void __launch_bounds__(256) k_gather_groups(
+    const double* __restrict__ vals, const int32_t* __restrict__ cols,
+    const int32_t* __restrict__ nnz, int32_t Bc, int32_t Bp, int32_t kmax, int32_t words,
+    int64_t Rcap, int32_t* __restrict__ glist, int32_t* __restrict__ gR,
+    double* __restrict__ gH, const int32_t* __restrict__ status, int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  extern __shared__ uint32_t gsm[];
+  uint32_t* bits = gsm;
+  int32_t* wbase = (int32_t*)(gsm + words);
+  int32_t* tsum = wbase + words;  // 256 + 1
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x, b0 = 64 * g;
+  int32_t* L = glist + (int64_t)g * Rcap;
+  double* H = gH + (int64_t)g * Rcap * 64;
+  for (int w = tid; w < words; w += 256) bits[w] = 0u;
+  __syncthreads();
+  const int ne = 64 * kmax;
+  for (int e = tid; e < ne; e += 256) {
+    const int b = b0 + (e & 63), q = e >> 6;
+    if (b < Bc && q < nnz[b]) {
+      const int32_t c = cols[(int64_t)q * Bp + b];
+      atomicOr(&bits[c >> 5], 1u << (c & 31));
+    }
+  }
+  __syncthreads();
+  const int per = (words + 255) / 256;
+  const int w0 = tid * per, w1 = min(w0 + per, words);
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+  tsum[tid] = cnt;
+  __syncthreads();
+  if (tid == 0) {  // 256 partial counts, in order
+    int run = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int v = tsum[t];
+      tsum[t] = run;
+      run += v;
+    }
+    tsum[256] = run;
+  }
+  __syncthreads();
+  int base = tsum[tid];
+  for (int w = w0; w < w1; ++w) {
+    wbase[w] = base;
+    uint32_t m = bits[w];
+    while (m) {
+      L[base++] = 32 * w + (__ffs(m) - 1);
+      m &= m - 1u;
+    }
+  }
+  const int R = tsum[256];
+  const int R4 = (R + 3) & ~3;
+  if (tid < R4 - R) L[R + tid] = 0;  // padding ranks: a valid row, zero H
+  if (tid == 0) gR[g] = R4;
+  for (int e = tid; e < R4 * 64; e += 256) H[e] = 0.0;
+  __syncthreads();  // zeros stored before the values below
+  for (int e = tid; e < ne; e += 256) {
+    const int bl = e & 63, b = b0 + bl, q = e >> 6;
+    if (b < Bc && q < nnz[b]) {
+      const int32_t c = cols[(int64_t)q * Bp + b];
+      const int r = wbase[c >> 5] + __popc(bits[c >> 5] & ((1u << (c & 31)) - 1u));
+      H[(int64_t)r * 64 + bl] = vals[(int64_t)q * Bp + b];
+    }
+  }
+}
+
+// Grouped gather, step 2: U^T[b0 + i][n] = sum_r H_g[r][i] P[list[r]][n]
+// on FP64 MFMA, one workgroup per (128 columns, group); wave w owns columns
+// 32w..32w+31 and all 64 rows (4 x 2 blocks of 16 x 16). Rows b >= Bc have
+// no entries and get 0.
+__global__ void __launch_bounds__(256) k_gather_mfma(
+    const double* __restrict__ P, int64_t ldp, int64_t N, const int32_t* __restrict__ glist,
+    const int32_t* __restrict__ gR, const double* __restrict__ gH, int64_t Rcap,
+    double* __restrict__ Ut, int64_t ldu, const int32_t* __restrict__ status, int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = blockIdx.y;
+  const int64_t c0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int32_t* L = glist + (int64_t)g * Rcap;
+  const double* H = gH + (int64_t)g * Rcap * 64;
+  const int R4 = gR[g];
+  v4d acc[4][2];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int kq = lane >> 4, li = lane & 15;
+  int64_t colv[2];
+  bool okc[2];
+#pragma unroll
+  for (int ni = 0; ni < 2; ++ni) {
+    colv[ni] = c0 + 16 * ni + li;
+    okc[ni] = colv[ni] < N;
+    if (!okc[ni]) colv[ni] = 0;  // clamped: a valid address, value masked
+  }
+#pragma unroll 4
+  for (int r = 0; r < R4; r += 4) {
+    const int kr = r + kq;
+    const double* prow = P + (int64_t)L[kr] * ldp;
+    double a[4], bv[2];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) a[mi] = H[(int64_t)kr * 64 + 16 * mi + li];
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const double v = prow[colv[ni]];
+      bv[ni] = okc[ni] ? v : 0.0;
+    }
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+  }
+  const int64_t b0 = 64 * (int64_t)g;
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+      if (okc[ni])
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          Ut[(b0 + 16 * mi + 4 * v + kq) * ldu + colv[ni]] = acc[mi][ni][v];
 }
 
 // S[a][b] (a >= b) = sum_k vals[a,k] U^T[b, cols[a,k]] + R delta_ab; the
@@ -560,6 +690,24 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
   if (!ws->Linv) return st;
   ws->wpart = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (size_t)nblk_max * N, &st);
   if (!ws->wpart) return st;
+  ws->Rcap = 0;
+  ws->glist = nullptr;
+  ws->gR = nullptr;
+  ws->gH = nullptr;
+  if (N <= GATHER_GROUP_NMAX) {
+    const int64_t ng = Bp / 64;
+    int64_t Rcap = std::min<int64_t>(N, (int64_t)64 * kmax);
+    Rcap = (Rcap + 3) / 4 * 4 + 4;
+    char* gw = (char*)ws_get(ctx, WS_UPD_GROUPS,
+                             (size_t)ng * Rcap * (64 * sizeof(double) + sizeof(int32_t)) +
+                                 (size_t)ng * sizeof(int32_t) + 256,
+                             &st);
+    if (!gw) return st;
+    ws->Rcap = Rcap;
+    ws->gH = (double*)gw;
+    ws->glist = (int32_t*)(gw + (size_t)ng * Rcap * 64 * sizeof(double));
+    ws->gR = ws->glist + (size_t)ng * Rcap;
+  }
   if (gemm_prec == RBF_F32) {
     if (!ws_get(ctx, WS_UPD_VLO, sizeof(float) * (size_t)Bp * ldu, &st)) return st;
   } else if (gemm_prec == RBF_BF16) {
@@ -784,10 +932,23 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     double* Ut = UtB[bi & 1];
     const int64_t sq = seq0 + bi;
     prof_begin(ctx, RBF_PROF_GATHER);
-    dim3 gg((unsigned)ceil_div(N, 1024), (unsigned)ceil_div(Bpc, 8));
-    k_upd_gather_u<<<gg, 256, 0, ctx->stream>>>(P, ldp, N, Bc, Bpc, vals, cols, nnz, Ut, ldu,
-                                                 ctx->d_status, sq);
-    RBF_LAUNCHED(ctx, "k_upd_gather_u");
+    if (ws.gH) {
+      const int32_t words = (int32_t)ceil_div(N, 32);
+      const size_t lds = sizeof(uint32_t) * (2 * (size_t)words + 257);
+      k_gather_groups<<<Bpc / 64, 256, lds, ctx->stream>>>(vals, cols, nnz, Bc, Bpc, kmax, words,
+                                                           ws.Rcap, ws.glist, ws.gR, ws.gH,
+                                                           ctx->d_status, sq);
+      RBF_LAUNCHED(ctx, "k_gather_groups");
+      dim3 gm((unsigned)ceil_div(N, 128), (unsigned)(Bpc / 64));
+      k_gather_mfma<<<gm, 256, 0, ctx->stream>>>(P, ldp, N, ws.glist, ws.gR, ws.gH, ws.Rcap, Ut,
+                                                  ldu, ctx->d_status, sq);
+      RBF_LAUNCHED(ctx, "k_gather_mfma");
+    } else {
+      dim3 gg((unsigned)ceil_div(N, 1024), (unsigned)ceil_div(Bpc, 8));
+      k_upd_gather_u<<<gg, 256, 0, ctx->stream>>>(P, ldp, N, Bc, Bpc, vals, cols, nnz, Ut, ldu,
+                                                   ctx->d_status, sq);
+      RBF_LAUNCHED(ctx, "k_upd_gather_u");
+    }
     prof_end(ctx, RBF_PROF_GATHER);
     dim3 gs((unsigned)ceil_div(Bpc, 256), (unsigned)Bpc);
     k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,

@@ -53,7 +53,18 @@ struct UpdWs {
   double* Lb;
   double* Linv;
   double* wpart;
+  // gather by groups of 64 batch rows (when N <= GATHER_GROUP_NMAX): per
+  // group the distinct rows of P its points touch (glist, Rcap entries),
+  // their count rounded up to 4 (gR), and the dense block of H over those
+  // rows (gH, Rcap x 64, rank-major)
+  int32_t* glist;
+  int32_t* gR;
+  double* gH;
+  int64_t Rcap;
 };
+
+// Largest N for the grouped gather (its LDS bitmap has one bit per center).
+constexpr int64_t GATHER_GROUP_NMAX = (int64_t)1 << 17;
 rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
                             rbf_prec gemm_prec, UpdWs* ws);
 
