@@ -257,6 +257,79 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
       }
 }
 
+// Triangular solve of the update as one product: V^T = X U^T with
+// X = L^{-1} (block lower triangular, held transposed in LiT[k][row],
+// leading dimension n, zero above its diagonal blocks) and U^T (n x ncols,
+// leading dimension ldu). Same 128x128 tile, stage loader and MFMA layout
+// as k_syrk_f64; the k-range of row block I stops at its last row
+// ((I + 1) * 128), where X is zero beyond. Heavier row blocks are issued
+// first.
+__global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restrict__ LiT,
+                                                           int32_t n,
+                                                           const double* __restrict__ Ut,
+                                                           int64_t ldu, int64_t ncols,
+                                                           double* __restrict__ Vt, int32_t nJ,
+                                                           const int32_t* __restrict__ status,
+                                                           int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  const int nI = (n + ST - 1) / ST;
+  const int I = nI - 1 - (int)(blockIdx.x / nJ), J = (int)(blockIdx.x % nJ);
+  const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
+  const int K = min(n, (I + 1) * ST);
+  __shared__ double As[2][SKC][SLD];
+  __shared__ double Bs[2][SKC][SLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  v4d acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int nch = (K + SKC - 1) / SKC;
+  double2 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
+  load_stage<SYRK_NT>(LiT, n, n, 0, K, I0, ra);
+  load_stage<SYRK_NT>(Ut, ldu, ncols, 0, K, J0, rb);
+  store_stage<SYRK_NT, SLD>(As[0], ra);
+  store_stage<SYRK_NT, SLD>(Bs[0], rb);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) {
+      load_stage<SYRK_NT>(LiT, n, n, (ch + 1) * SKC, K, I0, ra);
+      load_stage<SYRK_NT>(Ut, ldu, ncols, (ch + 1) * SKC, K, J0, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < SKC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[4];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+    if (ch + 1 < nch) {
+      store_stage<SYRK_NT, SLD>(As[buf ^ 1], ra);
+      store_stage<SYRK_NT, SLD>(Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * v + (lane >> 4);
+        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+        if (gi < n && gj < ncols) Vt[gi * ldu + gj] = acc[mi][ni][v];
+      }
+}
+
 // ------------------------------------------------ low-precision operands
 //
 // FP32: V^T is rounded to float (same k-major layout) and multiplied on
@@ -586,6 +659,17 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
                                                ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_syrk_bf16x3");
   prof_end(ctx, RBF_PROF_SYRK);
+  return RBF_OK;
+}
+
+rbf_status linv_apply(rbf_ctx* ctx, const double* LiT, int32_t n, const double* Ut,
+                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq) {
+  if (n <= 0 || ncols <= 0) return RBF_OK;
+  const int64_t nI = ceil_div(n, ST), nJ = ceil_div(ncols, ST);
+  k_linv_apply<<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(LiT, n, Ut, ldu, ncols, Vt,
+                                                                  (int32_t)nJ, ctx->d_status,
+                                                                  seq);
+  RBF_LAUNCHED(ctx, "k_linv_apply");
   return RBF_OK;
 }
 

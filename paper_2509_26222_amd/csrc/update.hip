@@ -307,13 +307,10 @@ __device__ inline int acc_col(int ni) {
   return 32 * ((threadIdx.x >> 6) & 1) + 16 * ni + (threadIdx.x & 15);
 }
 
-__device__ inline void mm_nt(const double (*X)[LDT], const double (*Y)[LDT], Acc64& A) {
+// A += X Y^T
+__device__ inline void mm_nt_acc(const double (*X)[LDT], const double (*Y)[LDT], Acc64& A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rb = 32 * (wave >> 1), cb = 32 * (wave & 1);
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni) A.c[mi][ni] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int k = 0; k < NB; k += 4) {
     const int kk = k + (lane >> 4);
@@ -331,6 +328,25 @@ __device__ inline void mm_nt(const double (*X)[LDT], const double (*Y)[LDT], Acc
   }
 }
 
+// A = X Y^T
+__device__ inline void mm_nt(const double (*X)[LDT], const double (*Y)[LDT], Acc64& A) {
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) A.c[mi][ni] = (v4d){0.0, 0.0, 0.0, 0.0};
+  mm_nt_acc(X, Y, A);
+}
+
+// A (64x64, leading dimension lda) = T^T: column-ordered walk, so the
+// global stores are coalesced and the LDS reads go down a padded column.
+__device__ inline void store_tile_t(const double (*T)[LDT], double* __restrict__ A, int64_t lda) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    A[(int64_t)(e >> 6) * lda + (e & 63)] = T[e & 63][e >> 6];
+  }
+}
+
 __device__ inline void acc_to_lds(const Acc64& A, double (*T)[LDT]) {
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -344,10 +360,110 @@ __device__ inline void acc_to_lds(const Acc64& A, double (*T)[LDT]) {
 // chol64() in chol64.hpp.
 #include "chol64.hpp"
 
+// Blocks of the inverse X = L^{-1} of the blocked factor, row by row:
+//   X_kj = -Linv_kk Y_kj,   Y_kj = sum_{m=j}^{k-1} L_km X_mj   (j < k).
+// X is held transposed in LiT (LiT[c][r] = X[r][c], leading dimension Bp,
+// zeroed before the factorization): the k-major operand of V^T = X U^T.
+// The sums are spread over the launches so no workgroup walks a whole row:
+// launch kb adds the term m = kb - 1 to the partial sums Y_kj of the rows
+// k > kb (kept, transposed, in LiT's block of X_kj) and finishes row kb
+// with its own last term. Every term is added in order of m.
+
+// Y_kj^T (block (j, k) of LiT) += (L_km X_mj)^T, m = kb - 1, k > kb.
+__device__ inline void linv_accum(int m, int k, int j, int32_t Bp, const double* __restrict__ Lb,
+                                  double* __restrict__ LiT, double (*T1)[LDT],
+                                  double (*T2)[LDT]) {
+  load_tile(T1, Lb + (int64_t)k * NB * Bp + (int64_t)m * NB, Bp);  // L_km
+  load_tile(T2, LiT + (int64_t)j * NB * Bp + (int64_t)m * NB, Bp);  // X_mj^T
+  double* blk = LiT + (int64_t)j * NB * Bp + (int64_t)k * NB;       // Y_kj^T
+  Acc64 Y;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Y.c[mi][ni][v] = blk[(int64_t)acc_col(ni) * Bp + acc_row(mi, v)];
+  __syncthreads();
+  mm_nt_acc(T1, T2, Y);  // Y += L_km X_mj
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        blk[(int64_t)acc_col(ni) * Bp + acc_row(mi, v)] = Y.c[mi][ni][v];
+}
+
+// X_kj (k = kb > j): Y_kj = (partial sum in LiT) + L_k,k-1 X_k-1,j, then
+// X_kj = -Linv_kk Y_kj, written transposed over the partial sum.
+__device__ inline void linv_finish(int kb, int j, int32_t Bp, const double* __restrict__ Lb,
+                                   const double* __restrict__ Linv, double* __restrict__ LiT,
+                                   double (*T1)[LDT], double (*T2)[LDT]) {
+  const int m = kb - 1;
+  load_tile(T1, Lb + (int64_t)kb * NB * Bp + (int64_t)m * NB, Bp);  // L_km
+  load_tile(T2, LiT + (int64_t)j * NB * Bp + (int64_t)m * NB, Bp);  // X_mj^T
+  double* blk = LiT + (int64_t)j * NB * Bp + (int64_t)kb * NB;
+  Acc64 Y;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Y.c[mi][ni][v] = blk[(int64_t)acc_col(ni) * Bp + acc_row(mi, v)];
+  __syncthreads();
+  mm_nt_acc(T1, T2, Y);
+  __syncthreads();  // T1, T2 free
+  load_tile(T1, Linv + (int64_t)kb * NB * NB, NB);  // Linv_kk
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T2[acc_col(ni)][acc_row(mi, v)] = Y.c[mi][ni][v];  // Y^T
+  __syncthreads();
+  Acc64 Z;
+  mm_nt(T2, T1, Z);  // Z = Y^T Linv_kk^T = (Linv_kk Y)^T = -X_kj^T
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        blk[(int64_t)acc_row(mi, v) * Bp + acc_col(ni)] = -Z.c[mi][ni][v];
+}
+
+// The inverse's workgroups of launch kb (kb >= 1): u < kb finishes X_kb,u;
+// the rest add term kb - 1 to the rows below.
+__device__ inline void linv_work(int u, int kb, int32_t Bp, const double* __restrict__ Lb,
+                                 const double* __restrict__ Linv, double* __restrict__ LiT,
+                                 double (*T1)[LDT], double (*T2)[LDT]) {
+  if (u < kb) {
+    linv_finish(kb, u, Bp, Lb, Linv, LiT, T1, T2);
+    return;
+  }
+  u -= kb;
+  linv_accum(kb - 1, kb + 1 + u / kb, u % kb, Bp, Lb, LiT, T1, T2);
+}
+
+// The last block row of L^{-1} (kb = nblk - 1), after the final step.
+__global__ void __launch_bounds__(256) k_linv_row(int32_t Bp, int32_t kb,
+                                                  const double* __restrict__ Lb,
+                                                  const double* __restrict__ Linv,
+                                                  double* __restrict__ LiT,
+                                                  const int32_t* __restrict__ status,
+                                                  int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  __shared__ double T1[NB][LDT], T2[NB][LDT];
+  linv_finish(kb, blockIdx.x, Bp, Lb, Linv, LiT, T1, T2);
+}
+
 // Factor diagonal block 0.
 __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S, int32_t Bp,
                                                     double* __restrict__ Lb,
                                                     double* __restrict__ Linv,
+                                                    double* __restrict__ LiT,
                                                     int32_t* __restrict__ status, int64_t batch,
                                                     int64_t seq) {
   if (seq_skip(status, seq)) return;
@@ -357,23 +473,33 @@ __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S
   chol64(T, Ti, status, batch, seq);
   store_tile(T, Lb, Bp);
   store_tile(Ti, Linv, NB);
+  if (LiT) store_tile_t(Ti, LiT, Bp);
 }
 
 // Step kb of the right-looking blocked Cholesky, one launch per block
 // column. Tiles t < m are panel tiles (i = kb+1+t): L_ik = A_ik Linv_kk^T.
-// The rest are trailing tiles (i, j), kb < j <= i: they recompute L_ik and
+// Then come the trailing tiles (i, j), kb < j <= i: they recompute L_ik and
 // L_jk from A and Linv_kk (read-only in this launch) and update A_ij; tile
-// (kb+1, kb+1) then factors itself, ready for step kb+1.
+// (kb+1, kb+1) then factors itself, ready for step kb+1. With LiT, the
+// launch also carries the inverse's work of step kb (linv_work: kb + kb *
+// (nblk - 1 - kb) workgroups of one or two block products), beside the
+// critical path of the factor.
 __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32_t Bp,
                                                    int32_t nblk, int32_t kb,
                                                    double* __restrict__ Lb,
                                                    double* __restrict__ Linv,
+                                                   double* __restrict__ LiT,
                                                    int32_t* __restrict__ status, int64_t batch,
                                                    int64_t seq) {
   if (seq_skip(status, seq)) return;
   __shared__ double Li[NB][LDT], T1[NB][LDT], T2[NB][LDT];
   const int m = nblk - kb - 1;
   const int t = blockIdx.x;
+  const int nfac = m + m * (m + 1) / 2;
+  if (t >= nfac) {
+    linv_work(t - nfac, kb, Bp, Lb, Linv, LiT, T1, T2);
+    return;
+  }
   int i, j;
   bool panel;
   if (t < m) {
@@ -430,6 +556,7 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
     chol64(Li, T2, status, batch, seq);
     store_tile(Li, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
     store_tile(T2, Linv + (int64_t)i * NB * NB, NB);
+    if (LiT) store_tile_t(T2, LiT + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
     return;
   }
 #pragma unroll
@@ -683,9 +810,13 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
   ws->flags = (int32_t*)ws_get(ctx, WS_UPD_FLAGS,
                                sizeof(int32_t) * 2 * (size_t)ceil_div(N, SYRK_TILE), &st);
   if (!ws->flags) return st;
-  ws->S = (double*)ws_get(ctx, WS_UPD_S, sizeof(double) * (size_t)Bp * Bp * 2, &st);
+  ws->S = (double*)ws_get(ctx, WS_UPD_S, sizeof(double) * (size_t)Bp * Bp * 3, &st);
   if (!ws->S) return st;
   ws->Lb = ws->S + (size_t)Bp * Bp;
+  ws->LiT = ws->Lb + (size_t)Bp * Bp;
+  ws->Vt = (double*)ws_get(ctx, WS_UPD_VT, sizeof(double) * (size_t)Bp * ldu * 2, &st);
+  if (!ws->Vt) return st;
+  ws->Vt2 = ws->Vt + (size_t)Bp * ldu;
   ws->Linv = (double*)ws_get(ctx, WS_UPD_LINV, sizeof(double) * (size_t)nblk_max * NB * NB, &st);
   if (!ws->Linv) return st;
   ws->wpart = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (size_t)nblk_max * N, &st);
@@ -717,15 +848,21 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
 }
 
 rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
-                        int64_t index, int64_t seq) {
+                        int64_t index, int64_t seq, double* LiT) {
   const int32_t nblk = n / NB;
-  k_chol_first<<<1, 256, 0, ctx->stream>>>(S, n, Lb, Linv, ctx->d_status, index, seq);
+  k_chol_first<<<1, 256, 0, ctx->stream>>>(S, n, Lb, Linv, LiT, ctx->d_status, index, seq);
   RBF_LAUNCHED(ctx, "k_chol_first");
   for (int32_t kb = 0; kb + 1 < nblk; ++kb) {
     const int m = nblk - kb - 1;
-    k_chol_step<<<m + m * (m + 1) / 2, 256, 0, ctx->stream>>>(S, n, nblk, kb, Lb, Linv,
-                                                             ctx->d_status, index, seq);
+    const int extra = LiT ? kb + kb * (nblk - 1 - kb) : 0;
+    k_chol_step<<<m + m * (m + 1) / 2 + extra, 256, 0, ctx->stream>>>(
+        S, n, nblk, kb, Lb, Linv, LiT, ctx->d_status, index, seq);
     RBF_LAUNCHED(ctx, "k_chol_step");
+  }
+  if (LiT && nblk > 1) {
+    k_linv_row<<<nblk - 1, 256, 0, ctx->stream>>>(n, nblk - 1, Lb, Linv, LiT, ctx->d_status,
+                                                   seq);
+    RBF_LAUNCHED(ctx, "k_linv_row");
   }
   return RBF_OK;
 }
@@ -903,6 +1040,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
   hipStream_t as = two ? ctx->aux : ctx->stream;
   const int64_t nfl = ceil_div(N, SYRK_TILE);
   double* UtB[2] = {ws.Ut, ws.Ut2};
+  double* VtB[2] = {ws.Vt, ws.Vt2};
   int32_t* Fl[2] = {ws.flags, ws.flags + nfl};
   auto sizes = [&](int64_t bi, int32_t* Bc, int32_t* Bpc) {
     const int64_t s0 = bi * B;
@@ -928,7 +1066,6 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
   auto chain = [&](int64_t bi) -> rbf_status {
     int32_t Bc, Bpc;
     sizes(bi, &Bc, &Bpc);
-    const int32_t nblk = Bpc / NB;
     double* Ut = UtB[bi & 1];
     const int64_t sq = seq0 + bi;
     prof_begin(ctx, RBF_PROF_GATHER);
@@ -954,14 +1091,16 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,
                                          ctx->d_status, sq);
     RBF_LAUNCHED(ctx, "k_upd_S");
+    double* Vt = VtB[bi & 1];
     prof_begin(ctx, RBF_PROF_CHOL);
-    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi, sq));
+    RBF_TRY(fill_zero(ctx, ws.LiT, sizeof(double) * (size_t)Bpc * Bpc));
+    RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi, sq, ws.LiT));
     prof_end(ctx, RBF_PROF_CHOL);
     prof_begin(ctx, RBF_PROF_TRSM);
-    RBF_TRY(trsm_blocks(ctx, Ut, ldu, N + 1, nblk, Lb, Bpc, Linv, false, sq));
+    RBF_TRY(linv_apply(ctx, ws.LiT, Bpc, Ut, ldu, N + 1, Vt, sq));
     prof_end(ctx, RBF_PROF_TRSM);
     dim3 gw((unsigned)ceil_div(N, 256), (unsigned)ceil_div(Bc, 64));
-    k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Ut, ldu, N, Bc, wpart, ctx->d_status, sq);
+    k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Vt, ldu, N, Bc, wpart, ctx->d_status, sq);
     RBF_LAUNCHED(ctx, "k_upd_w_part");
     k_upd_w_sum<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(w, wpart, N, (int32_t)gw.y,
                                                            ctx->d_status, sq);
@@ -985,7 +1124,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
       sizes(bi, &Bc, &Bpc);
       RBF_TRY(rows(bi));
       RBF_TRY(chain(bi));
-      RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec, nullptr, 0,
+      RBF_TRY(syrk_update(ctx, P, ldp, N, VtB[bi & 1], ldu, Bc, gemm_prec, nullptr, 0,
                           seq0 + bi));
     }
   } else {
@@ -1006,7 +1145,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     RBF_HIP(ctx, hipStreamWaitEvent(ms, ctx->ev_back, 0));
     // part 1: tiles in the row/column blocks batch bi+1 touches (all tiles
     // for the last batch)
-    RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec,
+    RBF_TRY(syrk_update(ctx, P, ldp, N, VtB[bi & 1], ldu, Bc, gemm_prec,
                         more ? Fl[(bi + 1) & 1] : nullptr, more ? 1 : 0, seq0 + bi));
     if (!more) break;
     RBF_HIP(ctx, hipEventRecord(ctx->ev_fwd, ms));
@@ -1018,7 +1157,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
       RBF_HIP(ctx, hipEventRecord(ctx->ev_back, as));
     }
     // part 2: the remaining tiles, concurrent with the chain above
-    RBF_TRY(syrk_update(ctx, P, ldp, N, UtB[bi & 1], ldu, Bc, gemm_prec, Fl[(bi + 1) & 1], 2,
+    RBF_TRY(syrk_update(ctx, P, ldp, N, VtB[bi & 1], ldu, Bc, gemm_prec, Fl[(bi + 1) & 1], 2,
                         seq0 + bi));
   }
   return RBF_OK;

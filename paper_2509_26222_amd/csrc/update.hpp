@@ -47,7 +47,10 @@ struct UpdWs {
   int32_t* cols;
   int32_t* nnz;
   double* Ut;
-  double* Ut2;     // second U^T / V^T buffer (consecutive batches alternate)
+  double* Ut2;     // second U^T buffer (consecutive batches alternate)
+  double* Vt;      // V^T = L^{-1} U^T, two buffers (consecutive batches alternate)
+  double* Vt2;
+  double* LiT;     // L^{-1} transposed (Bp x Bp)
   int32_t* flags;  // 2 x ceil(N / SYRK_TILE) touched-block flags
   double* S;
   double* Lb;
@@ -76,7 +79,15 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
 // records RBF_E_NOT_SPD with `index` in the status word. Launches belong to
 // launch group seq.
 rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* Linv,
-                        int64_t index, int64_t seq);
+                        int64_t index, int64_t seq, double* LiT = nullptr);
+
+// With LiT (n x n, leading dimension n, zero above the diagonal blocks on
+// entry), chol_blocked also forms X = L^{-1} transposed: LiT[c][r] = X[r][c].
+// linv_apply then computes V^T = X U^T (n x ncols, rows of U^T with leading
+// dimension ldu) into Vt (leading dimension ldu) on FP64 MFMA: the block
+// triangular solve as one product.
+rbf_status linv_apply(rbf_ctx* ctx, const double* LiT, int32_t n, const double* Ut,
+                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq);
 
 // X := L^{-1} X (trans = false) or X := L^{-T} X (trans = true) in place for
 // X with nblk*64 rows, ncols columns and leading dimension ldx, with L given
