@@ -32,7 +32,9 @@ constexpr int LDT = NB + 1;  // padded LDS row of a 64x64 tile
 // Regressor rows of the batch in column-major ELL (entry q of row b at
 // q * Bp + b), and the innovation y = z - H w into U^T[:, N]. With colmap,
 // a center's column is colmap[center] (the compact index of an active
-// center), else the center's own index.
+// center), else the center's own index. 16 lanes per point test the
+// candidates 16 at a time; a ballot and popcount prefix keep the entries in
+// candidate order (the order of a serial scan), capped at kmax.
 __global__ void __launch_bounds__(256) k_upd_rows(
     const double* __restrict__ xy, const double* __restrict__ z, int32_t Bc, int32_t Bp,
     const double* __restrict__ cxy, const int32_t* __restrict__ idx,
@@ -41,11 +43,14 @@ __global__ void __launch_bounds__(256) k_upd_rows(
     const double* __restrict__ w, double* __restrict__ vals, int32_t* __restrict__ cols,
     int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu, int64_t N,
     int32_t* __restrict__ status, int64_t batch, int64_t seq) {
-  const int b = blockIdx.x * 256 + threadIdx.x;
+  const int tid = threadIdx.x, l = tid & 15, gshift = tid & 48;
+  const int b = blockIdx.x * 16 + (tid >> 4);
   if (b >= Bp || seq_skip(status, seq)) return;
   if (b >= Bc) {
-    nnz[b] = 0;
-    Ut[(int64_t)b * ldu + N] = 0.0;
+    if (l == 0) {
+      nnz[b] = 0;
+      Ut[(int64_t)b * ldu + N] = 0.0;
+    }
     return;
   }
   const double x = xy[2 * b], y = xy[2 * b + 1];
@@ -57,26 +62,38 @@ __global__ void __launch_bounds__(256) k_upd_rows(
     for (int by = by0; by <= by1; ++by) {
       const int row = by * g.nbx;
       const int s0 = start[row + bx0], s1 = start[row + bx1 + 1];
-      for (int s = s0; s < s1; ++s) {
-        const double dx = __dsub_rn(x, cxy[2 * s]), dy = __dsub_rn(y, cxy[2 * s + 1]);
-        const double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
-        if (d2 <= k.rc2 && n < kmax) {
+      for (int base = s0; base < s1; base += 16) {
+        const int s = base + l;
+        bool ok = false;
+        double d2 = 0.0;
+        if (s < s1) {
+          const double dx = __dsub_rn(x, cxy[2 * s]), dy = __dsub_rn(y, cxy[2 * s + 1]);
+          d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+          ok = d2 <= k.rc2;
+        }
+        const uint32_t gm = (uint32_t)(__ballot(ok) >> gshift) & 0xFFFFu;
+        const int pos = n + __popc(gm & ((1u << l) - 1u));
+        if (ok && pos < kmax) {
           const double v = k.scale * exp(-d2 / k.den);
           const int32_t c = colmap ? colmap[idx[s]] : idx[s];
-          vals[(int64_t)n * Bp + b] = v;
-          cols[(int64_t)n * Bp + b] = c;
+          vals[(int64_t)pos * Bp + b] = v;
+          cols[(int64_t)pos * Bp + b] = c;
           hw += v * w[c];
-          ++n;
         }
+        n = min(n + __popc(gm), kmax);
       }
     }
   }
-  nnz[b] = n;
-  const double zb = z[b];
-  const double yb = zb - hw;
-  if (!isfinite(zb) || !isfinite(yb) || !isfinite(x) || !isfinite(y))
-    set_status(status, RBF_E_NONFINITE, batch, seq);
-  Ut[(int64_t)b * ldu + N] = yb;
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) hw += __shfl_xor(hw, off, 16);
+  if (l == 0) {
+    nnz[b] = n;
+    const double zb = z[b];
+    const double yb = zb - hw;
+    if (!isfinite(zb) || !isfinite(yb) || !isfinite(x) || !isfinite(y))
+      set_status(status, RBF_E_NONFINITE, batch, seq);
+    Ut[(int64_t)b * ldu + N] = yb;
+  }
 }
 
 // U^T[b, n] = sum_k vals[b,k] P[cols[b,k], n]  (P symmetric: rows of P).
@@ -265,6 +282,54 @@ __global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
     s = (a == b) ? 1.0 : 0.0;
   }
   S[(int64_t)a * Bp + b] = s;
+}
+
+// The same lower triangle of S from the grouped gather's data: workgroup
+// (ga, gb), gb <= ga, computes S[a][b] for the 64 rows a of group ga and the
+// 64 columns b of block gb as sum_r H_ga[r][a] U^T[b][list_ga[r]] on FP64
+// MFMA (wave w: columns 16w..16w+15, all 64 rows).
+__global__ void __launch_bounds__(256) k_upd_S_groups(
+    const int32_t* __restrict__ glist, const int32_t* __restrict__ gR,
+    const double* __restrict__ gH, int64_t Rcap, const double* __restrict__ Ut, int64_t ldu,
+    int32_t Bc, int32_t Bp, double R, double* __restrict__ S,
+    const int32_t* __restrict__ status, int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  const int t = blockIdx.x;
+  int ga = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ga + 1) * (ga + 2) / 2 <= t) ++ga;
+  while (ga * (ga + 1) / 2 > t) --ga;
+  const int gb = t - ga * (ga + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kq = lane >> 4, li = lane & 15;
+  const int32_t* L = glist + (int64_t)ga * Rcap;
+  const double* H = gH + (int64_t)ga * Rcap * 64;
+  const int R4 = gR[ga];
+  const int bcol = gb * 64 + wave * 16 + li;  // < Bp
+  const double* urow = Ut + (int64_t)bcol * ldu;
+  v4d acc[4];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi) acc[mi] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < R4; r += 4) {
+    const int kr = r + kq;
+    const double bv = urow[L[kr]];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+      acc[mi] = __builtin_amdgcn_mfma_f64_16x16x4f64(H[(int64_t)kr * 64 + 16 * mi + li], bv,
+                                                     acc[mi], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = ga * 64 + 16 * mi + 4 * v + kq;
+      if (a < bcol) continue;
+      double sv;
+      if (a < Bc && bcol < Bc)
+        sv = acc[mi][v] + ((a == bcol) ? R : 0.0);
+      else
+        sv = (a == bcol) ? 1.0 : 0.0;
+      S[(int64_t)a * Bp + bcol] = sv;
+    }
 }
 
 // ------------------------------------------------------------- 64x64 tiles
@@ -1047,15 +1112,17 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     *Bc = (int32_t)((M - s0) < B ? (M - s0) : B);
     *Bpc = (int32_t)ceil_div(*Bc, NB) * NB;
   };
-  // regressor rows, innovation y = z - H w and touched blocks of batch bi
+  // regressor rows, innovation y = z - H w and (two streams) touched blocks
+  // of batch bi
   auto rows = [&](int64_t bi) -> rbf_status {
     int32_t Bc, Bpc;
     sizes(bi, &Bc, &Bpc);
     const int64_t s0 = bi * B;
-    k_upd_rows<<<ceil_div(Bpc, 256), 256, 0, ctx->stream>>>(
+    k_upd_rows<<<ceil_div(Bpc, 16), 256, 0, ctx->stream>>>(
         xy + 2 * s0, z + s0, Bc, Bpc, g->d_cxy, g->d_idx, colmap, g->d_start, geom(g), rk, kmax, w,
         vals, cols, nnz, UtB[bi & 1], ldu, N, ctx->d_status, ctx->index_base + bi, seq0 + bi);
     RBF_LAUNCHED(ctx, "k_upd_rows");
+    if (!two) return RBF_OK;  // the touched blocks only steer the two-stream split
     RBF_TRY(fill_zero(ctx, Fl[bi & 1], sizeof(int32_t) * nfl));
     k_upd_flags<<<ceil_div(Bc, 256), 256, 0, ctx->stream>>>(cols, nnz, Bc, Bpc, Fl[bi & 1],
                                                              ctx->d_status, seq0 + bi);
@@ -1087,10 +1154,17 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
       RBF_LAUNCHED(ctx, "k_upd_gather_u");
     }
     prof_end(ctx, RBF_PROF_GATHER);
-    dim3 gs((unsigned)ceil_div(Bpc, 256), (unsigned)Bpc);
-    k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,
-                                         ctx->d_status, sq);
-    RBF_LAUNCHED(ctx, "k_upd_S");
+    if (ws.gH) {
+      const int ng = Bpc / 64;
+      k_upd_S_groups<<<ng * (ng + 1) / 2, 256, 0, ctx->stream>>>(
+          ws.glist, ws.gR, ws.gH, ws.Rcap, Ut, ldu, Bc, Bpc, p->R, S, ctx->d_status, sq);
+      RBF_LAUNCHED(ctx, "k_upd_S_groups");
+    } else {
+      dim3 gs((unsigned)ceil_div(Bpc, 256), (unsigned)Bpc);
+      k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,
+                                           ctx->d_status, sq);
+      RBF_LAUNCHED(ctx, "k_upd_S");
+    }
     double* Vt = VtB[bi & 1];
     prof_begin(ctx, RBF_PROF_CHOL);
     RBF_TRY(fill_zero(ctx, ws.LiT, sizeof(double) * (size_t)Bpc * Bpc));
