@@ -29,11 +29,12 @@ METRIC = ("rbf_eval Mpts/s + scan updates/s (10k centers) at stated err; "
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# HBM bytes of one k_syrk_f64 launch (all lower tiles) at N = 10,000, batch 1024,
-# from rocprofv3 FETCH_SIZE (x2.0, the copy-kernel calibration) + WRITE_SIZE (x1.0);
-# summary in profiles/k_syrk_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid
-# only for that kernel version and shape (None otherwise).
-SYRK_F64_TRAFFIC = {(10000, 1024): 3.5551e9 + 0.8186e9}
+# HBM bytes of one covariance product (k_syrk_f64 over whole rounds of tiles +
+# k_syrk_f64_tail over the rest) at N = 10,000, batch 1024, from rocprofv3
+# FETCH_SIZE (x2.0, the copy-kernel calibration) + WRITE_SIZE (x1.0); summary
+# in profiles/k_syrk_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid only for
+# those kernel versions and that shape (None otherwise).
+SYRK_F64_TRAFFIC = {(10000, 1024): 3.5557e9 + 0.8188e9}
 
 
 def parse():
@@ -472,7 +473,7 @@ def main():
             "sigma": p.sigma, "cutoff": p.cutoff, "lambda": p.lam, "R": p.R,
         },
         "roofline": {
-            "kernel": "k_syrk_f64 (P -= V V^T, FP64 MFMA)",
+            "kernel": "k_syrk_f64 + k_syrk_f64_tail (P -= V V^T, FP64 MFMA)",
             "bound": "mfma",
             "achieved": syrk_tfs,
             "peak": PEAK_FP64_TFLOPS,
@@ -483,9 +484,10 @@ def main():
             "launches": syrk_n,
             "avg_launch_ms": syrk_ms / max(syrk_n, 1),
             "flops_per_launch": syrk_flops / max(syrk_n, 1),
-            "launches_note": ("each batch's product is two launches (tiles in the next "
-                              "batch's touched row blocks first, then the rest); "
-                              "achieved = all SYRK flops / all SYRK launch time"),
+            "launches_note": ("one launch = one batch's product: k_syrk_f64 over the whole "
+                              "rounds of 128x128 tiles, then k_syrk_f64_tail over the "
+                              "leftover tiles as 64x64 sub-tiles, timed together by one "
+                              "event pair; achieved = all product flops / all product time"),
         },
         "update_streams": args.streams,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
