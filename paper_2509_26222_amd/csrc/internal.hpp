@@ -40,6 +40,8 @@ enum WsSlot {
   WS_SOLVE4,
   WS_SOLVE5,
   WS_SOLVE6,
+  WS_SOLVE7,    // solve: L^{-1} of every diagonal block, transposed
+  WS_SOLVE8,    // solve: one s x s block, and the second sweep vector
   WS_COUNT
 };
 

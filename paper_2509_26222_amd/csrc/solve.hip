@@ -12,6 +12,7 @@
 // and a backward sweep x_i = L_i^{-T} (y_i - G_i x_{i+1}). Refinement:
 // x += solve(b - calH x) until ||b - calH x|| <= rtol ||b|| per column.
 // Dense blocks use the FP64 MFMA kernels of the covariance update.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -127,6 +128,76 @@ __global__ void __launch_bounds__(256) k_gemm_sub(int64_t M, int64_t Nc, int64_t
         const int64_t gn = n0 + cb + 16 * ni + (lane & 15);
         if (gm < M && gn < Nc) C[gm * ldc + gn] -= acc[mi][ni][v];
       }
+}
+
+// Matrix-vector products of the one-right-hand-side sweeps, n x n blocks
+// (leading dimension lda), deterministic:
+//   k_mv_cols: out[j] = base[j] + sgn sum_k A[k][j] x[k]   (A^T x)
+//   k_mv_rows: out[c] = base[c] + sgn sum_r A[c][r] x[r]   (A x)
+// base may be null (0) or equal to out; x must not overlap out.
+// k_mv_cols: 64 outputs per workgroup, 16 slices of k summed in order.
+__global__ void __launch_bounds__(1024) k_mv_cols(const double* __restrict__ A, int64_t lda,
+                                                  int32_t n, const double* __restrict__ x,
+                                                  const double* base, double sgn, double* out) {
+  __shared__ double part[16][64];
+  const int tid = threadIdx.x, jl = tid & 63, sl = tid >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + jl;
+  const int per = (n + 15) / 16;
+  const int k0 = sl * per, k1 = min(n, k0 + per);
+  double s0 = 0.0, s1 = 0.0;
+  if (j < n) {
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+      s0 += A[(int64_t)k * lda + j] * x[k];
+      s1 += A[(int64_t)(k + 1) * lda + j] * x[k + 1];
+    }
+    if (k < k1) s0 += A[(int64_t)k * lda + j] * x[k];
+  }
+  part[sl][jl] = s0 + s1;
+  __syncthreads();
+  if (sl == 0 && j < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += part[q][jl];
+    out[j] = (base ? base[j] : 0.0) + sgn * t;
+  }
+}
+
+// k_mv_rows: one wave per output, a fixed-order butterfly over the lanes.
+__global__ void __launch_bounds__(256) k_mv_rows(const double* __restrict__ A, int64_t lda,
+                                                 int32_t n, const double* __restrict__ x,
+                                                 const double* base, double sgn, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const double* row = A + c * lda;
+  double s0 = 0.0, s1 = 0.0;
+  int r = lane;
+  for (; r + 64 < n; r += 128) {
+    s0 += row[r] * x[r];
+    s1 += row[r + 64] * x[r + 64];
+  }
+  if (r < n) s0 += row[r] * x[r];
+  double t = s0 + s1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  if (lane == 0) out[c] = (base ? base[c] : 0.0) + sgn * t;
+}
+
+static rbf_status mv_cols(rbf_ctx* ctx, const double* A, int64_t lda, int64_t n,
+                          const double* x, const double* base, double sgn, double* out) {
+  k_mv_cols<<<(unsigned)ceil_div(n, 64), 1024, 0, ctx->stream>>>(A, lda, (int32_t)n, x, base,
+                                                                  sgn, out);
+  RBF_LAUNCHED(ctx, "k_mv_cols");
+  return RBF_OK;
+}
+
+static rbf_status mv_rows(rbf_ctx* ctx, const double* A, int64_t lda, int64_t n,
+                          const double* x, const double* base, double sgn, double* out) {
+  k_mv_rows<<<(unsigned)ceil_div(n, 4), 256, 0, ctx->stream>>>(A, lda, (int32_t)n, x, base, sgn,
+                                                                out);
+  RBF_LAUNCHED(ctx, "k_mv_rows");
+  return RBF_OK;
 }
 
 static rbf_status gemm_sub(rbf_ctx* ctx, bool ta, int64_t M, int64_t Nc, int64_t K,
@@ -484,22 +555,35 @@ extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
   if (!part) return st;
   double* dnorm = (double*)ws_get(ctx, WS_TMP2, sizeof(double) * nrhs, &st);
   if (!dnorm) return st;
+  // L^{-1} of every diagonal block (transposed), kept for the sweeps
+  double* LiT = (double*)ws_get(ctx, WS_SOLVE7, sizeof(double) * nblk * ss, &st);
+  if (!LiT) return st;
+  // one block for the out-of-place product, then the forward sweep's vector
+  double* Tmp = (double*)ws_get(ctx, WS_SOLVE8, sizeof(double) * std::max(ss, Np), &st);
+  if (!Tmp) return st;
+  const bool vec1 = nrhs == 1;
   // ---- blocks
   RBF_TRY(fill_zero(ctx, D, sizeof(double) * nblk * ss));
   RBF_TRY(fill_zero(ctx, Ub, sizeof(double) * nblk * ss));
   k_csr_to_blocks<<<ceil_div(Np, 256), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, (int32_t)s,
                                                               (int32_t)nblk, D, Ub);
   RBF_LAUNCHED(ctx, "k_csr_to_blocks");
-  // ---- block Cholesky
+  // ---- block Cholesky: D_i -= U_{i-1}^T U_{i-1} (the covariance product's
+  // kernel, V^T = U_{i-1}), L_i L_i^T = D_i with X_i = L_i^{-1}, and
+  // U_i = X_i A_{i,i+1} as one product
+  RBF_TRY(fill_zero(ctx, LiT, sizeof(double) * nblk * ss));
   for (int64_t i = 0; i < nblk; ++i) {
     double* Di = D + i * ss;
     if (i > 0)
-      RBF_TRY(gemm_sub(ctx, true, s, s, s, Ub + (i - 1) * ss, s, Ub + (i - 1) * ss, s, Di, s,
-                       seq));
-    RBF_TRY(chol_blocked(ctx, Di, (int32_t)s, Lb + i * ss, Linv + i * nsub * 4096, i, seq));
-    if (i + 1 < nblk)
-      RBF_TRY(trsm_blocks(ctx, Ub + i * ss, s, s, (int32_t)nsub, Lb + i * ss, s,
-                          Linv + i * nsub * 4096, false, seq));
+      RBF_TRY(syrk_update(ctx, Di, s, s, Ub + (i - 1) * ss, s, (int32_t)s, RBF_F64, nullptr, 0,
+                          seq));
+    RBF_TRY(chol_blocked(ctx, Di, (int32_t)s, Lb + i * ss, Linv + i * nsub * 4096, i, seq,
+                         LiT + i * ss));
+    if (i + 1 < nblk) {
+      RBF_TRY(linv_apply(ctx, LiT + i * ss, (int32_t)s, Ub + i * ss, s, s, Tmp, seq));
+      RBF_HIP(ctx, hipMemcpyAsync(Ub + i * ss, Tmp, sizeof(double) * ss, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+    }
   }
   {
     int32_t h[4];
@@ -517,7 +601,21 @@ extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
   for (it = 0; it < max_iter && !conv; ++it) {
     k_pad_copy<<<ceil_div(Np * nrhs, 256), 256, 0, ctx->stream>>>(R, ldr, N, Np, nrhs, Y);
     RBF_LAUNCHED(ctx, "k_pad_copy");
-    for (int64_t i = 0; i < nblk; ++i) {
+    if (vec1) {
+      // L y = r by blocks: Z_i = X_i (r_i - U_{i-1}^T Z_{i-1}) into Tmp; then
+      // L^T y = z: Y_i = X_i^T (Z_i - U_i Y_{i+1})
+      for (int64_t i = 0; i < nblk; ++i) {
+        double* Yi = Y + i * s;
+        if (i > 0) RBF_TRY(mv_cols(ctx, Ub + (i - 1) * ss, s, s, Tmp + (i - 1) * s, Yi, -1.0, Yi));
+        RBF_TRY(mv_cols(ctx, LiT + i * ss, s, s, Yi, nullptr, 1.0, Tmp + i * s));
+      }
+      for (int64_t i = nblk - 1; i >= 0; --i) {
+        double* Zi = Tmp + i * s;
+        if (i + 1 < nblk) RBF_TRY(mv_rows(ctx, Ub + i * ss, s, s, Y + (i + 1) * s, Zi, -1.0, Zi));
+        RBF_TRY(mv_rows(ctx, LiT + i * ss, s, s, Zi, nullptr, 1.0, Y + i * s));
+      }
+    }
+    for (int64_t i = 0; !vec1 && i < nblk; ++i) {
       double* Yi = Y + i * s * nrhs;
       if (i > 0)
         RBF_TRY(gemm_sub(ctx, true, s, nrhs, s, Ub + (i - 1) * ss, s, Yi - s * nrhs, nrhs, Yi,
@@ -525,7 +623,7 @@ extern "C" rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
       RBF_TRY(trsm_blocks(ctx, Yi, nrhs, nrhs, (int32_t)nsub, Lb + i * ss, s,
                           Linv + i * nsub * 4096, false, seq));
     }
-    for (int64_t i = nblk - 1; i >= 0; --i) {
+    for (int64_t i = nblk - 1; !vec1 && i >= 0; --i) {
       double* Yi = Y + i * s * nrhs;
       if (i + 1 < nblk)
         RBF_TRY(gemm_sub(ctx, false, s, nrhs, s, Ub + i * ss, s, Yi + s * nrhs, nrhs, Yi, nrhs,

@@ -36,7 +36,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("batch", [1, 7, 64, 65, 200, 1024, 2000, 0])
+@pytest.mark.parametrize("batch", [1, 7, 64, 65, 150, 200, 300, 1024, 2000, 0])
 def test_update_chain_equals_batch_ridge(ctx, small, batch):
     s, p, grid, wb, Pb = small
     xy, z = s.xy, s.z
