@@ -229,8 +229,32 @@ __global__ void __launch_bounds__(256) k_gather_mfma(
     okc[ni] = colv[ni] < N;
     if (!okc[ni]) colv[ni] = 0;  // clamped: a valid address, value masked
   }
-#pragma unroll 4
-  for (int r = 0; r < R4; r += 4) {
+  // four k-steps at a time: all their loads are issued before the MFMAs
+  int r = 0;
+  for (; r + 16 <= R4; r += 16) {
+    double a[4][4], bv[4][2];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kr = r + 4 * st + kq;
+      const double* prow = P + (int64_t)L[kr] * ldp;
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) a[st][mi] = H[(int64_t)kr * 64 + 16 * mi + li];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const double v = prow[colv[ni]];
+        bv[st][ni] = okc[ni] ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][mi], bv[st][ni], acc[mi][ni], 0, 0, 0);
+  }
+  for (; r < R4; r += 4) {
     const int kr = r + kq;
     const double* prow = P + (int64_t)L[kr] * ldp;
     double a[4], bv[2];
