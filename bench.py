@@ -99,13 +99,15 @@ def batched_leg(ctx, api, synth, n_patches, tune):
         for r in raw:
             grid = ctx.grid(p, torch.from_numpy(r.centers).cuda())
             N = grid.N
-            pts = torch.from_numpy(
-                __import__("numpy").concatenate([r.xy, r.z[:, None]], 1)).float().cuda()
+            # points in bin order (setup, untimed), as the odometry frames are
+            xs, zs, _ = ctx.sort_points(grid, torch.from_numpy(r.xy).cuda(),
+                                        torch.from_numpy(r.z).cuda())
+            pts = torch.cat([xs, zs[:, None]], 1).float().contiguous()
             Q = pts.shape[0]
             out.append(dict(grid=grid,
                             w=torch.zeros(N, dtype=torch.float64, device="cuda"),
                             P=torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam),
-                            xy=torch.from_numpy(r.xy).cuda(), z=torch.from_numpy(r.z).cuda(),
+                            xy=xs, z=zs,
                             pts=pts, pose=(__import__("numpy").eye(3),
                                            __import__("numpy").zeros(3)),
                             f=torch.empty(Q, dtype=torch.float32, device="cuda"),

@@ -97,15 +97,18 @@ __global__ void __launch_bounds__(256) k_upd_rows(
 }
 
 // U^T[b, n] = sum_k vals[b,k] P[cols[b,k], n]  (P symmetric: rows of P).
-// Block: 8 batch rows x 1024 columns; each thread 4 columns.
+// Block: 8 batch rows x 1024 columns; each thread 4 columns. With gR, only
+// the rows of groups the grouped kernels leave (more than
+// GATHER_GROUP_RMAX distinct rows of P).
 __global__ void __launch_bounds__(256) k_upd_gather_u(
     const double* __restrict__ P, int64_t ldp, int64_t N, int32_t Bc, int32_t Bp,
     const double* __restrict__ vals, const int32_t* __restrict__ cols,
     const int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu,
-    const int32_t* __restrict__ status, int64_t seq) {
+    const int32_t* __restrict__ gR, const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t n0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   const int b0 = blockIdx.y * 8;
+  if (gR && gR[b0 / 64] <= GATHER_GROUP_RMAX) return;
   for (int r = 0; r < 8; ++r) {
     const int b = b0 + r;
     double acc[4] = {0, 0, 0, 0};
@@ -215,6 +218,7 @@ __global__ void __launch_bounds__(256) k_gather_mfma(
   const int32_t* L = glist + (int64_t)g * Rcap;
   const double* H = gH + (int64_t)g * Rcap * 64;
   const int R4 = gR[g];
+  if (R4 > GATHER_GROUP_RMAX) return;  // left to k_upd_gather_u
   v4d acc[4][2];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
@@ -283,19 +287,22 @@ __global__ void __launch_bounds__(256) k_gather_mfma(
 }
 
 // S[a][b] (a >= b) = sum_k vals[a,k] U^T[b, cols[a,k]] + R delta_ab; the
-// padding rows a >= Bc carry the identity.
+// padding rows a >= Bc carry the identity. With gR, only the rows a of
+// groups the grouped kernel leaves.
 __global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
                                                const int32_t* __restrict__ cols,
                                                const int32_t* __restrict__ nnz,
                                                const double* __restrict__ Ut, int64_t ldu,
                                                int32_t Bc, int32_t Bp, double R,
                                                double* __restrict__ S,
+                                               const int32_t* __restrict__ gR,
                                                const int32_t* __restrict__ status,
                                                int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int b = blockIdx.y;
   const int a = blockIdx.x * 256 + threadIdx.x;
   if (a >= Bp || a < b) return;
+  if (gR && gR[a / 64] <= GATHER_GROUP_RMAX) return;
   double s;
   if (a < Bc && b < Bc) {
     s = (a == b) ? R : 0.0;
@@ -328,6 +335,7 @@ __global__ void __launch_bounds__(256) k_upd_S_groups(
   const int32_t* L = glist + (int64_t)ga * Rcap;
   const double* H = gH + (int64_t)ga * Rcap * 64;
   const int R4 = gR[ga];
+  if (R4 > GATHER_GROUP_RMAX) return;  // left to k_upd_S
   const int bcol = gb * 64 + wave * 16 + li;  // < Bp
   const double* urow = Ut + (int64_t)bcol * ldu;
   v4d acc[4];
@@ -1171,10 +1179,11 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
       k_gather_mfma<<<gm, 256, 0, ctx->stream>>>(P, ldp, N, ws.glist, ws.gR, ws.gH, ws.Rcap, Ut,
                                                   ldu, ctx->d_status, sq);
       RBF_LAUNCHED(ctx, "k_gather_mfma");
-    } else {
+    }
+    {  // all rows without the grouped data, else the groups it leaves
       dim3 gg((unsigned)ceil_div(N, 1024), (unsigned)ceil_div(Bpc, 8));
       k_upd_gather_u<<<gg, 256, 0, ctx->stream>>>(P, ldp, N, Bc, Bpc, vals, cols, nnz, Ut, ldu,
-                                                   ctx->d_status, sq);
+                                                   ws.gH ? ws.gR : nullptr, ctx->d_status, sq);
       RBF_LAUNCHED(ctx, "k_upd_gather_u");
     }
     prof_end(ctx, RBF_PROF_GATHER);
@@ -1183,10 +1192,11 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
       k_upd_S_groups<<<ng * (ng + 1) / 2, 256, 0, ctx->stream>>>(
           ws.glist, ws.gR, ws.gH, ws.Rcap, Ut, ldu, Bc, Bpc, p->R, S, ctx->d_status, sq);
       RBF_LAUNCHED(ctx, "k_upd_S_groups");
-    } else {
+    }
+    {  // all rows without the grouped data, else the groups it leaves
       dim3 gs((unsigned)ceil_div(Bpc, 256), (unsigned)Bpc);
       k_upd_S<<<gs, 256, 0, ctx->stream>>>(vals, cols, nnz, Ut, ldu, Bc, Bpc, p->R, S,
-                                           ctx->d_status, sq);
+                                           ws.gH ? ws.gR : nullptr, ctx->d_status, sq);
       RBF_LAUNCHED(ctx, "k_upd_S");
     }
     double* Vt = VtB[bi & 1];

@@ -68,6 +68,12 @@ struct UpdWs {
 
 // Largest N for the grouped gather (its LDS bitmap has one bit per center).
 constexpr int64_t GATHER_GROUP_NMAX = (int64_t)1 << 17;
+
+// A group of 64 batch rows whose points touch more distinct rows of P than
+// this (points not in spatial order) takes the per-point gather and S
+// kernels instead of the dense group products, whose work grows with the
+// number of distinct rows.
+constexpr int32_t GATHER_GROUP_RMAX = 512;
 rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
                             rbf_prec gemm_prec, UpdWs* ws);
 

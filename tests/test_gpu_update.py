@@ -185,3 +185,25 @@ def test_update_two_streams_failure_commits_earlier_batches(ctx, small):
     assert _rel(host(w), w5) <= TOL_W
     assert np.abs(host(P) - P5).max() <= TOL_W * np.abs(P5).max()
     ctx.sync_status()
+
+
+def test_update_unsorted_and_sorted_points_large_grid(ctx):
+    """2,500 centers (25 x 25 m at 0.5 m) and 3,000 points: in their given
+    (random) order each 64-point group touches many more rows of P than the
+    grouped gather takes, so U = P H^T and S come from the per-point kernels;
+    in bin order they come from the grouped MFMA products. Both against the
+    oracle's batch ridge solution."""
+    s = synth.small_case(7, n_points=3000, n_queries=10, side=25.0, spacing=0.5)
+    p = api.Params()
+    grid = ctx.grid(p, dev(s.centers))
+    assert grid.N == 2500
+    wb, Pb = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R)
+    for sort in (False, True):
+        w, P = _state(grid.N, p)
+        xy, z = dev(s.xy), dev(s.z)
+        if sort:
+            xy, z, _ = ctx.sort_points(grid, xy, z)
+        ctx.update(p, grid, w, P, xy, z, batch=1024)
+        assert _rel(host(w), wb) <= TOL_W, sort
+        assert np.abs(host(P) - Pb).max() <= TOL_W * np.abs(Pb).max(), sort
+        assert torch.equal(P, P.T)
