@@ -6,18 +6,20 @@
 //   A. wave 0 factors the 16x16 diagonal block in registers, one row per lane
 //      (lane g, g = lane % 16, holds row g); step j takes the pivot and the
 //      column entries from their lanes with DPP row broadcasts (no LDS, no
-//      barrier)
-//      and scales by the pivot's reciprocal only, the square roots coming
-//      after the 16 steps; then the same wave forms the block's inverse by
-//      forward substitution, lane c holding column c;
-//   B. the panel rows below: L_p = A_p D^{-T} (16x16x16 FP64 MFMA per wave);
+//      barrier) and scales by the pivot's reciprocal only, the square roots
+//      coming after the 16 steps. It writes L and 1 / L_jj;
+//   B. the panel rows below, L_p D^T = A_p, by forward substitution in
+//      registers (waves 1-3, one row per lane, D read from LDS);
 //   C. the trailing lower blocks: A_rs -= L_r L_s^T (FP64 MFMA).
-// Then the off-diagonal 16x16 blocks of the inverse by block diagonals:
+// Then the four diagonal 16x16 inverses, one per wave, by forward
+// substitution (lane c holds column c), and the off-diagonal 16x16 blocks
+// of the inverse by block diagonals:
 //   Linv_ij = -Linv_ii sum_{j<=k<i} L_ik Linv_kj,
 // where the f64 MFMA output layout (lane j + 16 (i % 4), item i / 4) is the
 // B-operand layout of the next product's k-steps, so the two products chain
-// in registers. A non-positive or non-finite pivot records RBF_E_NOT_SPD
-// with `index` for launch group `seq` (the factor continues with pivot 1).
+// in registers. No panel waits for an inverse. A non-positive or non-finite
+// pivot records RBF_E_NOT_SPD with `index` for launch group `seq` (the
+// factor continues with pivot 1).
 #pragma once
 
 // Value of v in lane k of each row of 16 lanes: DPP row_newbcast (gfx90a
@@ -74,12 +76,12 @@ __device__ __forceinline__ double rcp_nr(double p) {
 }
 
 // Phase A for the diagonal block at (c0, c0): T gets L (zero above the
-// diagonal), Ti the block's inverse (zero above); returns false if a pivot
-// was not positive and finite. Wave 0 only.
+// diagonal), dinv[c0 + j] = 1 / L_jj; returns false if a pivot was not
+// positive and finite. Wave 0 only.
 // Step j works on the unscaled column c (c_g = a[g][j], pivot p_j = c_j):
 // a[g][k] -= c_g c_k / p_j for j < k, so the square roots are off the
 // dependent chain; afterwards L[g][j] = c_g / sqrt(p_j).
-__device__ __forceinline__ bool chol16_regs(double (*T)[LDT], double (*Ti)[LDT], int c0) {
+__device__ __forceinline__ bool chol16_factor(double (*T)[LDT], double* dinv, int c0) {
   const int lane = threadIdx.x & 63;
   const int g = lane & 15;
   double a[16], piv[16];
@@ -98,60 +100,81 @@ __device__ __forceinline__ bool chol16_regs(double (*T)[LDT], double (*Ti)[LDT],
     for (int k = j + 1; k < 16; ++k) a[k] -= t * row_bcast16(a[j], k);
   }
   __builtin_amdgcn_sched_barrier(0);
-  double inv[16];
+  double mine = 0.0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const double d = sqrt(piv[j]);
-    inv[j] = 1.0 / d;
-    a[j] = (g == j) ? d : a[j] * inv[j];
+    const double inv = 1.0 / d;
+    a[j] = (g == j) ? d : a[j] * inv;
+    mine = (g == j) ? inv : mine;
   }
   __builtin_amdgcn_sched_barrier(0);
-  // inverse by forward substitution: lane g computes column g,
-  // x_j = (delta_jg - sum_{q<j} L_jq x_q) / L_jj for j >= g
+  if (lane < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) T[c0 + g][c0 + k] = (k <= g) ? a[k] : 0.0;
+    dinv[c0 + g] = mine;
+  }
+  return nbad == 0;
+}
+
+// Phase B for panel c0: row r (one per lane of waves 1..3, g = lane % 16)
+// solves l D^T = a for its 16 entries, D = the panel's diagonal factor.
+__device__ __forceinline__ void panel_rows(double (*T)[LDT], const double* dinv, int c0, int r) {
+  const int lane = threadIdx.x & 63;
+  double x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = T[r][c0 + k];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    x[j] *= dinv[c0 + j];
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) x[k] -= x[j] * T[c0 + k][c0 + j];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) T[r][c0 + k] = x[k];
+  }
+}
+
+// Inverse of the 16x16 diagonal factor block at (b0, b0) into Ti (lane c of
+// the wave computes column c by forward substitution; D from LDS).
+__device__ __forceinline__ void diag_inverse(const double (*T)[LDT], double (*Ti)[LDT],
+                                             const double* dinv, int b0) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane & 15;
   double x[16];
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) {
     double s = (g == jj) ? 1.0 : 0.0;
 #pragma unroll
-    for (int q = 0; q < jj; ++q) s -= row_bcast16(a[q], jj) * x[q];
-    x[jj] = (jj >= g) ? s * inv[jj] : 0.0;
+    for (int q = 0; q < jj; ++q) s -= T[b0 + jj][b0 + q] * x[q];
+    x[jj] = (jj >= g) ? s * dinv[b0 + jj] : 0.0;
   }
-  __builtin_amdgcn_sched_barrier(0);
   if (lane < 16) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      T[c0 + g][c0 + k] = (k <= g) ? a[k] : 0.0;
-      Ti[c0 + k][c0 + g] = x[k];
-    }
+    for (int k = 0; k < 16; ++k) Ti[b0 + k][b0 + g] = x[k];
   }
-  return nbad == 0;
 }
 
 __device__ __forceinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int32_t* status,
                                     int64_t index, int64_t seq) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int bad;
+  __shared__ double dinv[NB];
   if (tid == 0) bad = 0;
   for (int e = tid; e < NB * NB; e += 256) Ti[e >> 6][e & 63] = 0.0;
   __syncthreads();
-  const bool w0 = wave == 0;
   for (int c0 = 0; c0 < NB; c0 += 16) {
-    // ---- A: 16x16 diagonal block and its inverse (wave 0, registers)
-    if (w0) {
-      const bool ok = chol16_regs(T, Ti, c0);
+    // ---- A: 16x16 diagonal block (wave 0, registers)
+    if (wave == 0) {
+      const bool ok = chol16_factor(T, dinv, c0);
       if (lane == 0 && !ok) bad = 1;
     }
     __syncthreads();
     const int nrb = (NB - c0 - 16) / 16;  // row blocks below the panel
     if (nrb == 0) break;
-    // ---- B: panel rows below: L_p = A_p D^{-T}
-    if (wave < nrb) {
-      const int r0 = c0 + 16 + 16 * wave;
-      v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
-      acc = mma16_nt(T, r0, c0, Ti, c0, c0, acc);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[r0 + 4 * v + (lane >> 4)][c0 + (lane & 15)] = acc[v];
-    }
+    // ---- B: panel rows below, L_p D^T = A_p
+    if (wave >= 1 && wave <= nrb) panel_rows(T, dinv, c0, c0 + 16 * wave + (lane & 15));
     __syncthreads();
     // ---- C: trailing lower blocks A_rs -= L_r L_s^T
     const int nblocks = nrb * (nrb + 1) / 2;
@@ -167,6 +190,9 @@ __device__ __forceinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int3
     }
     __syncthreads();
   }
+  // ---- the four diagonal inverses, one per wave
+  diag_inverse(T, Ti, dinv, 16 * wave);
+  __syncthreads();
   // strictly upper 16x16 blocks of L are zero (the diagonal blocks were
   // cleared above); the loop below reads only lower blocks of T
   for (int e = tid; e < NB * NB; e += 256)
