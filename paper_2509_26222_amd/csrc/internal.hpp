@@ -31,6 +31,7 @@ enum WsSlot {
   WS_UPD_FLAGS, // update: touched 128-row blocks of P, two batches
   WS_UPD_GROUPS,// update: per 64-row group, the distinct rows of P and dense H
   WS_UPD_VT,    // update: V^T = L^{-1} U^T, two buffers
+  WS_LINV_F32,  // update, mixed form: L^{-1} and U^T rounded to float
   WS_ACT_IDX,   // active-rows update: flags / compact map, active list, w_A
   WS_ACT_P,     // active-rows update: compact block P_AA
   WS_SOLVE0,

@@ -513,6 +513,76 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
   epilogue_f32acc_w8(P, ldp, N, I0, J0, I == J, acc);
 }
 
+// The triangular solve's product V^T = X U^T of the mixed form on FP32 MFMA
+// (operands rounded to float once per batch, FP32 accumulation, V^T stored
+// in FP64): same tiles, k-range and order of row blocks as k_linv_apply.
+__global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply_f32(const float* __restrict__ Lf,
+                                                               int32_t n,
+                                                               const float* __restrict__ Uf,
+                                                               int64_t ldu, int64_t ncols,
+                                                               double* __restrict__ Vt,
+                                                               int32_t nJ,
+                                                               const int32_t* __restrict__ status,
+                                                               int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  const int nI = (n + ST - 1) / ST;
+  const int I = nI - 1 - (int)(blockIdx.x / nJ), J = (int)(blockIdx.x % nJ);
+  const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
+  const int K = min(n, (I + 1) * ST);
+  __shared__ __attribute__((aligned(16))) float As[2][FKC][FLD];
+  __shared__ __attribute__((aligned(16))) float Bs[2][FKC][FLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  v4f acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const int nch = (K + FKC - 1) / FKC;
+  float4 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
+  load_stage_f32<SYRK_NT>(Lf, n, n, 0, K, I0, ra);
+  load_stage_f32<SYRK_NT>(Uf, ldu, ncols, 0, K, J0, rb);
+  store_stage_f32<SYRK_NT>(As[0], ra);
+  store_stage_f32<SYRK_NT>(Bs[0], rb);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) {
+      load_stage_f32<SYRK_NT>(Lf, n, n, (ch + 1) * FKC, K, I0, ra);
+      load_stage_f32<SYRK_NT>(Uf, ldu, ncols, (ch + 1) * FKC, K, J0, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < FKC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      float a[2], b[4];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+    if (ch + 1 < nch) {
+      store_stage_f32<SYRK_NT>(As[buf ^ 1], ra);
+      store_stage_f32<SYRK_NT>(Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+        if (gi < n && gj < ncols) Vt[gi * ldu + gj] = (double)acc[mi][ni][v];
+      }
+}
+
 constexpr int BKC = 32;      // k per stage (one 16x16x32 MFMA)
 constexpr int BLD = BKC + 8; // LDS pitch in bf16 (80 bytes)
 
@@ -663,13 +733,33 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
 }
 
 rbf_status linv_apply(rbf_ctx* ctx, const double* LiT, int32_t n, const double* Ut,
-                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq) {
+                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq, rbf_prec prec) {
   if (n <= 0 || ncols <= 0) return RBF_OK;
   const int64_t nI = ceil_div(n, ST), nJ = ceil_div(ncols, ST);
-  k_linv_apply<<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(LiT, n, Ut, ldu, ncols, Vt,
-                                                                  (int32_t)nJ, ctx->d_status,
-                                                                  seq);
-  RBF_LAUNCHED(ctx, "k_linv_apply");
+  if (prec == RBF_F64) {
+    k_linv_apply<<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(LiT, n, Ut, ldu, ncols, Vt,
+                                                                    (int32_t)nJ, ctx->d_status,
+                                                                    seq);
+    RBF_LAUNCHED(ctx, "k_linv_apply");
+    return RBF_OK;
+  }
+  // mixed form: X and U^T (all n rows, the padding ones being zero) rounded
+  // to float into a slot of their own (the product's low-precision copy of
+  // V^T may still be in use by the previous batch), then the FP32 product
+  rbf_status st;
+  float* Lf = (float*)ws_get(ctx, WS_LINV_F32,
+                             sizeof(float) * ((size_t)n * n + (size_t)n * ldu), &st);
+  if (!Lf) return st;
+  float* Uf = Lf + (size_t)n * n;
+  k_cvt_f32<<<ceil_div((int64_t)n * n, 256), 256, 0, ctx->stream>>>(LiT, n, n, n, Lf,
+                                                                    ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_cvt_f32");
+  k_cvt_f32<<<ceil_div((int64_t)n * ldu, 256), 256, 0, ctx->stream>>>(Ut, ldu, n, ncols, Uf,
+                                                                      ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_cvt_f32");
+  k_linv_apply_f32<<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(
+      Lf, n, Uf, ldu, ncols, Vt, (int32_t)nJ, ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_linv_apply_f32");
   return RBF_OK;
 }
 

@@ -936,6 +936,9 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
     ws->glist = (int32_t*)(gw + (size_t)ng * Rcap * 64 * sizeof(double));
     ws->gR = ws->glist + (size_t)ng * Rcap;
   }
+  if (gemm_prec != RBF_F64 &&
+      !ws_get(ctx, WS_LINV_F32, sizeof(float) * ((size_t)Bp * Bp + (size_t)Bp * ldu), &st))
+    return st;
   if (gemm_prec == RBF_F32) {
     if (!ws_get(ctx, WS_UPD_VLO, sizeof(float) * (size_t)Bp * ldu, &st)) return st;
   } else if (gemm_prec == RBF_BF16) {
@@ -1205,7 +1208,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi, sq, ws.LiT));
     prof_end(ctx, RBF_PROF_CHOL);
     prof_begin(ctx, RBF_PROF_TRSM);
-    RBF_TRY(linv_apply(ctx, ws.LiT, Bpc, Ut, ldu, N + 1, Vt, sq));
+    RBF_TRY(linv_apply(ctx, ws.LiT, Bpc, Ut, ldu, N + 1, Vt, sq, gemm_prec));
     prof_end(ctx, RBF_PROF_TRSM);
     dim3 gw((unsigned)ceil_div(N, 256), (unsigned)ceil_div(Bc, 64));
     k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Vt, ldu, N, Bc, wpart, ctx->d_status, sq);

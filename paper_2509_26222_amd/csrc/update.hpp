@@ -91,9 +91,11 @@ rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* 
 // entry), chol_blocked also forms X = L^{-1} transposed: LiT[c][r] = X[r][c].
 // linv_apply then computes V^T = X U^T (n x ncols, rows of U^T with leading
 // dimension ldu) into Vt (leading dimension ldu) on FP64 MFMA: the block
-// triangular solve as one product.
+// triangular solve as one product. prec = RBF_F32 or RBF_BF16 (the mixed
+// form) rounds X and U^T to float and multiplies on FP32 MFMA.
 rbf_status linv_apply(rbf_ctx* ctx, const double* LiT, int32_t n, const double* Ut,
-                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq);
+                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq,
+                      rbf_prec prec = RBF_F64);
 
 // X := L^{-1} X (trans = false) or X := L^{-T} X (trans = true) in place for
 // X with nblk*64 rows, ncols columns and leading dimension ldx, with L given

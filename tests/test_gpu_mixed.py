@@ -143,10 +143,15 @@ def test_mixed_bf16_eight_frames_refined_each_frame(ctx):
     wb = O.spd_solve(H, bb)
     q = np.random.default_rng(1).uniform(0, 50, size=(5000, 2))
     ef, eg, ew = _errors(q, centers, host(w), wb, p)
+    # P after eight frames of BF16x3 products: still symmetric positive
+    # definite (the Cholesky succeeds), so later S = H P H^T + R I stay SPD
+    info = int(torch.linalg.cholesky_ex(P).info)
     print(f"bf16 eight frames: CG iterations per frame {its}; max|df| {ef:.2e} m, "
-          f"grad rel {eg:.2e}, w rel {ew:.2e}")
+          f"grad rel {eg:.2e}, w rel {ew:.2e}; Cholesky of P info {info}")
     assert ef <= 1e-4
     assert eg <= 1e-3
+    assert torch.equal(P, P.T)
+    assert info == 0
 
 
 def test_mixed_update_40k_centers_batch_4096(ctx):
