@@ -28,6 +28,31 @@ __device__ inline void tile_of(int64_t t, int* I, int* J) {
   *J = (int)(t - (int64_t)i * (i + 1) / 2);
 }
 
+// Lower tile t of an nt x nt tile grid in blocked order: bands of 8 tile
+// rows, each band's full 8-column blocks left to right, then its diagonal
+// triangle; tiles row by row inside a block. Consecutive tiles (those a
+// round of workgroups of one XCD runs together) then share 16 panels of
+// V^T instead of one row panel and 64 column panels.
+__device__ inline void tile_of_blocked(int64_t t, int nt, int* I, int* J) {
+  int b = (int)((sqrt(16.0 + 128.0 * (double)t) - 4.0) / 64.0);
+  while (32 * (int64_t)(b + 1) * (b + 1) + 4 * (int64_t)(b + 1) <= t) ++b;
+  while (32 * (int64_t)b * b + 4 * (int64_t)b > t) --b;
+  const int r = (int)(t - (32 * (int64_t)b * b + 4 * (int64_t)b));
+  const int h = min(8, nt - 8 * b);
+  if (r < b * 8 * h) {
+    const int bj = r / (8 * h), q = r % (8 * h);
+    *I = 8 * b + q / 8;
+    *J = 8 * bj + q % 8;
+    return;
+  }
+  const int q = r - b * 8 * h;
+  int i = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= q) ++i;
+  while (i * (i + 1) / 2 > q) --i;
+  *I = 8 * b + i;
+  *J = 8 * b + (q - i * (i + 1) / 2);
+}
+
 // Tile filter of a split product: part 0 all tiles, part 1 the tiles in a
 // flagged block row or column, part 2 the others.
 __device__ inline bool tile_in_part(const int32_t* __restrict__ flags, int part, int I, int J) {
@@ -100,7 +125,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P,
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
   int I, J;
-  tile_of(t, &I, &J);
+  tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
   if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
   __shared__ double As[2][SKC][SLD];
@@ -193,7 +218,7 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
   const int64_t t = (bid & 7) * per_xcd + local;
   if (t >= T) return;
   int I, J;
-  tile_of(t, &I, &J);
+  tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
   if (!tile_in_part(flags, part, I, J)) return;
   if (I == J && si < sj) return;
   const int64_t I0 = (int64_t)I * ST + si * SUB, J0 = (int64_t)J * ST + sj * SUB;
@@ -465,7 +490,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
   int I, J;
-  tile_of(t, &I, &J);
+  tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
   if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
   __shared__ __attribute__((aligned(16))) float As[2][FKC][FLD];
@@ -617,7 +642,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
   int I, J;
-  tile_of(t, &I, &J);
+  tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
   if (!tile_in_part(flags, part, I, J)) return;
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[ST][BLD];
