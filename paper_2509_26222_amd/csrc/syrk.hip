@@ -608,29 +608,42 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply_f32(const float* __re
       }
 }
 
-constexpr int BKC = 32;      // k per stage (one 16x16x32 MFMA)
-constexpr int BLD = BKC + 8; // LDS pitch in bf16 (80 bytes)
+constexpr int BKC = 64;      // k per stage (two 16x16x32 MFMA steps)
+constexpr int BLD = BKC + 8; // LDS pitch in bf16 (144 bytes)
 
 // One thread's share of a BF16 stage (8-wave layout: 4 threads per row of
-// 32 k values, one 16-byte piece each): row ga (I panel) and gb (J panel) of
-// V_hi and V_lo from k index k0. Rows beyond N read row N-1 (in bounds) and
-// are zeroed by a mask, so no pointer is selected (a select between a global
-// and a local address made the loads generic and put a zero on the stack).
+// 64 k values, two 16-byte pieces each, at k0 and k0 + 32): row ga (I panel)
+// and gb (J panel) of V_hi and V_lo. Rows beyond N read row N-1 (in bounds)
+// and are zeroed by a mask, so no pointer is selected (a select between a
+// global and a local address made the loads generic and put a zero on the
+// stack).
+struct Bf16Stage {
+  uint4 ah[2], al[2], bh[2], bl[2];
+};
+
+__device__ __forceinline__ void mask4(uint4& v, uint32_t m) {
+  v.x &= m; v.y &= m; v.z &= m; v.w &= m;
+}
+
 __device__ __forceinline__ void load_bf16_stage(const __bf16* __restrict__ Vhi,
                                                 const __bf16* __restrict__ Vlo, int32_t Kp,
                                                 int64_t N, int64_t ga, int64_t gb, int64_t k0,
-                                                uint4& rah, uint4& ral, uint4& rbh,
-                                                uint4& rbl) {
+                                                Bf16Stage& r) {
   const int64_t ra = ga < N ? ga : N - 1, rb = gb < N ? gb : N - 1;
   const uint32_t ma = ga < N ? 0xffffffffu : 0u, mb = gb < N ? 0xffffffffu : 0u;
-  rah = *reinterpret_cast<const uint4*>(Vhi + ra * Kp + k0);
-  ral = *reinterpret_cast<const uint4*>(Vlo + ra * Kp + k0);
-  rbh = *reinterpret_cast<const uint4*>(Vhi + rb * Kp + k0);
-  rbl = *reinterpret_cast<const uint4*>(Vlo + rb * Kp + k0);
-  rah.x &= ma; rah.y &= ma; rah.z &= ma; rah.w &= ma;
-  ral.x &= ma; ral.y &= ma; ral.z &= ma; ral.w &= ma;
-  rbh.x &= mb; rbh.y &= mb; rbh.z &= mb; rbh.w &= mb;
-  rbl.x &= mb; rbl.y &= mb; rbl.z &= mb; rbl.w &= mb;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t k = k0 + 32 * h;
+    r.ah[h] = *reinterpret_cast<const uint4*>(Vhi + ra * Kp + k);
+    r.al[h] = *reinterpret_cast<const uint4*>(Vlo + ra * Kp + k);
+    r.bh[h] = *reinterpret_cast<const uint4*>(Vhi + rb * Kp + k);
+    r.bl[h] = *reinterpret_cast<const uint4*>(Vlo + rb * Kp + k);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    mask4(r.ah[h], ma); mask4(r.al[h], ma);
+    mask4(r.bh[h], mb); mask4(r.bl[h], mb);
+  }
 }
 
 __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
@@ -658,40 +671,48 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
   const int nch = Kp / BKC;
-  uint4 rah, ral, rbh, rbl;
-  load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)lq, rah, ral, rbh, rbl);
+  Bf16Stage rs;
+  load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)lq, rs);
   for (int ch = 0; ch < nch; ++ch) {
     __syncthreads();
-    *reinterpret_cast<uint4*>(&Ah[lrow][lq]) = rah;
-    *reinterpret_cast<uint4*>(&Al[lrow][lq]) = ral;
-    *reinterpret_cast<uint4*>(&Bh[lrow][lq]) = rbh;
-    *reinterpret_cast<uint4*>(&Bl[lrow][lq]) = rbl;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<uint4*>(&Ah[lrow][lq + 32 * h]) = rs.ah[h];
+      *reinterpret_cast<uint4*>(&Al[lrow][lq + 32 * h]) = rs.al[h];
+      *reinterpret_cast<uint4*>(&Bh[lrow][lq + 32 * h]) = rs.bh[h];
+      *reinterpret_cast<uint4*>(&Bl[lrow][lq + 32 * h]) = rs.bl[h];
+    }
     __syncthreads();
     if (ch + 1 < nch)
-      load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)(ch + 1) * BKC + lq, rah,
-                      ral, rbh, rbl);
-    const int kq = 8 * (lane >> 4);
-    v8bf ah[2], al[2], bh[4], bl[4];
+      load_bf16_stage(Vhi, Vlo, Kp, N, I0 + lrow, J0 + lrow, (int64_t)(ch + 1) * BKC + lq, rs);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int ra_ = wm * 32 + q * 16 + (lane & 15);
-      ah[q] = *reinterpret_cast<const v8bf*>(&Ah[ra_][kq]);
-      al[q] = *reinterpret_cast<const v8bf*>(&Al[ra_][kq]);
-    }
+    for (int h = 0; h < 2; ++h) {
+      const int kq = 32 * h + 8 * (lane >> 4);
+      v8bf ah[2], al[2], bh[4], bl[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int rb_ = wn * 64 + q * 16 + (lane & 15);
-      bh[q] = *reinterpret_cast<const v8bf*>(&Bh[rb_][kq]);
-      bl[q] = *reinterpret_cast<const v8bf*>(&Bl[rb_][kq]);
-    }
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 4; ++ni) {
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+      for (int q = 0; q < 2; ++q) {
+        const int ra_ = wm * 32 + q * 16 + (lane & 15);
+        ah[q] = *reinterpret_cast<const v8bf*>(&Ah[ra_][kq]);
+        al[q] = *reinterpret_cast<const v8bf*>(&Al[ra_][kq]);
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rb_ = wn * 64 + q * 16 + (lane & 15);
+        bh[q] = *reinterpret_cast<const v8bf*>(&Bh[rb_][kq]);
+        bl[q] = *reinterpret_cast<const v8bf*>(&Bl[rb_][kq]);
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+          acc[mi][ni] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+        }
+    }
   }
   epilogue_f32acc_w8(P, ldp, N, I0, J0, I == J, acc);
 }
