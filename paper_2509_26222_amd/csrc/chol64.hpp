@@ -6,8 +6,9 @@
 //   A. wave 0 factors the 16x16 diagonal block in registers, one row per lane
 //      (lane g, g = lane % 16, holds row g); step j takes the pivot and the
 //      column entries from their lanes with DPP row broadcasts (no LDS, no
-//      barrier) and scales by the pivot's reciprocal only, the square roots
-//      coming after the 16 steps. It writes L and 1 / L_jj;
+//      barrier) and scales by the pivot's reciprocal only; after the 16
+//      steps lane j takes the square root of pivot j and its reciprocal, and
+//      broadcasts the reciprocal. It writes L and 1 / L_jj;
 //   B. the panel rows below, L_p D^T = A_p, by forward substitution in
 //      registers (waves 1-3, one row per lane, D read from LDS);
 //   C. the trailing lower blocks: A_rs -= L_r L_s^T (FP64 MFMA).
@@ -84,30 +85,36 @@ __device__ __forceinline__ double rcp_nr(double p) {
 __device__ __forceinline__ bool chol16_factor(double (*T)[LDT], double* dinv, int c0) {
   const int lane = threadIdx.x & 63;
   const int g = lane & 15;
-  double a[16], piv[16];
+  double a[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) a[k] = T[c0 + g][c0 + k];
   int nbad = 0;  // counted without branches: the 16 steps stay one block
+  double mypiv = 1.0;  // lane g keeps pivot g
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const double pj = row_bcast16(a[j], j);
     const int good = (int)(pj > 0.0) & (int)(pj < INFINITY);
     nbad += 1 - good;
-    piv[j] = good ? pj : 1.0;
-    const double t = a[j] * rcp_nr(piv[j]);
+    const double pv = good ? pj : 1.0;
+    mypiv = (g == j) ? pv : mypiv;
+    const double t = a[j] * rcp_nr(pv);
     // entries above the diagonal (lanes g < k) receive unused values
 #pragma unroll
     for (int k = j + 1; k < 16; ++k) a[k] -= t * row_bcast16(a[j], k);
   }
   __builtin_amdgcn_sched_barrier(0);
-  double mine = 0.0;
+  // each lane takes the root and reciprocal of its own pivot (one square
+  // root and one division per lane rather than sixteen) and the others
+  // receive the reciprocals by broadcast. The broadcasts are statements of
+  // their own: inside an arm of the select below they would make it a
+  // branch, with the source lane switched off while they read it.
+  const double mine_d = sqrt(mypiv);
+  const double mine = 1.0 / mine_d;
+  double rinv[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const double d = sqrt(piv[j]);
-    const double inv = 1.0 / d;
-    a[j] = (g == j) ? d : a[j] * inv;
-    mine = (g == j) ? inv : mine;
-  }
+  for (int j = 0; j < 16; ++j) rinv[j] = row_bcast16(mine, j);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) a[j] = (g == j) ? mine_d : a[j] * rinv[j];
   __builtin_amdgcn_sched_barrier(0);
   if (lane < 16) {
 #pragma unroll
