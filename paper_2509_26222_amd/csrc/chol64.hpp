@@ -169,13 +169,20 @@ __device__ __forceinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int3
   __shared__ int bad;
   __shared__ double dinv[NB];
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) Ti[e >> 6][e & 63] = 0.0;
-  __syncthreads();
   for (int c0 = 0; c0 < NB; c0 += 16) {
     // ---- A: 16x16 diagonal block (wave 0, registers)
     if (wave == 0) {
       const bool ok = chol16_factor(T, dinv, c0);
       if (lane == 0 && !ok) bad = 1;
+    } else if (c0 == 0) {
+      // meanwhile waves 1-3 clear the strictly upper 16x16 blocks of L and
+      // of its inverse: no phase reads them, and the inverse's diagonal and
+      // lower blocks are all written below
+      for (int e = tid - 64; e < NB * NB; e += 192)
+        if (((e & 63) >> 4) > (e >> 10)) {
+          T[e >> 6][e & 63] = 0.0;
+          Ti[e >> 6][e & 63] = 0.0;
+        }
     }
     __syncthreads();
     const int nrb = (NB - c0 - 16) / 16;  // row blocks below the panel
@@ -200,10 +207,6 @@ __device__ __forceinline__ void chol64(double (*T)[LDT], double (*Ti)[LDT], int3
   // ---- the four diagonal inverses, one per wave
   diag_inverse(T, Ti, dinv, 16 * wave);
   __syncthreads();
-  // strictly upper 16x16 blocks of L are zero (the diagonal blocks were
-  // cleared above); the loop below reads only lower blocks of T
-  for (int e = tid; e < NB * NB; e += 256)
-    if (((e & 63) >> 4) > (e >> 10)) T[e >> 6][e & 63] = 0.0;
   // ---- off-diagonal blocks of the inverse, by block diagonals d = i - j
   for (int d = 1; d < 4; ++d) {
     const int nb = 4 - d;
