@@ -53,6 +53,47 @@ __device__ __forceinline__ double row_bcast16(double v, int k) {
   }
 }
 
+// a += v(lane k of its row of 16) * m as one v_fmac_f64 with a DPP
+// row_newbcast source (the only DPP control 64-bit operands take), instead
+// of two 32-bit broadcasts and an FMA. Same fused operation, so the same
+// result. A DPP read needs two wait states after the VALU write of its
+// source, which the compiler does not count across inline asm: `wait`
+// appends them (s_nop 1) where the written register is the next one read
+// through DPP (the next step's pivot column).
+template <int K>
+__device__ __forceinline__ void fmac_bcast16_k(double& a, double v, double m, bool wait) {
+  if (wait)
+    asm volatile(
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf\n\ts_nop 1"
+        : "+v"(a)
+        : "v"(v), "v"(m), "i"(K));
+  else
+    asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(a)
+                 : "v"(v), "v"(m), "i"(K));
+}
+// k must fold to a constant (unrolled loops), which leaves one case.
+__device__ __forceinline__ void fmac_bcast16(double& a, double v, double m, int k, bool wait) {
+  switch (k) {
+    case 0: fmac_bcast16_k<0>(a, v, m, wait); break;
+    case 1: fmac_bcast16_k<1>(a, v, m, wait); break;
+    case 2: fmac_bcast16_k<2>(a, v, m, wait); break;
+    case 3: fmac_bcast16_k<3>(a, v, m, wait); break;
+    case 4: fmac_bcast16_k<4>(a, v, m, wait); break;
+    case 5: fmac_bcast16_k<5>(a, v, m, wait); break;
+    case 6: fmac_bcast16_k<6>(a, v, m, wait); break;
+    case 7: fmac_bcast16_k<7>(a, v, m, wait); break;
+    case 8: fmac_bcast16_k<8>(a, v, m, wait); break;
+    case 9: fmac_bcast16_k<9>(a, v, m, wait); break;
+    case 10: fmac_bcast16_k<10>(a, v, m, wait); break;
+    case 11: fmac_bcast16_k<11>(a, v, m, wait); break;
+    case 12: fmac_bcast16_k<12>(a, v, m, wait); break;
+    case 13: fmac_bcast16_k<13>(a, v, m, wait); break;
+    case 14: fmac_bcast16_k<14>(a, v, m, wait); break;
+    default: fmac_bcast16_k<15>(a, v, m, wait); break;
+  }
+}
+
 // 16x16 product tile on FP64 MFMA: acc += A[r0.., a0..] * B where B[k][j] is
 // B_t[b0 + j][bk0 + k] (i.e. the operand is read transposed from LDS).
 __device__ __forceinline__ v4d mma16_nt(const double (*A)[LDT], int r0, int a0, const double (*Bt)[LDT],
@@ -97,10 +138,10 @@ __device__ __forceinline__ bool chol16_factor(double (*T)[LDT], double* dinv, in
     nbad += 1 - good;
     const double pv = good ? pj : 1.0;
     mypiv = (g == j) ? pv : mypiv;
-    const double t = a[j] * rcp_nr(pv);
+    const double negt = -(a[j] * rcp_nr(pv));
     // entries above the diagonal (lanes g < k) receive unused values
 #pragma unroll
-    for (int k = j + 1; k < 16; ++k) a[k] -= t * row_bcast16(a[j], k);
+    for (int k = j + 1; k < 16; ++k) fmac_bcast16(a[k], a[j], negt, k, k == j + 1);
   }
   __builtin_amdgcn_sched_barrier(0);
   // each lane takes the root and reciprocal of its own pivot (one square
