@@ -72,27 +72,41 @@ __device__ __forceinline__ void fmac_bcast16_k(double& a, double v, double m, bo
                  : "+v"(a)
                  : "v"(v), "v"(m), "i"(K));
 }
-// k must fold to a constant (unrolled loops), which leaves one case.
-__device__ __forceinline__ void fmac_bcast16(double& a, double v, double m, int k, bool wait) {
-  switch (k) {
-    case 0: fmac_bcast16_k<0>(a, v, m, wait); break;
-    case 1: fmac_bcast16_k<1>(a, v, m, wait); break;
-    case 2: fmac_bcast16_k<2>(a, v, m, wait); break;
-    case 3: fmac_bcast16_k<3>(a, v, m, wait); break;
-    case 4: fmac_bcast16_k<4>(a, v, m, wait); break;
-    case 5: fmac_bcast16_k<5>(a, v, m, wait); break;
-    case 6: fmac_bcast16_k<6>(a, v, m, wait); break;
-    case 7: fmac_bcast16_k<7>(a, v, m, wait); break;
-    case 8: fmac_bcast16_k<8>(a, v, m, wait); break;
-    case 9: fmac_bcast16_k<9>(a, v, m, wait); break;
-    case 10: fmac_bcast16_k<10>(a, v, m, wait); break;
-    case 11: fmac_bcast16_k<11>(a, v, m, wait); break;
-    case 12: fmac_bcast16_k<12>(a, v, m, wait); break;
-    case 13: fmac_bcast16_k<13>(a, v, m, wait); break;
-    case 14: fmac_bcast16_k<14>(a, v, m, wait); break;
-    default: fmac_bcast16_k<15>(a, v, m, wait); break;
-  }
+// a -= v(lane K of its row of 16) * m, the same instruction with the
+// multiplier negated by the operand modifier.
+template <int K>
+__device__ __forceinline__ void fnmac_bcast16_k(double& a, double v, double m) {
+  asm volatile("v_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(a)
+               : "v"(v), "v"(m), "i"(K));
 }
+// k must fold to a constant (unrolled loops), which leaves one case.
+#define RBF_BCAST16_CASES(F, ...)                                     \
+  switch (k) {                                                        \
+    case 0: F<0>(__VA_ARGS__); break;                                 \
+    case 1: F<1>(__VA_ARGS__); break;                                 \
+    case 2: F<2>(__VA_ARGS__); break;                                 \
+    case 3: F<3>(__VA_ARGS__); break;                                 \
+    case 4: F<4>(__VA_ARGS__); break;                                 \
+    case 5: F<5>(__VA_ARGS__); break;                                 \
+    case 6: F<6>(__VA_ARGS__); break;                                 \
+    case 7: F<7>(__VA_ARGS__); break;                                 \
+    case 8: F<8>(__VA_ARGS__); break;                                 \
+    case 9: F<9>(__VA_ARGS__); break;                                 \
+    case 10: F<10>(__VA_ARGS__); break;                               \
+    case 11: F<11>(__VA_ARGS__); break;                               \
+    case 12: F<12>(__VA_ARGS__); break;                               \
+    case 13: F<13>(__VA_ARGS__); break;                               \
+    case 14: F<14>(__VA_ARGS__); break;                               \
+    default: F<15>(__VA_ARGS__); break;                               \
+  }
+__device__ __forceinline__ void fmac_bcast16(double& a, double v, double m, int k, bool wait) {
+  RBF_BCAST16_CASES(fmac_bcast16_k, a, v, m, wait)
+}
+__device__ __forceinline__ void fnmac_bcast16(double& a, double v, double m, int k) {
+  RBF_BCAST16_CASES(fnmac_bcast16_k, a, v, m)
+}
+#undef RBF_BCAST16_CASES
 
 // 16x16 product tile on FP64 MFMA: acc += A[r0.., a0..] * B where B[k][j] is
 // B_t[b0 + j][bk0 + k] (i.e. the operand is read transposed from LDS).
@@ -167,16 +181,23 @@ __device__ __forceinline__ bool chol16_factor(double (*T)[LDT], double* dinv, in
 
 // Phase B for panel c0: row r (one per lane of waves 1..3, g = lane % 16)
 // solves l D^T = a for its 16 entries, D = the panel's diagonal factor.
+// Lane g also holds row g of D and 1 / D_gg, so D_kj and 1 / D_jj reach
+// every lane by DPP broadcast from lane k (resp. j) rather than as LDS
+// reads; the DPP sources come from LDS loads, never from a VALU write.
 __device__ __forceinline__ void panel_rows(double (*T)[LDT], const double* dinv, int c0, int r) {
   const int lane = threadIdx.x & 63;
-  double x[16];
+  const int g = lane & 15;
+  double x[16], d[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) x[k] = T[r][c0 + k];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    x[j] *= dinv[c0 + j];
+  for (int k = 0; k < 16; ++k) d[k] = T[c0 + g][c0 + k];
+  const double dv = dinv[c0 + g];
 #pragma unroll
-    for (int k = j + 1; k < 16; ++k) x[k] -= x[j] * T[c0 + k][c0 + j];
+  for (int j = 0; j < 16; ++j) {
+    x[j] *= row_bcast16(dv, j);
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) fnmac_bcast16(x[k], d[j], x[j], k);  // x_k -= D_kj x_j
   }
   if (lane < 16) {
 #pragma unroll
@@ -185,18 +206,24 @@ __device__ __forceinline__ void panel_rows(double (*T)[LDT], const double* dinv,
 }
 
 // Inverse of the 16x16 diagonal factor block at (b0, b0) into Ti (lane c of
-// the wave computes column c by forward substitution; D from LDS).
+// the wave computes column c by forward substitution). Lane g holds row g
+// of D and 1 / D_gg, broadcast by DPP as in panel_rows.
 __device__ __forceinline__ void diag_inverse(const double (*T)[LDT], double (*Ti)[LDT],
                                              const double* dinv, int b0) {
   const int lane = threadIdx.x & 63;
   const int g = lane & 15;
-  double x[16];
+  double x[16], d[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) d[k] = T[b0 + g][b0 + k];
+  const double dv = dinv[b0 + g];
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) {
     double s = (g == jj) ? 1.0 : 0.0;
 #pragma unroll
-    for (int q = 0; q < jj; ++q) s -= T[b0 + jj][b0 + q] * x[q];
-    x[jj] = (jj >= g) ? s * dinv[b0 + jj] : 0.0;
+    for (int q = 0; q < jj; ++q) fnmac_bcast16(s, d[q], x[q], jj);  // s -= D_jj,q x_q
+    // the broadcast is a statement of its own (not inside the select)
+    const double sj = s * row_bcast16(dv, jj);
+    x[jj] = (jj >= g) ? sj : 0.0;
   }
   if (lane < 16) {
 #pragma unroll
