@@ -20,7 +20,7 @@
 // B-operand layout of the next product's k-steps, so the two products chain
 // in registers. No panel waits for an inverse. A non-positive or non-finite
 // pivot records RBF_E_NOT_SPD with `index` for launch group `seq` (the
-// factor continues with pivot 1).
+// factor runs to its end; its output is then not used).
 #pragma once
 
 // Value of v in lane k of each row of 16 lanes: DPP row_newbcast (gfx90a
@@ -57,20 +57,15 @@ __device__ __forceinline__ double row_bcast16(double v, int k) {
 // row_newbcast source (the only DPP control 64-bit operands take), instead
 // of two 32-bit broadcasts and an FMA. Same fused operation, so the same
 // result. A DPP read needs two wait states after the VALU write of its
-// source, which the compiler does not count across inline asm: `wait`
-// appends them (s_nop 1) where the written register is the next one read
-// through DPP (the next step's pivot column).
+// source; the compiler pads its own DPP reads after inline asm, but not
+// the DPP read inside this asm, so every source given to it here is either
+// loaded from LDS or written several dependent instructions earlier (a
+// listing check over the compiled kernels confirms it).
 template <int K>
-__device__ __forceinline__ void fmac_bcast16_k(double& a, double v, double m, bool wait) {
-  if (wait)
-    asm volatile(
-        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf\n\ts_nop 1"
-        : "+v"(a)
-        : "v"(v), "v"(m), "i"(K));
-  else
-    asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-                 : "+v"(a)
-                 : "v"(v), "v"(m), "i"(K));
+__device__ __forceinline__ void fmac_bcast16_k(double& a, double v, double m) {
+  asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(a)
+               : "v"(v), "v"(m), "i"(K));
 }
 // a -= v(lane K of its row of 16) * m, the same instruction with the
 // multiplier negated by the operand modifier.
@@ -100,8 +95,8 @@ __device__ __forceinline__ void fnmac_bcast16_k(double& a, double v, double m) {
     case 14: F<14>(__VA_ARGS__); break;                               \
     default: F<15>(__VA_ARGS__); break;                               \
   }
-__device__ __forceinline__ void fmac_bcast16(double& a, double v, double m, int k, bool wait) {
-  RBF_BCAST16_CASES(fmac_bcast16_k, a, v, m, wait)
+__device__ __forceinline__ void fmac_bcast16(double& a, double v, double m, int k) {
+  RBF_BCAST16_CASES(fmac_bcast16_k, a, v, m)
 }
 __device__ __forceinline__ void fnmac_bcast16(double& a, double v, double m, int k) {
   RBF_BCAST16_CASES(fnmac_bcast16_k, a, v, m)
@@ -145,17 +140,23 @@ __device__ __forceinline__ bool chol16_factor(double (*T)[LDT], double* dinv, in
   for (int k = 0; k < 16; ++k) a[k] = T[c0 + g][c0 + k];
   int nbad = 0;  // counted without branches: the 16 steps stay one block
   double mypiv = 1.0;  // lane g keeps pivot g
+  // The pivot test stays off the dependent chain of the steps: a pivot that
+  // is not positive and finite is counted (the batch is then discarded
+  // through the status word) and the factor goes on with it. Each step
+  // updates the next pivot column first and broadcasts the next pivot.
+  double pj = row_bcast16(a[0], 0);
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double pj = row_bcast16(a[j], j);
-    const int good = (int)(pj > 0.0) & (int)(pj < INFINITY);
-    nbad += 1 - good;
-    const double pv = good ? pj : 1.0;
-    mypiv = (g == j) ? pv : mypiv;
-    const double negt = -(a[j] * rcp_nr(pv));
+    nbad += 1 - ((int)(pj > 0.0) & (int)(pj < INFINITY));
+    mypiv = (g == j) ? pj : mypiv;
+    const double negt = -(a[j] * rcp_nr(pj));
     // entries above the diagonal (lanes g < k) receive unused values
+    if (j + 1 < 16) {
+      fmac_bcast16(a[j + 1], a[j], negt, j + 1);
+      pj = row_bcast16(a[j + 1], j + 1);
+    }
 #pragma unroll
-    for (int k = j + 1; k < 16; ++k) fmac_bcast16(a[k], a[j], negt, k, k == j + 1);
+    for (int k = j + 2; k < 16; ++k) fmac_bcast16(a[k], a[j], negt, k);
   }
   __builtin_amdgcn_sched_barrier(0);
   // each lane takes the root and reciprocal of its own pivot (one square
