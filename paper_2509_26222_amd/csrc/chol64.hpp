@@ -4,16 +4,21 @@
 //
 // Right-looking over four 16-column panels. For panel c0:
 //   A. wave 0 factors the 16x16 diagonal block in registers, one row per lane
-//      (lane g, g = lane % 16, holds row g); step j takes the pivot and the
-//      column entries from their lanes with DPP row broadcasts (no LDS, no
-//      barrier) and scales by the pivot's reciprocal only; after the 16
-//      steps lane j takes the square root of pivot j and its reciprocal, and
-//      broadcasts the reciprocal. It writes L and 1 / L_jj;
+//      (lane g, g = lane % 16, holds row g); step j takes the pivot from its
+//      lane with a DPP row broadcast and updates the later columns with
+//      FP64 FMAs whose column entry comes from its lane through the FMA's
+//      own DPP source (no LDS, no barrier), scaling by the pivot's
+//      reciprocal only; after the 16 steps lane j takes the square root of
+//      pivot j and its reciprocal, and broadcasts the reciprocal. It writes
+//      L and 1 / L_jj;
 //   B. the panel rows below, L_p D^T = A_p, by forward substitution in
-//      registers (waves 1-3, one row per lane, D read from LDS);
+//      registers (waves 1-3, one row per lane; lane g also holds row g of
+//      the diagonal factor D, whose entries reach the other lanes the same
+//      way);
 //   C. the trailing lower blocks: A_rs -= L_r L_s^T (FP64 MFMA).
 // Then the four diagonal 16x16 inverses, one per wave, by forward
-// substitution (lane c holds column c), and the off-diagonal 16x16 blocks
+// substitution (lane c holds column c, lane g row g of D), and the
+// off-diagonal 16x16 blocks
 // of the inverse by block diagonals:
 //   Linv_ij = -Linv_ii sum_{j<=k<i} L_ik Linv_kj,
 // where the f64 MFMA output layout (lane j + 16 (i % 4), item i / 4) is the
