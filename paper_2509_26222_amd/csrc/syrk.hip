@@ -192,13 +192,14 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P,
 // Tail of the FP64 product. A launch of 128x128 tiles runs in rounds of
 // (workgroups per CU x CUs per XCD) tiles per XCD; the tiles past the last
 // full round would leave most CUs idle while they finish. They are computed
-// instead as 64x64 sub-tiles by this kernel (4 waves, each 32 x 32 = 2 x 2
-// MFMA blocks), four per tile (three on the diagonal: the upper-right one
+// instead as 64x64 sub-tiles by this kernel (8 waves, each 16 x 32 = 1 x 2
+// MFMA blocks: with one 16-deep stage of MFMA work per wave this short,
+// more waves per SIMD hide the stage loads), four per tile (three on the diagonal: the upper-right one
 // is the mirror of the lower-left). Every element accumulates the same
 // MFMAs over k in the same order as in the 128x128 kernel, so the result is
 // bit for bit the same. Local tiles main_per_xcd .. per_xcd - 1 of each XCD.
 constexpr int SUB = 64;
-constexpr int SUB_NT = 256;
+constexpr int SUB_NT = 512;
 constexpr int SUB_LD = SUB + 8;
 
 __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P, int64_t ldp,
@@ -226,12 +227,10 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
   __shared__ double As[2][SKC][SUB_LD];
   __shared__ double Bs[2][SKC][SUB_LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;  // rows wm*32.., columns wn*32..
-  v4d acc[2][2];
+  const int wm = wave >> 1, wn = wave & 1;  // rows wm*16.., columns wn*32..
+  v4d acc[2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < 2; ++b) acc[b] = (v4d){0.0, 0.0, 0.0, 0.0};
   const int nch = (K + SKC - 1) / SKC;
   double2 ra[16 * SUB / 2 / SUB_NT], rb[16 * SUB / 2 / SUB_NT];
   load_stage<SUB_NT, SUB>(Ut, ldu, N, 0, K, I0, ra);
@@ -248,16 +247,13 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
 #pragma unroll
     for (int kk = 0; kk < SKC; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a[2], b[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
+      const double a = As[buf][kr][wm * 16 + (lane & 15)];
+      double b[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) b[q] = Bs[buf][kr][wn * 32 + q * 16 + (lane & 15)];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+      for (int ni = 0; ni < 2; ++ni)
+        acc[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ni], acc[ni], 0, 0, 0);
     }
     if (ch + 1 < nch) {
       store_stage<SUB_NT, SUB_LD, SUB>(As[buf ^ 1], ra);
@@ -267,19 +263,17 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
   }
   const bool diag = (I == J && si == sj);
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * v + (lane >> 4);
-        const int64_t gj = J0 + wn * 32 + ni * 16 + (lane & 15);
-        if (gi < N && gj < N && (!diag || gi >= gj)) {
-          const double nv = P[gi * ldp + gj] - acc[mi][ni][v];
-          P[gi * ldp + gj] = nv;
-          if (gi != gj) P[gj * ldp + gi] = nv;
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gi = I0 + wm * 16 + 4 * v + (lane >> 4);
+      const int64_t gj = J0 + wn * 32 + ni * 16 + (lane & 15);
+      if (gi < N && gj < N && (!diag || gi >= gj)) {
+        const double nv = P[gi * ldp + gj] - acc[ni][v];
+        P[gi * ldp + gj] = nv;
+        if (gi != gj) P[gj * ldp + gi] = nv;
       }
+    }
 }
 
 // Triangular solve of the update as one product: V^T = X U^T with
