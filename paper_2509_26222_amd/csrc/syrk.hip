@@ -192,15 +192,17 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P,
 // Tail of the FP64 product. A launch of 128x128 tiles runs in rounds of
 // (workgroups per CU x CUs per XCD) tiles per XCD; the tiles past the last
 // full round would leave most CUs idle while they finish. They are computed
-// instead as 64x64 sub-tiles by this kernel (8 waves, each 16 x 32 = 1 x 2
-// MFMA blocks: with one 16-deep stage of MFMA work per wave this short,
-// more waves per SIMD hide the stage loads), four per tile (three on the diagonal: the upper-right one
-// is the mirror of the lower-left). Every element accumulates the same
-// MFMAs over k in the same order as in the 128x128 kernel, so the result is
-// bit for bit the same. Local tiles main_per_xcd .. per_xcd - 1 of each XCD.
-constexpr int SUB = 64;
+// instead as 32x64 sub-tiles by this kernel, eight per tile (six on the
+// diagonal: the two above it are mirrors), each on 8 waves of 16 x 16 (one
+// MFMA block): many short workgroups spread the leftover work over the
+// chip and keep several waves per SIMD to hide the short stages' loads.
+// Every element accumulates the same MFMAs over k in the same order as in
+// the 128x128 kernel, so the result is bit for bit the same. Local tiles
+// main_per_xcd .. per_xcd - 1 of each XCD.
+constexpr int SUB_M = 32;
+constexpr int SUB_N = 64;
 constexpr int SUB_NT = 512;
-constexpr int SUB_LD = SUB + 8;
+constexpr int SUB_PER_TILE = (ST / SUB_M) * (ST / SUB_N);
 
 __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P, int64_t ldp,
                                                           int64_t N,
@@ -213,67 +215,63 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
                                                           int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t bid = blockIdx.x;
-  const int64_t local = main_per_xcd + ((bid >> 3) >> 2);
-  const int sub = (int)((bid >> 3) & 3), si = sub >> 1, sj = sub & 1;
+  const int64_t local = main_per_xcd + (bid >> 3) / SUB_PER_TILE;
+  const int sub = (int)((bid >> 3) % SUB_PER_TILE);
+  const int si = sub / (ST / SUB_N), sj = sub % (ST / SUB_N);
   if (local >= per_xcd) return;
   const int64_t t = (bid & 7) * per_xcd + local;
   if (t >= T) return;
   int I, J;
   tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
   if (!tile_in_part(flags, part, I, J)) return;
-  if (I == J && si < sj) return;
-  const int64_t I0 = (int64_t)I * ST + si * SUB, J0 = (int64_t)J * ST + sj * SUB;
+  if (I == J && si * SUB_M + SUB_M - 1 < sj * SUB_N) return;  // above the diagonal
+  const int64_t I0 = (int64_t)I * ST + si * SUB_M, J0 = (int64_t)J * ST + sj * SUB_N;
   if (I0 >= N || J0 >= N) return;
-  __shared__ double As[2][SKC][SUB_LD];
-  __shared__ double Bs[2][SKC][SUB_LD];
+  __shared__ double As[2][SKC][SUB_M + 8];
+  __shared__ double Bs[2][SKC][SUB_N + 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;  // rows wm*16.., columns wn*32..
-  v4d acc[2];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) acc[b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int wm = wave >> 2, wn = wave & 3;  // rows wm*16.., columns wn*16..
+  v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
   const int nch = (K + SKC - 1) / SKC;
-  double2 ra[16 * SUB / 2 / SUB_NT], rb[16 * SUB / 2 / SUB_NT];
-  load_stage<SUB_NT, SUB>(Ut, ldu, N, 0, K, I0, ra);
-  load_stage<SUB_NT, SUB>(Ut, ldu, N, 0, K, J0, rb);
-  store_stage<SUB_NT, SUB_LD, SUB>(As[0], ra);
-  store_stage<SUB_NT, SUB_LD, SUB>(Bs[0], rb);
+  // a stage: the 16 x 32 slice of the row panel (threads 0-255, one double2
+  // each) and the 16 x 64 slice of the column panel (all 512 threads)
+  constexpr int NA = SUB_NT / 2;
+  double2 ra[1], rb[1];
+  if (tid < NA) load_stage<NA, SUB_M>(Ut, ldu, N, 0, K, I0, ra);
+  load_stage<SUB_NT, SUB_N>(Ut, ldu, N, 0, K, J0, rb);
+  if (tid < NA) store_stage<NA, SUB_M + 8, SUB_M>(As[0], ra);
+  store_stage<SUB_NT, SUB_N + 8, SUB_N>(Bs[0], rb);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nch) {
-      load_stage<SUB_NT, SUB>(Ut, ldu, N, (ch + 1) * SKC, K, I0, ra);
-      load_stage<SUB_NT, SUB>(Ut, ldu, N, (ch + 1) * SKC, K, J0, rb);
+      if (tid < NA) load_stage<NA, SUB_M>(Ut, ldu, N, (ch + 1) * SKC, K, I0, ra);
+      load_stage<SUB_NT, SUB_N>(Ut, ldu, N, (ch + 1) * SKC, K, J0, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < SKC; kk += 4) {
       const int kr = kk + (lane >> 4);
-      const double a = As[buf][kr][wm * 16 + (lane & 15)];
-      double b[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) b[q] = Bs[buf][kr][wn * 32 + q * 16 + (lane & 15)];
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-        acc[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ni], acc[ni], 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kr][wm * 16 + (lane & 15)],
+                                                 Bs[buf][kr][wn * 16 + (lane & 15)], acc, 0,
+                                                 0, 0);
     }
     if (ch + 1 < nch) {
-      store_stage<SUB_NT, SUB_LD, SUB>(As[buf ^ 1], ra);
-      store_stage<SUB_NT, SUB_LD, SUB>(Bs[buf ^ 1], rb);
+      if (tid < NA) store_stage<NA, SUB_M + 8, SUB_M>(As[buf ^ 1], ra);
+      store_stage<SUB_NT, SUB_N + 8, SUB_N>(Bs[buf ^ 1], rb);
     }
     __syncthreads();
   }
-  const bool diag = (I == J && si == sj);
+  const bool diag = (I == J);
 #pragma unroll
-  for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t gi = I0 + wm * 16 + 4 * v + (lane >> 4);
-      const int64_t gj = J0 + wn * 32 + ni * 16 + (lane & 15);
-      if (gi < N && gj < N && (!diag || gi >= gj)) {
-        const double nv = P[gi * ldp + gj] - acc[ni][v];
-        P[gi * ldp + gj] = nv;
-        if (gi != gj) P[gj * ldp + gi] = nv;
-      }
+  for (int v = 0; v < 4; ++v) {
+    const int64_t gi = I0 + wm * 16 + 4 * v + (lane >> 4);
+    const int64_t gj = J0 + wn * 16 + (lane & 15);
+    if (gi < N && gj < N && (!diag || gi >= gj)) {
+      const double nv = P[gi * ldp + gj] - acc[v];
+      P[gi * ldp + gj] = nv;
+      if (gi != gj) P[gj * ldp + gi] = nv;
     }
+  }
 }
 
 // Triangular solve of the update as one product: V^T = X U^T with
@@ -731,7 +729,7 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
       RBF_LAUNCHED(ctx, "k_syrk_f64");
     }
     if (main_per_xcd < per_xcd) {
-      const unsigned gt = (unsigned)((per_xcd - main_per_xcd) * 8 * 4);
+      const unsigned gt = (unsigned)((per_xcd - main_per_xcd) * 8 * SUB_PER_TILE);
       k_syrk_f64_tail<<<gt, SUB_NT, 0, ctx->stream>>>(P, ldp, N, Ut, ldu, Bc, T, per_xcd,
                                                       main_per_xcd, flags, part, ctx->d_status,
                                                       seq);
