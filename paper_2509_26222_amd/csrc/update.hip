@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S
 // launch also carries the inverse's work of step kb (linv_work: kb + kb *
 // (nblk - 1 - kb) workgroups of one or two block products), beside the
 // critical path of the factor.
-__global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32_t Bp,
+__global__ void __launch_bounds__(256, 2) k_chol_step(double* __restrict__ S, int32_t Bp,
                                                    int32_t nblk, int32_t kb,
                                                    double* __restrict__ Lb,
                                                    double* __restrict__ Linv,
@@ -589,12 +589,14 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
                                                    int32_t* __restrict__ status, int64_t batch,
                                                    int64_t seq) {
   if (seq_skip(status, seq)) return;
-  __shared__ double Li[NB][LDT], T1[NB][LDT], T2[NB][LDT];
+  // two 64x64 tiles of LDS (67 KB) in every role, so a step workgroup fits
+  // on a CU beside one covariance-product workgroup
+  __shared__ double Ta[NB][LDT], Tb[NB][LDT];
   const int m = nblk - kb - 1;
   const int t = blockIdx.x;
   const int nfac = m + m * (m + 1) / 2;
   if (t >= nfac) {
-    linv_work(t - nfac, kb, Bp, Lb, Linv, LiT, T1, T2);
+    linv_work(t - nfac, kb, Bp, Lb, Linv, LiT, Ta, Tb);
     return;
   }
   int i, j;
@@ -612,12 +614,11 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
     i = kb + 1 + ii;
     j = kb + 1 + (u - ii * (ii + 1) / 2);
   }
-  load_tile(Li, Linv + (int64_t)kb * NB * NB, NB);
-  load_tile(T1, S + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
-  if (!panel && j != i) load_tile(T2, S + (int64_t)j * NB * Bp + (int64_t)kb * NB, Bp);
+  load_tile(Ta, Linv + (int64_t)kb * NB * NB, NB);
+  load_tile(Tb, S + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
   __syncthreads();
   Acc64 A;
-  mm_nt(T1, Li, A);  // L_ik = A_ik Linv_kk^T
+  mm_nt(Tb, Ta, A);  // L_ik = A_ik Linv_kk^T
   if (panel) {
     double* out = Lb + (int64_t)i * NB * Bp + (int64_t)kb * NB;
 #pragma unroll
@@ -630,13 +631,20 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
     return;
   }
   Acc64 Bq;
-  if (j != i) mm_nt(T2, Li, Bq);  // L_jk
+  if (j != i) {
+    // L_jk = A_jk Linv_kk^T, with A_jk loaded over A_ik (now in registers)
+    __syncthreads();
+    load_tile(Tb, S + (int64_t)j * NB * Bp + (int64_t)kb * NB, Bp);
+    __syncthreads();
+    mm_nt(Tb, Ta, Bq);
+  }
   __syncthreads();
-  acc_to_lds(A, T1);  // T1 = L_ik
-  if (j != i) acc_to_lds(Bq, T2);  // T2 = L_jk
+  // Linv_kk is no longer needed: Ta = L_ik, Tb = L_jk
+  acc_to_lds(A, Ta);
+  if (j != i) acc_to_lds(Bq, Tb);
   __syncthreads();
   Acc64 U;
-  mm_nt(T1, (j != i) ? T2 : T1, U);  // L_ik L_jk^T
+  mm_nt(Ta, (j != i) ? Tb : Ta, U);  // L_ik L_jk^T
   double* Aij = S + (int64_t)i * NB * Bp + (int64_t)j * NB;
   if (i == kb + 1 && j == kb + 1) {
     __syncthreads();
@@ -647,13 +655,13 @@ __global__ void __launch_bounds__(256) k_chol_step(double* __restrict__ S, int32
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = acc_row(mi, v), c = acc_col(ni);
-          Li[r][c] = Aij[(int64_t)r * Bp + c] - U.c[mi][ni][v];
+          Tb[r][c] = Aij[(int64_t)r * Bp + c] - U.c[mi][ni][v];
         }
     __syncthreads();
-    chol64(Li, T2, status, batch, seq);
-    store_tile(Li, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
-    store_tile(T2, Linv + (int64_t)i * NB * NB, NB);
-    if (LiT) store_tile_t(T2, LiT + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
+    chol64(Tb, Ta, status, batch, seq);
+    store_tile(Tb, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
+    store_tile(Ta, Linv + (int64_t)i * NB * NB, NB);
+    if (LiT) store_tile_t(Ta, LiT + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
     return;
   }
 #pragma unroll
