@@ -137,7 +137,9 @@ __global__ void __launch_bounds__(256) k_upd_gather_u(
 // by an LDS bitmap over the N centers, ranked in ascending order by a
 // popcount scan. Writes the list (padded to a multiple of 4 with row 0) and
 // the dense block H_g[rank][row] (zero where a row has no entry).
-__global__ void __launch_bounds__(256) k_gather_groups(
+constexpr int GG_NT = 1024;  // threads per group of 64 batch rows
+
+__global__ void __launch_bounds__(GG_NT) k_gather_groups(
     const double* __restrict__ vals, const int32_t* __restrict__ cols,
     const int32_t* __restrict__ nnz, int32_t Bc, int32_t Bp, int32_t kmax, int32_t words,
     int64_t Rcap, int32_t* __restrict__ glist, int32_t* __restrict__ gR,
@@ -146,15 +148,15 @@ __global__ void __launch_bounds__(256) k_gather_groups(
   extern __shared__ uint32_t gsm[];
   uint32_t* bits = gsm;
   int32_t* wbase = (int32_t*)(gsm + words);
-  int32_t* tsum = wbase + words;  // 256 + 1
+  int32_t* tsum = wbase + words;  // one per wave
   const int tid = threadIdx.x;
   const int g = blockIdx.x, b0 = 64 * g;
   int32_t* L = glist + (int64_t)g * Rcap;
   double* H = gH + (int64_t)g * Rcap * 64;
-  for (int w = tid; w < words; w += 256) bits[w] = 0u;
+  for (int w = tid; w < words; w += GG_NT) bits[w] = 0u;
   __syncthreads();
   const int ne = 64 * kmax;
-  for (int e = tid; e < ne; e += 256) {
+  for (int e = tid; e < ne; e += GG_NT) {
     const int b = b0 + (e & 63), q = e >> 6;
     if (b < Bc && q < nnz[b]) {
       const int32_t c = cols[(int64_t)q * Bp + b];
@@ -162,23 +164,27 @@ __global__ void __launch_bounds__(256) k_gather_groups(
     }
   }
   __syncthreads();
-  const int per = (words + 255) / 256;
+  const int per = (words + GG_NT - 1) / GG_NT;
   const int w0 = tid * per, w1 = min(w0 + per, words);
   int cnt = 0;
   for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
-  tsum[tid] = cnt;
-  __syncthreads();
-  if (tid == 0) {  // 256 partial counts, in order
-    int run = 0;
-    for (int t = 0; t < 256; ++t) {
-      const int v = tsum[t];
-      tsum[t] = run;
-      run += v;
-    }
-    tsum[256] = run;
+  // exclusive scan of the counts in thread order: a shuffle scan in each
+  // wave, then the totals of the waves before
+  const int lane = tid & 63, wv = tid >> 6;
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
   }
+  if (lane == 63) tsum[wv] = incl;
   __syncthreads();
-  int base = tsum[tid];
+  int base = incl - cnt;
+  int R = 0;
+  for (int w = 0; w < GG_NT / 64; ++w) {
+    if (w < wv) base += tsum[w];
+    R += tsum[w];
+  }
   for (int w = w0; w < w1; ++w) {
     wbase[w] = base;
     uint32_t m = bits[w];
@@ -187,13 +193,12 @@ __global__ void __launch_bounds__(256) k_gather_groups(
       m &= m - 1u;
     }
   }
-  const int R = tsum[256];
   const int R4 = (R + 3) & ~3;
   if (tid < R4 - R) L[R + tid] = 0;  // padding ranks: a valid row, zero H
   if (tid == 0) gR[g] = R4;
-  for (int e = tid; e < R4 * 64; e += 256) H[e] = 0.0;
+  for (int e = tid; e < R4 * 64; e += GG_NT) H[e] = 0.0;
   __syncthreads();  // zeros stored before the values below
-  for (int e = tid; e < ne; e += 256) {
+  for (int e = tid; e < ne; e += GG_NT) {
     const int bl = e & 63, b = b0 + bl, q = e >> 6;
     if (b < Bc && q < nnz[b]) {
       const int32_t c = cols[(int64_t)q * Bp + b];
@@ -1181,8 +1186,8 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     prof_begin(ctx, RBF_PROF_GATHER);
     if (ws.gH) {
       const int32_t words = (int32_t)ceil_div(N, 32);
-      const size_t lds = sizeof(uint32_t) * (2 * (size_t)words + 257);
-      k_gather_groups<<<Bpc / 64, 256, lds, ctx->stream>>>(vals, cols, nnz, Bc, Bpc, kmax, words,
+      const size_t lds = sizeof(uint32_t) * (2 * (size_t)words + GG_NT / 64);
+      k_gather_groups<<<Bpc / 64, GG_NT, lds, ctx->stream>>>(vals, cols, nnz, Bc, Bpc, kmax, words,
                                                            ws.Rcap, ws.glist, ws.gR, ws.gH,
                                                            ctx->d_status, sq);
       RBF_LAUNCHED(ctx, "k_gather_groups");
