@@ -340,15 +340,36 @@ __global__ void __launch_bounds__(256) k_upd_S_groups(
   const int32_t* L = glist + (int64_t)ga * Rcap;
   const double* H = gH + (int64_t)ga * Rcap * 64;
   const int R4 = gR[ga];
-  if (R4 > GATHER_GROUP_RMAX) return;  // left to k_upd_S
+  if (R4 > GATHER_GROUP_RMAX) return;  // left to k_upd_S (uniform per workgroup)
+  // the group's row list in LDS, so that the value loads of four k-steps
+  // can be issued together below (each step's value load needs its index)
+  __shared__ int32_t Ls[GATHER_GROUP_RMAX];
+  for (int e = threadIdx.x; e < R4; e += 256) Ls[e] = L[e];
+  __syncthreads();
   const int bcol = gb * 64 + wave * 16 + li;  // < Bp
   const double* urow = Ut + (int64_t)bcol * ldu;
   v4d acc[4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi) acc[mi] = (v4d){0.0, 0.0, 0.0, 0.0};
-  for (int r = 0; r < R4; r += 4) {
+  int r = 0;
+  for (; r + 16 <= R4; r += 16) {
+    double bv[4], hv[4][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kr = r + 4 * st + kq;
+      bv[st] = urow[Ls[kr]];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) hv[st][mi] = H[(int64_t)kr * 64 + 16 * mi + li];
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+        acc[mi] = __builtin_amdgcn_mfma_f64_16x16x4f64(hv[st][mi], bv[st], acc[mi], 0, 0, 0);
+  }
+  for (; r < R4; r += 4) {
     const int kr = r + kq;
-    const double bv = urow[L[kr]];
+    const double bv = urow[Ls[kr]];
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
       acc[mi] = __builtin_amdgcn_mfma_f64_16x16x4f64(H[(int64_t)kr * 64 + 16 * mi + li], bv,
