@@ -599,6 +599,67 @@ __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S
   if (LiT) store_tile_t(Ti, LiT, Bp);
 }
 
+// The diagonal workgroup of step kb (the launch's critical path), with Ta =
+// Linv_kk and Tb = A_ik (i = kb + 1) loaded: L_ik = A_ik Linv_kk^T, then
+// A_ii - L_ik L_ik^T factored in place. The two products use their zero
+// structure with the work balanced over the four waves, each element
+// keeping the MFMA sequence over k of the full product: wave w forms row
+// block w of L_ik, where column block n needs k < 16 (n + 1) only (Linv_kk
+// is lower triangular; 40 k-steps per wave instead of 64); the lower 16x16
+// blocks of L_ik L_ik^T, the only ones the factor reads, are dealt round
+// robin (at most 3 blocks, 48 k-steps, per wave).
+__device__ inline void chol_step_diag(const double* __restrict__ S, int32_t Bp, int i,
+                                      double* __restrict__ Lb, double* __restrict__ Linv,
+                                      double* __restrict__ LiT, double (*Ta)[LDT],
+                                      double (*Tb)[LDT], int32_t* __restrict__ status,
+                                      int64_t batch, int64_t seq) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  v4d l[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    l[n] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16 * (n + 1); k += 4)
+      l[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(Tb[16 * wave + li][k + kq],
+                                                  Ta[16 * n + li][k + kq], l[n], 0, 0, 0);
+  }
+  __syncthreads();  // every wave is done with Linv_kk
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ta[16 * wave + 4 * v + kq][16 * n + li] = l[n][v];
+  __syncthreads();
+  const double* Aii = S + (int64_t)i * NB * Bp + (int64_t)i * NB;
+  // lower blocks (r, n), n <= r, in order 0:(0,0) 1:(1,0) 2:(1,1) 3:(2,0)
+  // 4:(2,1) 5:(2,2) 6:(3,0) 7:(3,1) 8:(3,2) 9:(3,3); wave w takes w, w+4, w+8
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int b = wave + 4 * q;
+    if (b < 10) {
+      const int r = b < 1 ? 0 : b < 3 ? 1 : b < 6 ? 2 : 3;
+      const int n = b - r * (r + 1) / 2;
+      v4d u = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < NB; k += 4)
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(Ta[16 * r + li][k + kq],
+                                                 Ta[16 * n + li][k + kq], u, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = 16 * r + 4 * v + kq, cc = 16 * n + li;
+        Tb[rr][cc] = Aii[(int64_t)rr * Bp + cc] - u[v];
+      }
+    }
+  }
+  __syncthreads();
+  // the strictly upper blocks of Tb still hold A_ik; the factor clears them
+  // without reading them
+  chol64(Tb, Ta, status, batch, seq);
+  store_tile(Tb, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
+  store_tile(Ta, Linv + (int64_t)i * NB * NB, NB);
+  if (LiT) store_tile_t(Ta, LiT + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
+}
+
 // Step kb of the right-looking blocked Cholesky, one launch per block
 // column. Tiles t < m are panel tiles (i = kb+1+t): L_ik = A_ik Linv_kk^T.
 // Then come the trailing tiles (i, j), kb < j <= i: they recompute L_ik and
@@ -643,6 +704,10 @@ __global__ void __launch_bounds__(256, 2) k_chol_step(double* __restrict__ S, in
   load_tile(Ta, Linv + (int64_t)kb * NB * NB, NB);
   load_tile(Tb, S + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
   __syncthreads();
+  if (!panel && i == kb + 1 && j == kb + 1) {
+    chol_step_diag(S, Bp, i, Lb, Linv, LiT, Ta, Tb, status, batch, seq);
+    return;
+  }
   Acc64 A;
   mm_nt(Tb, Ta, A);  // L_ik = A_ik Linv_kk^T
   if (panel) {
@@ -672,24 +737,6 @@ __global__ void __launch_bounds__(256, 2) k_chol_step(double* __restrict__ S, in
   Acc64 U;
   mm_nt(Ta, (j != i) ? Tb : Ta, U);  // L_ik L_jk^T
   double* Aij = S + (int64_t)i * NB * Bp + (int64_t)j * NB;
-  if (i == kb + 1 && j == kb + 1) {
-    __syncthreads();
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = acc_row(mi, v), c = acc_col(ni);
-          Tb[r][c] = Aij[(int64_t)r * Bp + c] - U.c[mi][ni][v];
-        }
-    __syncthreads();
-    chol64(Tb, Ta, status, batch, seq);
-    store_tile(Tb, Lb + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
-    store_tile(Ta, Linv + (int64_t)i * NB * NB, NB);
-    if (LiT) store_tile_t(Ta, LiT + (int64_t)i * NB * Bp + (int64_t)i * NB, Bp);
-    return;
-  }
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
