@@ -407,13 +407,57 @@ __global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ U
 // P -= C (FP32 accumulators) for the 8-wave layout (wave: rows wm*32 +
 // 2 x 16, columns wn*64 + 4 x 16), written to both triangles as in the FP64
 // kernel.
+//
+// BATCH: per half, the P values are loaded, then all new values formed,
+// then the stores. Element by element, a load that follows a store to P
+// may alias it, so the compiler waits out a memory round trip per element;
+// the loads (this thread's lower elements) and the stores (the same
+// elements and their upper mirrors) never overlap, and each element's
+// arithmetic is the same. It pays in the BF16x3 kernel (0.63 -> 0.54 ms per
+// product at N = 10,000); the FP32 and FP64 kernels, MFMA-bound with
+// registers to the limit, were slower with it and keep the element order.
+template <bool BATCH>
 __device__ inline void epilogue_f32acc_w8(double* __restrict__ P, int64_t ldp, int64_t N,
                                           int64_t I0, int64_t J0, bool diag,
                                           const v4f acc[2][4]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  if (!BATCH) {
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+          const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+          if (gi < N && gj < N && (!diag || gi >= gj)) {
+            const double nv = P[gi * ldp + gj] - (double)acc[mi][ni][v];
+            P[gi * ldp + gj] = nv;
+            if (gi != gj) P[gj * ldp + gi] = nv;
+          }
+        }
+    return;
+  }
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi) {
+    double pv[4][4];
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
+        pv[ni][v] = (gi < N && gj < N && (!diag || gi >= gj)) ? P[gi * ldp + gj] : 0.0;
+      }
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        pv[ni][v] -= (double)acc[mi][ni][v];
+        // keeps the subtraction from moving down into its store's branch
+        asm volatile("" : "+v"(pv[ni][v]));
+      }
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
@@ -421,11 +465,11 @@ __device__ inline void epilogue_f32acc_w8(double* __restrict__ P, int64_t ldp, i
         const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
         const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
         if (gi < N && gj < N && (!diag || gi >= gj)) {
-          const double nv = P[gi * ldp + gj] - (double)acc[mi][ni][v];
-          P[gi * ldp + gj] = nv;
-          if (gi != gj) P[gj * ldp + gi] = nv;
+          P[gi * ldp + gj] = pv[ni][v];
+          if (gi != gj) P[gj * ldp + gi] = pv[ni][v];
         }
       }
+  }
 }
 
 constexpr int FKC = 32;      // rows of V^T per stage (FP32)
@@ -527,7 +571,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
     }
     __syncthreads();
   }
-  epilogue_f32acc_w8(P, ldp, N, I0, J0, I == J, acc);
+  epilogue_f32acc_w8<false>(P, ldp, N, I0, J0, I == J, acc);
 }
 
 // The triangular solve's product V^T = X U^T of the mixed form on FP32 MFMA
@@ -706,7 +750,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
         }
     }
   }
-  epilogue_f32acc_w8(P, ldp, N, I0, J0, I == J, acc);
+  epilogue_f32acc_w8<true>(P, ldp, N, I0, J0, I == J, acc);
 }
 
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
