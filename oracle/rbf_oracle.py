@@ -94,14 +94,6 @@ def regressor_csr(x, c, sigma, cutoff, sigma_eps, chunk=2048):
     return sp.vstack(blocks, format="csr")
 
 
-def ell_rows(Phi):
-    """Point-major ELL view of a dense kernel matrix: for each row, the
-    nonzero columns in ascending order and their values."""
-    cols = [np.flatnonzero(r) for r in Phi]
-    vals = [Phi[i, cc] for i, cc in enumerate(cols)]
-    return cols, vals
-
-
 # ---------------------------------------------------------------------------
 # Adaptive center selection (subsection "The RBF Approximation Model")
 # ---------------------------------------------------------------------------

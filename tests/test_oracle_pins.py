@@ -157,6 +157,61 @@ def test_gram_pattern_covers_nonzeros():
         assert nz <= set(pat[j].tolist())
 
 
+@pytest.mark.parametrize("seps", [0.0, 0.1])
+def test_gram_pattern_equals_kdtree_pairs(seps):
+    """Exact row-by-row equality with scipy's k-d tree pair search at the
+    radius 2 * cutoff * sqrt(sigma^2 + sigma_eps^2) (diagonal included), on
+    jittered centers (no pair distance sits on the radius)."""
+    rng = np.random.default_rng(11)
+    c = synth.grid_centers(rng, 24, 20, 0.5)
+    r = 2.0 * CUT * math.sqrt(SIG * SIG + seps * seps)
+    pairs = cKDTree(c).query_pairs(r, output_type="ndarray")
+    N = c.shape[0]
+    ref = [{j} for j in range(N)]
+    for a, b in pairs:
+        ref[a].add(int(b))
+        ref[b].add(int(a))
+    pat = O.gram_pattern(c, SIG, CUT, seps)
+    assert len(pat) == N
+    for j in range(N):
+        assert pat[j].tolist() == sorted(ref[j])
+    # sigma_eps widens the pattern: the sigma_t radius, not sigma's
+    if seps > 0.0:
+        narrow = O.gram_pattern(c, SIG, CUT, 0.0)
+        assert sum(len(a) for a in pat) > sum(len(a) for a in narrow)
+
+
+@pytest.mark.parametrize("seps,bound", [(0.0, 36), (0.1, 37)])
+def test_gram_pattern_on_lattice_is_integer_disc(seps, bound):
+    """Unjittered 0.5 m lattice: centers (a, b) and (a', b') pair iff
+    (a-a')^2 + (b-b')^2 <= (2 cutoff sigma_t / 0.5)^2, i.e. <= 36 at
+    sigma_eps = 0 (the tie at exactly 3 m kept: hard inclusive cutoff) and
+    <= 37 at sigma_eps = 0.1 (37.44). Integer arithmetic only."""
+    nx, ny = 17, 15
+    c = synth.grid_centers(None, nx, ny, 0.5, jitter=0.0)
+    pat = O.gram_pattern(c, SIG, CUT, seps)
+    for j in range(nx * ny):
+        aj, bj = j % nx, j // nx
+        ref = [k for k in range(nx * ny)
+               if (k % nx - aj) ** 2 + (k // nx - bj) ** 2 <= bound]
+        assert pat[j].tolist() == ref
+
+
+@pytest.mark.parametrize("seps", [0.0, 0.1])
+def test_gram_pattern_is_tight(seps):
+    """Every pair of the pattern can be nonzero in calH: one point at the
+    midpoint of the two centers has both regressor entries nonzero (so the
+    pattern is exactly the set of reachable entries, not a wider one)."""
+    rng = np.random.default_rng(12)
+    c = synth.grid_centers(rng, 12, 10, 0.5)
+    pat = O.gram_pattern(c, SIG, CUT, seps)
+    for j in range(c.shape[0]):
+        for k in pat[j]:
+            mid = 0.5 * (c[j] + c[k])
+            m = O.regressor_dense(mid[None, :], c[[j, k]], SIG, CUT, seps)
+            assert (m > 0.0).all()
+
+
 def test_ridge_matches_augmented_least_squares():
     c, x, z = small()
     w, _ = O.ridge_batch(x, z, c, SIG, CUT, 0.0, LAM, RV, with_P=False)
