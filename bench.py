@@ -43,8 +43,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--frames", type=int, default=4, help="distinct frames generated")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="distinct frames generated (0 = one per warmup and timed step)")
     ap.add_argument("--eval-reps", type=int, default=500)
+    ap.add_argument("--eval-fill", type=int, default=20_000_000,
+                    help="points of the GPU-filling evaluation launch (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--patches", type=int, default=256,
                     help="patches in the batched-form leg (0 = skip; 256 = full workload)")
@@ -226,39 +229,104 @@ def rows_leg(ctx, api, synth, L, od, allxy, centers, grid, frame, w, p, reps=3):
     return out
 
 
-def cpu_baseline(od, centers_np, p, batches=3, eval_pts=2000):
+def _host_cpu():
+    """Host CPU model name and the number of cores the process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        nproc = os.cpu_count() or 1
+    return model, nproc
+
+
+def cpu_baseline(od, centers_np, p, first, pcols, frame0, batches=3, eval_pts=2000):
     """The FP64 oracle, as it stands, on a bounded sample of one frame:
     `batches` Kalman batches of the update and `eval_pts` evaluation points,
-    scaled to one frame (20k update points, 200k evaluation points)."""
+    scaled to one frame (20k update points, 200k evaluation points), with
+    all host threads and again with one thread (one batch, a quarter of the
+    points). The same leg checks the GPU state after the first frame (from
+    the prior) against the oracle: the batch ridge solution of that frame
+    (w = calH^{-1} b, P = R calH^{-1} on sampled columns) by a sparse solve,
+    and the heights it implies at 2000 of the frame's scan points."""
     import numpy as np
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    model, nproc = _host_cpu()
     B = 1024
     xy, z = od.ground(0)
     N = centers_np.shape[0]
-    w0, P0 = O.initial_state(N, p.lam, p.R)
-    m = batches * B
-    t0 = time.perf_counter()
-    O.kalman_update(w0, P0, xy[:m], z[:m], centers_np, p.sigma, p.cutoff, 0.0, p.R, batch=B)
-    t_upd = time.perf_counter() - t0
-    pts, R, t = od.scan(0, n=eval_pts)
-    t0 = time.perf_counter()
-    O.eval_pose(pts, R, t, 0.0, centers_np, w0 + 0.1, p.sigma, p.cutoff)
-    t_ev = time.perf_counter() - t0
-    per_frame = t_upd * (od.GROUND_PER_FRAME / m) + t_ev * (od.SCAN_PER_FRAME / eval_pts)
-    return {
+
+    def sample(nb, ne):
+        w0, P0 = O.initial_state(N, p.lam, p.R)
+        m = nb * B
+        t0 = time.perf_counter()
+        O.kalman_update(w0, P0, xy[:m], z[:m], centers_np, p.sigma, p.cutoff, 0.0, p.R,
+                        batch=B)
+        t_upd = time.perf_counter() - t0
+        pts, R, t = od.scan(0, n=ne)
+        t0 = time.perf_counter()
+        O.eval_pose(pts, R, t, 0.0, centers_np, w0 + 0.1, p.sigma, p.cutoff)
+        t_ev = time.perf_counter() - t0
+        per_frame = t_upd * (od.GROUND_PER_FRAME / m) + t_ev * (od.SCAN_PER_FRAME / ne)
+        return per_frame, t_upd, t_ev
+
+    per_frame, t_upd, t_ev = sample(batches, eval_pts)
+    with threadpool_limits(limits=1):
+        per_frame1, t_upd1, t_ev1 = sample(1, eval_pts // 4)
+    out = {
         "value": 1.0 / per_frame, "unit": "scan updates/s", "cores": int(cores),
         "kind": "oracle",
         "sample": (f"frame 0: {batches} of {math.ceil(od.GROUND_PER_FRAME / B)} Kalman "
-                   f"batches ({m} of {od.GROUND_PER_FRAME} points, dense P {N}x{N}) in "
-                   f"{t_upd:.1f} s and {eval_pts} of {od.SCAN_PER_FRAME} scan points "
-                   f"(f, grad, r, J) in {t_ev:.1f} s, scaled to one frame"),
+                   f"batches ({batches * B} of {od.GROUND_PER_FRAME} points, dense P "
+                   f"{N}x{N}) in {t_upd:.1f} s and {eval_pts} of {od.SCAN_PER_FRAME} scan "
+                   f"points (f, grad, r, J) in {t_ev:.1f} s, scaled to one frame; one "
+                   f"thread: 1 batch in {t_upd1:.1f} s and {eval_pts // 4} points in "
+                   f"{t_ev1:.1f} s"),
         "eval_mpts_s": eval_pts / t_ev / 1e6,
+        "value_1thread": 1.0 / per_frame1,
+        "host_cpu": model,
+        "nproc": nproc,
     }
+    # ---- the GPU's first frame against the oracle's batch ridge solution
+    xy0, z0 = xy, z
+    H, b = O.gram(xy0, z0, centers_np, p.sigma, p.cutoff, 0.0, p.lam, sparse=True)
+    E = np.zeros((N, pcols.shape[0] + 1))
+    E[pcols, np.arange(pcols.shape[0])] = 1.0
+    E[:, -1] = b
+    X = O.spd_solve(H, E)
+    Pref, wref = p.R * X[:, :-1], X[:, -1]
+    spts = frame0[2][:2000].double().cpu().numpy()
+    R0, t0_ = frame0[3]
+    qxy = O.to_world(spts, R0, t0_)[:, :2]
+    f_ref = O.eval_height_grad(qxy, centers_np, wref, p.sigma, p.cutoff)[0]
+    err = {"reference": ("first frame from the prior (20k points): oracle batch ridge "
+                         "solution by sparse LU; P on 16 sampled columns; heights at 2000 "
+                         "scan points from the oracle's evaluation of each w")}
+    for prec, st in first.items():
+        wg = st["w"].cpu().numpy()
+        Pg = st["P"].cpu().numpy()
+        e = {"w_rel": float(np.linalg.norm(wg - wref) / np.linalg.norm(wref)),
+             "P_cols_max_abs": float(np.abs(Pg - Pref).max()),
+             "P_cols_rel": float(np.linalg.norm(Pg - Pref) / np.linalg.norm(Pref)),
+             "height_max_m": float(np.abs(O.eval_height_grad(qxy, centers_np, wg, p.sigma,
+                                                             p.cutoff)[0] - f_ref).max())}
+        if "w_refined" in st:
+            wr = st["w_refined"].cpu().numpy()
+            e["w_rel_refined"] = float(np.linalg.norm(wr - wref) / np.linalg.norm(wref))
+            e["height_max_m_refined"] = float(np.abs(
+                O.eval_height_grad(qxy, centers_np, wr, p.sigma, p.cutoff)[0] - f_ref).max())
+        err[prec] = e
+    out["err"] = err
+    return out
 
 
 def main():
@@ -289,7 +357,8 @@ def main():
                                  L.SELECT_VOXEL)
     N = centers.shape[0]
     grid = ctx.grid(p, centers.contiguous())
-    nfr = max(1, min(args.frames, args.steps + args.warmup))
+    nfr = args.frames if args.frames > 0 else args.steps + args.warmup
+    nfr = max(1, min(nfr, args.steps + args.warmup))
     frames = []
     for k in range(nfr):
         xy, z = od.ground(k)
@@ -307,13 +376,24 @@ def main():
     hb = torch.zeros(N, dtype=torch.float64, device=dev)
     refine_log = {}
     n_act = []
+    # state after the first frame from the prior, for the oracle comparison
+    # of the cpu_baseline leg: w (before refinement in the mixed legs), w
+    # after refinement, and sampled columns of P
+    pcols = torch.as_tensor(np.sort(np.random.default_rng(5).choice(N, 16, replace=False)),
+                            device=dev)
+    first = {}
+    step_ms = {}
 
-    def run_sequence(gemm_prec, streams=args.streams, active=False):
+    def run_sequence(gemm_prec, streams=args.streams, active=False, joseph=False):
         """Warmup + timed frames from the prior (w = 0, P = (R/lambda) I).
         Low-precision covariance products are followed by the FP64
         refinement of w against the accumulated information form. With
-        active=True each frame is absorbed by the active-rows form."""
+        active=True each frame is absorbed by the active-rows form; with
+        joseph=True (FP32 products) the covariance update takes the Joseph
+        form."""
+        label = gemm_prec + ("_joseph" if joseph else "")
         ctx.set_update_streams(streams)
+        ctx.set_update_joseph(joseph)
         w.zero_()
         P.zero_()
         P.diagonal().fill_(p.R / p.lam)
@@ -331,12 +411,16 @@ def main():
             else:
                 ctx.update(p, grid, w, P, xs, zs, batch=args.batch, gemm_prec=gemm_prec,
                            sync=False)
+            if k == 0 and not active:
+                first[label] = {"w": w.clone(), "P": P[:, pcols].clone()}
             if gemm_prec != "f64":
                 ctx.assemble_gram(p, grid, xs, zs, rowptr, colidx, hvals, hb,
                                   add_lambda=(k == 0))
                 rel, it, _ = ctx.refine(p, rowptr, colidx, hvals, hb, P, w, rtol=1e-10,
                                         max_iter=30)
                 sweeps.append(it)
+                if k == 0 and not active:
+                    first[label]["w_refined"] = w.clone()
             return ctx.eval(p, grid, w, pts, pose=pose)
 
         for k in range(args.warmup):
@@ -345,27 +429,37 @@ def main():
         ctx.sync_status()
         ctx.profile(True)
         torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
         t0 = time.perf_counter()
         for k in range(args.steps):
+            evs[k][0].record()
             step(args.warmup + k)
+            evs[k][1].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        ctx.set_update_joseph(False)
+        ms = np.array([a.elapsed_time(b) for a, b in evs])
+        step_ms[(label, streams, active)] = {
+            "median": float(np.median(ms)), "p10": float(np.percentile(ms, 10)),
+            "p90": float(np.percentile(ms, 90))}
         ctx.sync_status()
         prof = {name: ctx.profile_read(kind) for name, kind in
                 (("syrk", L.PROF_SYRK), ("trsm", L.PROF_TRSM), ("chol", L.PROF_CHOL),
                  ("gather", L.PROF_GATHER), ("eval", L.PROF_EVAL))}
         ctx.profile(False)
-        refine_log[gemm_prec] = sweeps
+        refine_log[label] = sweeps
         return t1 - t0, prof
 
     # mixed-precision covariance products first, FP64 last (its w is kept)
     mixed = {}
     last = frames[(args.warmup + args.steps - 1) % nfr]
-    for mp in (() if args.no_mixed else ("bf16", "f32")):
-        dtm, profm = run_sequence(mp)
+    for mp in (() if args.no_mixed else ("bf16", "f32", "f32_joseph")):
+        dtm, profm = run_sequence(mp.split("_")[0], joseph=mp.endswith("joseph"))
         log(f"{mp} covariance-product leg: {dtm / args.steps * 1e3:.1f} ms/step")
         fm = ctx.eval(p, grid, w, last[2], pose=last[3])["f"].clone()
         mixed[mp] = {"value": args.steps / dtm, "ms_per_step": dtm / args.steps * 1e3,
+                     "step_ms": step_ms[(mp, args.streams, False)],
                      "syrk_ms_per_step": profm["syrk"][0] / args.steps,
                      "refine_sweeps_per_step": refine_log[mp][args.warmup:], "_f": fm}
     other = 3 - args.streams
@@ -384,6 +478,7 @@ def main():
         fa = ctx.eval(p, grid, w, last[2], pose=last[3])["f"].clone()
         wa = w.clone()
         active_rows = {"value": args.steps / dt_a, "ms_per_step": dt_a / args.steps * 1e3,
+                       "step_ms": step_ms[("f64", args.streams, True)],
                        "active_centers_per_step": n_act[args.warmup:],
                        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_a.items()}}
     dt, prof = run_sequence("f64")
@@ -405,44 +500,66 @@ def main():
     syrk_flops = N * (N + 1) * pts_per_frame * args.steps
     syrk_tfs = syrk_flops / (syrk_ms * 1e-3) / 1e12 if syrk_ms > 0 else 0.0
 
-    # ---- rbf_eval throughput: 500 launches of 200k points (1e8) per timed region
+    # ---- rbf_eval throughput: 500 launches of 200k points (1e8) per timed
+    # region, each launch timed by its own event pair; then launches of 20M
+    # points (the frame's scan points repeated), which fill the GPU
     ev = {}
     xy0, z0, pts0, pose0 = frames[0]
+    big = pts0.repeat(args.eval_fill // pts0.shape[0], 1) if args.eval_fill else None
+
+    def launches(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(reps)]
+        ta = time.perf_counter()
+        for a, b in pairs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - ta) / reps
+        us = np.array([a.elapsed_time(b) for a, b in pairs]) * 1e3
+        return wall, {"median": float(np.median(us)), "p10": float(np.percentile(us, 10)),
+                      "p90": float(np.percentile(us, 90))}
+
     for name, dt_ in (("f64", torch.float64), ("f32", torch.float32)):
         pts = pts0.to(dt_).contiguous()
-        for _ in range(3):
-            ctx.eval(p, grid, w, pts, pose=pose0)
-        torch.cuda.synchronize()
+        q = pts.shape[0]
         ctx.profile(True)
-        ta = time.perf_counter()
-        for _ in range(args.eval_reps):
-            ctx.eval(p, grid, w, pts, pose=pose0)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
+        wall, call_us = launches(lambda: ctx.eval(p, grid, w, pts, pose=pose0), args.eval_reps)
         ems, en = ctx.profile_read(L.PROF_EVAL)
         ctx.profile(False)
-        # fused Gauss-Newton terms on the same points (J not written)
-        for _ in range(3):
-            ctx.eval_gn(p, grid, w, pts, pose=pose0)
-        torch.cuda.synchronize()
-        tg0 = time.perf_counter()
-        for _ in range(args.eval_reps):
-            ctx.eval_gn(p, grid, w, pts, pose=pose0)
-        torch.cuda.synchronize()
-        gn_s = (time.perf_counter() - tg0) / args.eval_reps
-        q = pts.shape[0]
+        gn_wall, gn_us = launches(lambda: ctx.eval_gn(p, grid, w, pts, pose=pose0),
+                                  args.eval_reps)
         esz = pts.element_size()
         bytes_pt = 3 * esz + 10 * esz  # read xyz, write f, grad(2), r, J(6)
         kern_s = ems * 1e-3 / en
         ev[name] = {
-            "mpts_s_wall": q * args.eval_reps / (tb - ta) / 1e6,
+            "mpts_s_wall": q / wall / 1e6,
             "mpts_s_kernel": q / kern_s / 1e6,
             "kernel_us": kern_s * 1e6,
+            "call_us": call_us,
             "points": q,
             "hbm_gbs": q * bytes_pt / kern_s / 1e9,
             "hbm_frac": q * bytes_pt / kern_s / 1e9 / PEAK_HBM_GBS,
-            "gauss_newton_mpts_s_wall": q / gn_s / 1e6,
+            "gauss_newton_mpts_s_wall": q / gn_wall / 1e6,
+            "gauss_newton_call_us": gn_us,
         }
+        if big is not None:
+            bp = big.to(dt_).contiguous()
+            ctx.profile(True)
+            bwall, bus = launches(lambda: ctx.eval(p, grid, w, bp, pose=pose0), 5)
+            bms, bn = ctx.profile_read(L.PROF_EVAL)
+            ctx.profile(False)
+            bk = bms * 1e-3 / bn
+            ev[name]["fill"] = {"points": int(bp.shape[0]), "kernel_us": bk * 1e6,
+                                "mpts_s_kernel": bp.shape[0] / bk / 1e6,
+                                "mpts_s_wall": bp.shape[0] / bwall / 1e6,
+                                "hbm_frac": bp.shape[0] * bytes_pt / bk / 1e9 / PEAK_HBM_GBS}
+            del bp
+    del big
 
     if not args.no_rows:
         out_rows = rows_leg(ctx, api, synth, L, od, torch.from_numpy(allxy).to(dev), centers,
@@ -458,6 +575,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3,
+        "step_ms": step_ms[("f64", args.streams, False)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -500,6 +618,7 @@ def main():
         "rows": out_rows,
     }
     log("eval leg done")
+    frame0_keep = frames[0]
     if args.patches > 0:
         del P, frames
         torch.cuda.empty_cache()
@@ -507,7 +626,12 @@ def main():
         out["batched"] = batched_leg(ctx, api, synth, args.patches, not args.no_tune)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(od, centers.cpu().numpy(), p)
+        cb = cpu_baseline(od, centers.cpu().numpy(), p, first, pcols.cpu().numpy(),
+                          frame0_keep)
+        out["err"] = cb.pop("err")
+        out["cpu_baseline"] = cb
+    else:
+        out["err"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -92,14 +92,21 @@ rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream);
  * regressor rows, gather, Cholesky and triangular solve run on a second
  * stream of the library's. Results are bitwise the same. (On one MI355X
  * the two streams contend for CUs and the two-stream schedule measured
- * slower.) Under stream capture rbf_update always uses one stream. */
+ * slower.) The two-stream schedule cannot be captured into a graph:
+ * rbf_update and rbf_update_active on a capturing stream return
+ * RBF_E_INVALID_ARG, before any launch, while streams = 2. */
 rbf_status rbf_ctx_set_update_streams(rbf_ctx* ctx, int32_t streams);
-/* Evaluation mode of rbf_eval on this context: on = 0 (the default) reads
- * each point's candidates from the bin-sorted center table; on != 0 groups
- * query sets of 2048 points or more by bin (counting sort) and stages each
- * bin's candidate centers in LDS for its points. Results agree to rounding
- * (the candidates are summed in another order). */
-rbf_status rbf_ctx_set_eval_binned(rbf_ctx* ctx, int32_t on);
+/* Form of the covariance update of rbf_update on this context (mixed form
+ * with FP32 products only). on = 0 (the default): P -= V V^T. on != 0: the
+ * Joseph form P <- (I - K H) P (I - K H)^T + K R K^T of the Kalman update
+ * (eq. H_inverse_update written for the covariance), expanded as
+ * P - K U^T - U K^T + K S K^T with the gain K = U S^{-1} formed in FP64 and
+ * the three products on FP32 MFMA accumulated into the FP64 P (lower tiles,
+ * mirrored, so P stays exactly symmetric). Equal to the default in exact
+ * arithmetic; with rounded products its terms are larger than V V^T and
+ * cancel. rbf_update with the Joseph form on returns RBF_E_INVALID_ARG unless
+ * gemm_prec is RBF_F32 and the context uses one stream. */
+rbf_status rbf_ctx_set_update_joseph(rbf_ctx* ctx, int32_t on);
 /* Synchronise the stream, return the first device-side error recorded
  * since the last call (RBF_OK if none) and clear it. */
 rbf_status rbf_sync_status(rbf_ctx* ctx);
@@ -167,13 +174,22 @@ rbf_status rbf_state_grow(rbf_ctx* ctx, const rbf_params* params, double* w,
 
 /* Build the neighbour-binned center table used by every kernel below:
  * square bins of side slightly above cutoff*max(sigma, sigma_t), so all
- * centers within the kernel support of a point lie in its 3x3 bins. The
- * centers (N x 2 f64, device) are copied; the caller may free them after
- * the call. The grid owns its device memory until rbf_grid_destroy.
- * The call synchronises (it reads the centers' bounding box). */
+ * centers within the kernel support of a point lie in its 3x3 bins, and,
+ * for the evaluation kernels, a second sorted copy over bins of side
+ * 1.01*cutoff*sigma/3 (at most 16384 of them per axis; more returns
+ * RBF_E_INVALID_ARG). The centers (N x 2 f64, device) are copied; the
+ * caller may free them after the call. The grid owns its device memory
+ * until rbf_grid_destroy. The call synchronises (it reads the centers'
+ * bounding box). */
 rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* params,
                            const double* centers, int64_t N, rbf_grid** out);
 rbf_status rbf_grid_destroy(rbf_grid* grid);
+/* The same call with the argument order of the center-binning step of the
+ * evaluation path (centers, N, then the parameters): bins the centers the
+ * kernel matrix and its evaluation are built on (eq. rbf_kernel, compact
+ * support; subsection "The RBF Approximation Model"). */
+rbf_status rbf_bin_centers(rbf_ctx* ctx, const double* centers, int64_t N,
+                           const rbf_params* params, rbf_grid** out);
 /* Host outputs: number of centers, bins in x and y, and the largest number
  * of centers that can lie within one point's 3x3 bins (an upper bound on
  * the nonzeros of one regressor row). Any pointer may be NULL. */
@@ -223,6 +239,33 @@ rbf_status rbf_assemble_gram(rbf_ctx* ctx, const rbf_params* params,
                              const int64_t* rowptr, const int32_t* colidx,
                              double* vals, double* b, int32_t add_lambda);
 
+/* Sparse symmetric matrix in CSR form (device arrays; both triangles). */
+typedef struct {
+  int64_t n;        /* rows (and columns)                                  */
+  int64_t nnz;      /* stored entries                                      */
+  int64_t* rowptr;  /* n + 1 offsets                                       */
+  int32_t* colidx;  /* nnz column indices, ascending within a row          */
+  double* vals;     /* nnz values                                          */
+} rbf_csr;
+
+enum { RBF_ASSEMBLE_PHI = 1, RBF_ASSEMBLE_GRAM = 2 };
+
+/* Kernel-matrix assembly in one call (eq. rbf_kernel; ridge estimator eq.
+ * RBF_estimator with calH = lambda I + sum m m^T, b = sum m z). `what` is
+ * RBF_ASSEMBLE_PHI, RBF_ASSEMBLE_GRAM or both or-ed:
+ *   PHI   the regressor rows of the M points, as rbf_assemble_phi (prec
+ *         RBF_F64 or RBF_F32; phi_val, phi_col, phi_nnz, kmax as there);
+ *   GRAM  accumulate the information matrix into H (the pattern of
+ *         rbf_gram_pattern in H->rowptr / H->colidx, H->n == N, values
+ *         added to H->vals) and b (N) as rbf_assemble_gram (z required,
+ *         prec must be RBF_F64; add_lambda adds the ridge term once).
+ * Arguments a part does not use may be NULL / 0. Errors as in the two
+ * calls it makes (the PHI part runs first). */
+rbf_status rbf_assemble(rbf_ctx* ctx, const rbf_params* params, const rbf_grid* grid,
+                        const double* xy, const double* z, int64_t M, int32_t what,
+                        rbf_prec prec, void* phi_val, int32_t* phi_col, int32_t* phi_nnz,
+                        int32_t kmax, rbf_csr* H, double* b, int32_t add_lambda);
+
 /* ------------------------------------------------------ recursive update */
 
 /* Absorb M points into (w, P) by the Kalman-style recursion of eqs.
@@ -240,7 +283,10 @@ rbf_status rbf_assemble_gram(rbf_ctx* ctx, const rbf_params* params,
  * RBF_E_NONFINITE) no later batch runs, and (w, P) is the state after the
  * batches before it. n_done (host, may be NULL): if non-NULL the call
  * synchronises and stores the number of points absorbed; if NULL the call
- * is asynchronous and errors are read with rbf_sync_status. */
+ * is asynchronous and errors are read with rbf_sync_status. A device error
+ * still pending from an earlier asynchronous call (not yet read by
+ * rbf_sync_status) makes every batch skip: (w, P) is unchanged, and with
+ * n_done the call returns that error with *n_done = 0. */
 rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* params,
                       const rbf_grid* grid, double* w, double* P, int64_t ldp,
                       const double* xy, const double* z, int64_t M,
@@ -337,12 +383,43 @@ rbf_status rbf_refine(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
  *             (eqs. manifold_derivative, manifold_grad_2 with the body
  *             point in the skew matrix).
  * prec RBF_F64: pts and outputs are double; RBF_F32: float (w stays f64
- * and is rounded per load). Any output pointer except f may be NULL. */
+ * and is rounded once per call). Any output pointer except f may be NULL.
+ * xy points (dim 2), grad and jac are read and written two elements at a
+ * time and must be aligned to two elements (16 bytes in FP64, 8 in FP32);
+ * a misaligned pointer returns RBF_E_INVALID_ARG. Candidate centers come
+ * from the grid's evaluation bins (side about cutoff*sigma/3): each bin row
+ * within the support radius is read only over the bins that meet the
+ * support circle. */
 rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* params,
                     const rbf_grid* grid, const double* w, const void* pts,
                     int64_t Q, int32_t dim, const double* pose, double z_off,
                     rbf_prec prec, void* f, void* grad, void* resid,
                     void* jac);
+
+/* Evaluation at a pose increment, for differentiation with respect to the
+ * pose (form 3): as rbf_eval in the pose form (dim 3), at
+ *   R = R0 Exp(delta[0:3]),  t = t0 + delta[3:6],
+ * around a linearisation pose pose0 (host, 12 doubles: R0 row-major then
+ * t0), with the increment delta (DEVICE, 6 f64) read on the device, so that
+ * it never travels to the host. Exp is the exponential map of SO(3)
+ * (Rodrigues' formula), formed by a one-thread kernel in FP64. */
+rbf_status rbf_eval_at(rbf_ctx* ctx, const rbf_params* params, const rbf_grid* grid,
+                       const double* w, const void* pts, int64_t Q, const double* pose0,
+                       const double* delta, double z_off, rbf_prec prec, void* f,
+                       void* grad, void* resid, void* jac);
+
+/* Adjoint of rbf_eval_at: as rbf_eval_adjoint in the pose form, with the
+ * pose gradient taken with respect to the increment: d_delta (device, 6
+ * f64, may be NULL) is ACCUMULATED with
+ *   d_delta[0:3] += J_r(delta[0:3])^T dL/dtheta,  d_delta[3:6] += dL/dt,
+ * where dL/dtheta is the gradient for the right perturbation
+ * R <- R Exp(theta) at the evaluated pose and J_r is the right Jacobian of
+ * SO(3) (Exp(v + e) = Exp(v) Exp(J_r(v) e) to first order). */
+rbf_status rbf_eval_adjoint_at(rbf_ctx* ctx, const rbf_params* params, const rbf_grid* grid,
+                               const double* w, const void* pts, int64_t Q,
+                               const double* pose0, const double* delta, rbf_prec prec,
+                               const void* gbar_f, const void* gbar_r, void* d_pts,
+                               double* d_w, double* d_delta);
 
 /* Gauss-Newton terms of the manifold residual, fused into the evaluation:
  * the Levenberg-Marquardt minimisation of eq. cost_fn (subsection "The

@@ -39,13 +39,20 @@ class Patch(C.Structure):
                 ("M", i64), ("pts", vp), ("Q", i64), ("pose", dbl * 12), ("f", vp),
                 ("grad", vp), ("resid", vp), ("jac", vp), ("batch", i64)]
 
+class CSR(C.Structure):
+    """rbf_csr (include/rbf.h)."""
+    _fields_ = [("n", i64), ("nnz", i64), ("rowptr", vp), ("colidx", vp), ("vals", vp)]
+
+
+ASSEMBLE_PHI, ASSEMBLE_GRAM = 1, 2
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "rbf_ctx_create": (C.c_int, [C.POINTER(vp), C.c_int, vp]),
     "rbf_ctx_destroy": (C.c_int, [vp]),
     "rbf_ctx_set_stream": (C.c_int, [vp, vp]),
     "rbf_ctx_set_update_streams": (C.c_int, [vp, i32]),
-    "rbf_ctx_set_eval_binned": (C.c_int, [vp, i32]),
+    "rbf_ctx_set_update_joseph": (C.c_int, [vp, i32]),
     "rbf_sync_status": (C.c_int, [vp]),
     "rbf_last_error_index": (i64, [vp]),
     "rbf_last_error": (C.c_char_p, [vp]),
@@ -57,12 +64,15 @@ SIGNATURES = {
     "rbf_state_grow": (C.c_int, [vp, pp, vp, vp, i64, i64, i64]),
     "rbf_grid_create": (C.c_int, [vp, pp, vp, i64, C.POINTER(vp)]),
     "rbf_grid_destroy": (C.c_int, [vp]),
+    "rbf_bin_centers": (C.c_int, [vp, vp, i64, pp, C.POINTER(vp)]),
     "rbf_grid_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32),
                                 C.POINTER(i32), C.POINTER(i32)]),
     "rbf_sort_points": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
     "rbf_assemble_phi": (C.c_int, [vp, pp, vp, vp, i64, C.c_int, vp, vp, vp, i32]),
     "rbf_gram_pattern": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(i64)]),
     "rbf_assemble_gram": (C.c_int, [vp, pp, vp, vp, vp, i64, vp, vp, vp, vp, i32]),
+    "rbf_assemble": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.c_int, vp, vp, vp, i32,
+                               C.POINTER(CSR), vp, i32]),
     "rbf_update": (C.c_int, [vp, pp, vp, vp, vp, i64, vp, vp, i64, i64, C.c_int,
                              C.POINTER(i64)]),
     "rbf_update_active": (C.c_int, [vp, pp, vp, vp, vp, i64, vp, vp, i64, i64, C.c_int,
@@ -73,6 +83,10 @@ SIGNATURES = {
                              C.POINTER(dbl), C.POINTER(i32)]),
     "rbf_eval": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl), dbl,
                            C.c_int, vp, vp, vp, vp]),
+    "rbf_eval_at": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(dbl), vp, dbl, C.c_int, vp,
+                              vp, vp, vp]),
+    "rbf_eval_adjoint_at": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(dbl), vp, C.c_int,
+                                      vp, vp, vp, vp, vp]),
     "rbf_eval_gn": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(dbl), dbl, C.c_int, vp, vp,
                               vp]),
     "rbf_eval_adjoint": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl),

@@ -61,6 +61,51 @@ def _ptr(t: torch.Tensor | None, dtype=None, name="tensor", dev=None) -> int | N
     return t.data_ptr()
 
 
+def _need(t, shape, name):
+    """Raise unless t is a tensor of this shape (None: any extent). Checked
+    before any pointer is taken, so a mismatch never reaches the library,
+    which cannot see the extents of the buffers it is given."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dim() != len(shape) or any(e is not None and t.shape[i] != e
+                                    for i, e in enumerate(shape)):
+        want = "x".join("*" if e is None else str(e) for e in shape)
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {want}")
+
+
+def _numel(t, n, name, at_least=False):
+    """Raise unless t holds n elements (at least n with at_least)."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if (t.numel() < n) if at_least else (t.numel() != n):
+        raise ValueError(f"{name}: {t.numel()} elements, expected "
+                         f"{'at least ' if at_least else ''}{n}")
+
+
+def _matrix(P, n, name, dev):
+    """Row-major float64 device matrix of at least n x n; its pointer."""
+    if not isinstance(P, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] < n or P.shape[1] < n:
+        raise ValueError(f"{name}: must be a row-major matrix of at least {n} x {n}, "
+                         f"got shape {tuple(P.shape)} strides {P.stride()}")
+    return _ptr_any_stride(P, torch.float64, name, dev)
+
+
+def _ptr_any_stride(t, dtype, name, dev):
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+    if t.device.index != dev:
+        raise ValueError(f"{name}: on device {t.device}, context is on cuda:{dev}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    return t.data_ptr()
+
+
 class Context:
     """rbf_ctx bound to one device and (by default) torch's current stream."""
 
@@ -123,6 +168,7 @@ class Context:
 
     def select_centers(self, xy: torch.Tensor, roi, res: float, r_kd: float,
                        thr: int, mode: int = L.SELECT_RADIUS, cap: int | None = None):
+        _need(xy, (None, 2), "xy")
         M = xy.shape[0]
         x0, y0, x1, y1 = [float(v) for v in roi]
         import math
@@ -143,6 +189,7 @@ class Context:
                             cap: int | None = None):
         """Selection on running counts (int32, nx * ny, updated in place);
         returns the nodes that became centers with this call's points."""
+        _need(xy, (None, 2), "xy")
         M = xy.shape[0]
         x0, y0, x1, y1 = [float(v) for v in roi]
         import math
@@ -164,33 +211,37 @@ class Context:
                    n_new: int):
         """New centers n_old..n_new-1 join (w, P) with the prior, in place;
         w and P are the capacity-sized buffers (P row-major, stride(1) == 1)."""
-        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] < n_new or P.shape[1] < n_new:
-            raise ValueError("P must be a row-major tensor of at least n_new x n_new")
-        if w.numel() < n_new:
-            raise ValueError("w must hold n_new entries")
+        _numel(w, n_new, "w", at_least=True)
+        Pp = _matrix(P, n_new, "P", self.device)
         pc = params.c()
         self._check(self.lib.rbf_state_grow(
-            self.h, C.byref(pc), _ptr(w, torch.float64, "w", self.device),
-            P.data_ptr() if P.dtype == torch.float64 and P.is_cuda else None, P.stride(0),
+            self.h, C.byref(pc), _ptr(w, torch.float64, "w", self.device), Pp, P.stride(0),
             n_old, n_new), "rbf_state_grow")
 
     def grid(self, params: Params, centers: torch.Tensor) -> "Grid":
         return Grid(self, params, centers)
 
+    def bin_centers(self, params: Params, centers: torch.Tensor) -> "Grid":
+        """The same grid through rbf_bin_centers."""
+        return Grid(self, params, centers, entry="rbf_bin_centers")
+
     def sort_points(self, grid: "Grid", xy: torch.Tensor, z: torch.Tensor | None = None):
+        _need(xy, (None, 2), "xy")
         M = xy.shape[0]
+        _numel(z, M, "z")
         xy_o = torch.empty_like(xy)
         z_o = torch.empty_like(z) if z is not None else None
         perm = torch.empty(M, dtype=torch.int32, device=xy.device)
         self._check(self.lib.rbf_sort_points(
             self.h, grid.h, _ptr(xy, torch.float64, "xy", self.device),
-            _ptr(z, torch.float64, "z"), M, _ptr(xy_o), _ptr(z_o), _ptr(perm)),
+            _ptr(z, torch.float64, "z", self.device), M, _ptr(xy_o), _ptr(z_o), _ptr(perm)),
             "rbf_sort_points")
         return xy_o, z_o, perm
 
     def assemble_phi(self, params: Params, grid: "Grid", xy: torch.Tensor,
                      kmax: int | None = None, prec="f64"):
         prec = _prec(prec)
+        _need(xy, (None, 2), "xy")
         M = xy.shape[0]
         kmax = kmax if kmax is not None else grid.max_candidates
         vals = torch.empty((M, kmax), dtype=_DT[prec], device=xy.device)
@@ -223,6 +274,11 @@ class Context:
                       z: torch.Tensor, rowptr: torch.Tensor, colidx: torch.Tensor,
                       vals: torch.Tensor | None = None, b: torch.Tensor | None = None,
                       add_lambda: bool = True):
+        _need(xy, (None, 2), "xy")
+        _numel(z, xy.shape[0], "z")
+        _numel(rowptr, grid.N + 1, "rowptr")
+        _numel(vals, colidx.numel(), "vals")
+        _numel(b, grid.N, "b")
         dev = xy.device
         if vals is None:
             vals = torch.zeros(colidx.shape[0], dtype=torch.float64, device=dev)
@@ -231,23 +287,72 @@ class Context:
         pc = params.c()
         self._check(self.lib.rbf_assemble_gram(
             self.h, C.byref(pc), grid.h, _ptr(xy, torch.float64, "xy", self.device),
-            _ptr(z, torch.float64, "z"), xy.shape[0], _ptr(rowptr, torch.int64, "rowptr"),
-            _ptr(colidx, torch.int32, "colidx"), _ptr(vals, torch.float64, "vals"),
-            _ptr(b, torch.float64, "b"), int(add_lambda)), "rbf_assemble_gram")
+            _ptr(z, torch.float64, "z", self.device), xy.shape[0],
+            _ptr(rowptr, torch.int64, "rowptr", self.device),
+            _ptr(colidx, torch.int32, "colidx", self.device),
+            _ptr(vals, torch.float64, "vals", self.device),
+            _ptr(b, torch.float64, "b", self.device), int(add_lambda)), "rbf_assemble_gram")
         return vals, b
+
+    def assemble(self, params: Params, grid: "Grid", xy: torch.Tensor, z=None,
+                 what=("phi", "gram"), prec="f64", kmax: int | None = None, H=None, b=None,
+                 add_lambda: bool = True):
+        """rbf_assemble: regressor rows (phi) and/or the information matrix
+        (gram) of the points in one call. H = (rowptr, colidx, vals) with the
+        pattern of gram_pattern; vals and b are accumulated (created as zeros
+        if None). Returns {"phi": (vals, cols, nnz), "gram": (vals, b)}."""
+        _need(xy, (None, 2), "xy")
+        M = xy.shape[0]
+        prec = _prec(prec)
+        bits = (L.ASSEMBLE_PHI if "phi" in what else 0) | (L.ASSEMBLE_GRAM if "gram" in what
+                                                            else 0)
+        out = {}
+        pv = pc_ = pn = None
+        kmax = kmax if kmax is not None else grid.max_candidates
+        if bits & L.ASSEMBLE_PHI:
+            pv = torch.empty((M, kmax), dtype=_DT[prec], device=xy.device)
+            pc_ = torch.empty((M, kmax), dtype=torch.int32, device=xy.device)
+            pn = torch.empty(M, dtype=torch.int32, device=xy.device)
+            out["phi"] = (pv, pc_, pn)
+        csr = None
+        if bits & L.ASSEMBLE_GRAM:
+            _numel(z, M, "z")
+            rowptr, colidx, vals = H
+            _numel(rowptr, grid.N + 1, "rowptr")
+            if vals is None:
+                vals = torch.zeros(colidx.shape[0], dtype=torch.float64, device=xy.device)
+            _numel(vals, colidx.numel(), "vals")
+            if b is None:
+                b = torch.zeros(grid.N, dtype=torch.float64, device=xy.device)
+            _numel(b, grid.N, "b")
+            csr = L.CSR(grid.N, colidx.numel(), _ptr(rowptr, torch.int64, "rowptr", self.device),
+                        _ptr(colidx, torch.int32, "colidx", self.device),
+                        _ptr(vals, torch.float64, "vals", self.device))
+            out["gram"] = (vals, b)
+        pcv = params.c()
+        self._check(self.lib.rbf_assemble(
+            self.h, C.byref(pcv), grid.h, _ptr(xy, torch.float64, "xy", self.device),
+            _ptr(z, torch.float64, "z", self.device), M, bits, prec, _ptr(pv), _ptr(pc_),
+            _ptr(pn), kmax, C.byref(csr) if csr is not None else None,
+            _ptr(b, torch.float64, "b", self.device) if csr is not None else None,
+            int(add_lambda)), "rbf_assemble")
+        return out
 
     def update(self, params: Params, grid: "Grid", w: torch.Tensor, P: torch.Tensor,
                xy: torch.Tensor, z: torch.Tensor, batch: int = 0, gemm_prec="f64",
                sync: bool = True) -> int | None:
+        _need(xy, (None, 2), "xy")
+        _numel(z, xy.shape[0], "z")
+        _numel(w, grid.N, "w")
+        _need(P, (grid.N, grid.N), "P")
+        Pp = _matrix(P, grid.N, "P", self.device)
         ldp = P.stride(0)
-        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] != grid.N or P.shape[1] != grid.N:
-            raise ValueError("P must be an N x N row-major tensor")
         pc = params.c()
         nd = C.c_int64()
         st = self.lib.rbf_update(
-            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
-            P.data_ptr() if P.dtype == torch.float64 and P.is_cuda else None, ldp,
-            _ptr(xy, torch.float64, "xy"), _ptr(z, torch.float64, "z"), xy.shape[0],
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device), Pp, ldp,
+            _ptr(xy, torch.float64, "xy", self.device), _ptr(z, torch.float64, "z", self.device),
+            xy.shape[0],
             batch, _prec(gemm_prec), C.byref(nd) if sync else None)
         self._check(st, "rbf_update")
         return nd.value if sync else None
@@ -257,36 +362,43 @@ class Context:
                       active: torch.Tensor | None = None):
         """Active-rows update of one scan; returns (points absorbed, |A|).
         `active` (int32, N entries, optional) receives the active centers."""
+        _need(xy, (None, 2), "xy")
+        _numel(z, xy.shape[0], "z")
+        _numel(w, grid.N, "w")
+        _need(P, (grid.N, grid.N), "P")
+        _numel(active, grid.N, "active", at_least=True)
+        Pp = _matrix(P, grid.N, "P", self.device)
         ldp = P.stride(0)
-        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] != grid.N or P.shape[1] != grid.N:
-            raise ValueError("P must be an N x N row-major tensor")
-        if active is not None and (active.dtype != torch.int32 or active.numel() < grid.N):
-            raise ValueError("active must be an int32 tensor of N entries")
         pc = params.c()
         nd = C.c_int64()
         na = C.c_int64()
         st = self.lib.rbf_update_active(
-            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
-            P.data_ptr() if P.dtype == torch.float64 and P.is_cuda else None, ldp,
-            _ptr(xy, torch.float64, "xy"), _ptr(z, torch.float64, "z"), xy.shape[0],
-            batch, _prec(gemm_prec), _ptr(active, torch.int32, "active") if active is not None
-            else None, C.byref(na), C.byref(nd))
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device), Pp, ldp,
+            _ptr(xy, torch.float64, "xy", self.device), _ptr(z, torch.float64, "z", self.device),
+            xy.shape[0], batch, _prec(gemm_prec),
+            _ptr(active, torch.int32, "active", self.device), C.byref(na), C.byref(nd))
         self._check(st, "rbf_update_active")
         return nd.value, na.value
 
     def solve(self, rowptr, colidx, vals, B: torch.Tensor, rtol: float = 1e-10,
               max_iter: int = 50, inner="f64", X: torch.Tensor | None = None):
+        _need(rowptr, (None,), "rowptr")
         N = rowptr.shape[0] - 1
+        _numel(vals, colidx.numel(), "vals")
         Bm = B if B.dim() == 2 else B.view(-1, 1)
+        _need(Bm, (N, None), "B")
         nrhs = Bm.shape[1]
         if X is None:
             X = torch.empty_like(Bm)
+        _need(X, (N, nrhs), "X")
         rel = (C.c_double * max(nrhs, 1))()
         it = C.c_int32()
         st = self.lib.rbf_solve(
             self.h, N, _ptr(rowptr, torch.int64, "rowptr", self.device),
-            _ptr(colidx, torch.int32, "colidx"), _ptr(vals, torch.float64, "vals"),
-            _ptr(Bm, torch.float64, "B"), Bm.stride(0), _ptr(X, torch.float64, "X"),
+            _ptr(colidx, torch.int32, "colidx", self.device),
+            _ptr(vals, torch.float64, "vals", self.device),
+            _ptr(Bm, torch.float64, "B", self.device), Bm.stride(0),
+            _ptr(X, torch.float64, "X", self.device),
             X.stride(0), nrhs, rtol, max_iter, _prec(inner), rel, C.byref(it))
         relres = [rel[k] for k in range(nrhs)]
         if st not in (L.RBF_OK, 5):
@@ -294,40 +406,49 @@ class Context:
         out = X if B.dim() == 2 else X.view(-1)
         return out, relres, it.value, st
 
+    def set_update_joseph(self, on: bool):
+        """update() with FP32 products: Joseph form of the covariance update
+        (off by default)."""
+        self._check(self.lib.rbf_ctx_set_update_joseph(self.h, int(bool(on))),
+                    "rbf_ctx_set_update_joseph")
+
     def set_update_streams(self, streams: int):
         """Schedule of update(): 1 (default) uses one stream, 2 overlaps the
         next batch's chain with the covariance product on a second stream."""
         self._check(self.lib.rbf_ctx_set_update_streams(self.h, streams),
                     "rbf_ctx_set_update_streams")
 
-    def set_eval_binned(self, on: bool):
-        """eval(): group large query sets by bin and stage candidates in LDS
-        (off by default; slower on points in arbitrary order)."""
-        self._check(self.lib.rbf_ctx_set_eval_binned(self.h, int(bool(on))),
-                    "rbf_ctx_set_eval_binned")
-
     def refine(self, params: Params, rowptr, colidx, vals, b, P: torch.Tensor,
                w: torch.Tensor, rtol: float = 1e-12, max_iter: int = 20, check=True):
         """FP64 refinement of w against calH = (rowptr, colidx, vals), b with
         the recursion's P as preconditioner. Returns (relres, sweeps, status);
         raises unless check is False."""
+        _need(rowptr, (None,), "rowptr")
         N = rowptr.shape[0] - 1
-        if P.dim() != 2 or P.stride(1) != 1 or P.shape[0] != N or P.shape[1] != N:
-            raise ValueError("P must be an N x N row-major tensor")
+        _numel(vals, colidx.numel(), "vals")
+        _numel(b, N, "b")
+        _numel(w, N, "w")
+        _need(P, (N, N), "P")
+        Pp = _matrix(P, N, "P", self.device)
         rel = C.c_double()
         it = C.c_int32()
         st = self.lib.rbf_refine(
             self.h, N, _ptr(rowptr, torch.int64, "rowptr", self.device),
-            _ptr(colidx, torch.int32, "colidx"), _ptr(vals, torch.float64, "vals"),
-            _ptr(b, torch.float64, "b"), _ptr(P, torch.float64, "P"), P.stride(0),
-            params.R, _ptr(w, torch.float64, "w"), rtol, max_iter, C.byref(rel), C.byref(it))
+            _ptr(colidx, torch.int32, "colidx", self.device),
+            _ptr(vals, torch.float64, "vals", self.device),
+            _ptr(b, torch.float64, "b", self.device), Pp, P.stride(0),
+            params.R, _ptr(w, torch.float64, "w", self.device), rtol, max_iter, C.byref(rel),
+            C.byref(it))
         if check:
             self._check(st, "rbf_refine")
         return rel.value, it.value, st
 
     def eval(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
              pose=None, z_off: float = 0.0, grad=True, resid=True, jac=True):
+        """f, grad f and (pose form) residual and Jacobian at the points."""
+        _need(pts, (None, None), "pts")
         Q, dim = pts.shape
+        _check_eval(grid, w, pts, pose)
         prec = _PREC[pts.dtype]
         dt = pts.dtype
         dev = pts.device
@@ -339,17 +460,65 @@ class Context:
         pc = params.c()
         self._check(self.lib.rbf_eval(
             self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
-            _ptr(pts, None, "pts"), Q, dim, pose_c, z_off, prec, _ptr(f), _ptr(g),
+            _ptr(pts, None, "pts", self.device), Q, dim, pose_c, z_off, prec, _ptr(f), _ptr(g),
             _ptr(r), _ptr(J)), "rbf_eval")
         return {"f": f, "grad": g, "resid": r, "jac": J}
+
+    def eval_at(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
+                pose0, delta: torch.Tensor, z_off: float = 0.0, grad=True, resid=True,
+                jac=True):
+        """Pose form at R0 Exp(delta[:3]), t0 + delta[3:] with the increment
+        delta (6 float64, on the device) read by the library on the device."""
+        _need(pts, (None, 3), "pts")
+        Q = pts.shape[0]
+        _check_eval(grid, w, pts, pose0)
+        _numel(delta, 6, "delta")
+        dt = pts.dtype
+        dev = pts.device
+        f = torch.empty(Q, dtype=dt, device=dev)
+        g = torch.empty((Q, 2), dtype=dt, device=dev) if grad else None
+        r = torch.empty(Q, dtype=dt, device=dev) if resid else None
+        J = torch.empty((Q, 6), dtype=dt, device=dev) if jac else None
+        pc = params.c()
+        self._check(self.lib.rbf_eval_at(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            _ptr(pts, None, "pts", self.device), Q, _pose(pose0),
+            _ptr(delta, torch.float64, "delta", self.device), z_off, _PREC[dt], _ptr(f),
+            _ptr(g), _ptr(r), _ptr(J)), "rbf_eval_at")
+        return {"f": f, "grad": g, "resid": r, "jac": J}
+
+    def eval_adjoint_at(self, params: Params, grid: "Grid", w: torch.Tensor,
+                        pts: torch.Tensor, pose0, delta: torch.Tensor, gbar_f=None,
+                        gbar_r=None, d_pts=True, d_w: torch.Tensor | None = None,
+                        d_delta: torch.Tensor | None = None):
+        """Adjoint of eval_at; d_w and d_delta (6) are accumulated."""
+        _need(pts, (None, 3), "pts")
+        Q = pts.shape[0]
+        _check_eval(grid, w, pts, pose0)
+        _numel(delta, 6, "delta")
+        _numel(gbar_f, Q, "gbar_f")
+        _numel(gbar_r, Q, "gbar_r")
+        _numel(d_w, grid.N, "d_w")
+        _numel(d_delta, 6, "d_delta")
+        dp = torch.empty_like(pts) if d_pts else None
+        pc = params.c()
+        self._check(self.lib.rbf_eval_adjoint_at(
+            self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
+            _ptr(pts, None, "pts", self.device), Q, _pose(pose0),
+            _ptr(delta, torch.float64, "delta", self.device), _PREC[pts.dtype],
+            _ptr(gbar_f, pts.dtype, "gbar_f", self.device),
+            _ptr(gbar_r, pts.dtype, "gbar_r", self.device), _ptr(dp),
+            _ptr(d_w, torch.float64, "d_w", self.device),
+            _ptr(d_delta, torch.float64, "d_delta", self.device)), "rbf_eval_adjoint_at")
+        return dp, d_w, d_delta
 
     def eval_gn(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
                 pose, z_off: float = 0.0):
         """Fused Gauss-Newton terms of the manifold residual over the points:
         (J^T J (6x6), J^T r (6), r^T r) in FP64, per-point J not written."""
+        _need(pts, (None, 3), "pts")
         Q = pts.shape[0]
-        if pts.dim() != 2 or pts.shape[1] != 3:
-            raise ValueError("pts must be Q x 3 body-frame points")
+        _check_eval(grid, w, pts, pose)
         prec = _PREC[pts.dtype]
         JtJ = torch.empty((6, 6), dtype=torch.float64, device=pts.device)
         Jtr = torch.empty(6, dtype=torch.float64, device=pts.device)
@@ -357,7 +526,8 @@ class Context:
         pc = params.c()
         self._check(self.lib.rbf_eval_gn(
             self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
-            _ptr(pts, None, "pts"), Q, _pose(pose), z_off, prec, _ptr(JtJ), _ptr(Jtr),
+            _ptr(pts, None, "pts", self.device), Q, _pose(pose), z_off, prec, _ptr(JtJ),
+            _ptr(Jtr),
             _ptr(rtr)), "rbf_eval_gn")
         return JtJ, Jtr, rtr[0]
 
@@ -365,17 +535,36 @@ class Context:
                      pts: torch.Tensor, pose=None, gbar_f=None, gbar_r=None,
                      d_pts=True, d_w: torch.Tensor | None = None,
                      d_pose: torch.Tensor | None = None):
+        _need(pts, (None, None), "pts")
         Q, dim = pts.shape
+        _check_eval(grid, w, pts, pose)
+        _numel(gbar_f, Q, "gbar_f")
+        _numel(gbar_r, Q, "gbar_r")
+        _numel(d_w, grid.N, "d_w")
+        _numel(d_pose, 6, "d_pose")
         prec = _PREC[pts.dtype]
         dp = torch.empty_like(pts) if d_pts else None
         pc = params.c()
         self._check(self.lib.rbf_eval_adjoint(
             self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
-            _ptr(pts, None, "pts"), Q, dim, _pose(pose), prec,
-            _ptr(gbar_f, pts.dtype, "gbar_f"), _ptr(gbar_r, pts.dtype, "gbar_r"),
-            _ptr(dp), _ptr(d_w, torch.float64, "d_w"),
-            _ptr(d_pose, torch.float64, "d_pose")), "rbf_eval_adjoint")
+            _ptr(pts, None, "pts", self.device), Q, dim, _pose(pose), prec,
+            _ptr(gbar_f, pts.dtype, "gbar_f", self.device),
+            _ptr(gbar_r, pts.dtype, "gbar_r", self.device),
+            _ptr(dp), _ptr(d_w, torch.float64, "d_w", self.device),
+            _ptr(d_pose, torch.float64, "d_pose", self.device)), "rbf_eval_adjoint")
         return dp, d_w, d_pose
+
+
+def _check_eval(grid, w, pts, pose):
+    """Shapes of an evaluation call: pts Q x 2 (world xy, no pose) or Q x 3
+    (body frame, with a pose), floating point; w one weight per center."""
+    if pts.shape[1] not in (2, 3):
+        raise ValueError(f"pts: shape {tuple(pts.shape)}, expected Qx2 or Qx3")
+    if (pts.shape[1] == 3) != (pose is not None):
+        raise ValueError("pose is required for Qx3 body-frame points and only for them")
+    if pts.dtype not in (torch.float64, torch.float32):
+        raise TypeError(f"pts: dtype {pts.dtype}, expected float64 or float32")
+    _numel(w, grid.N, "w")
 
 
 class Batched:
@@ -392,6 +581,7 @@ class Batched:
         self._keep = patches
         arr = (L.Patch * len(patches))()
         for i, p in enumerate(patches):
+            _check_patch(i, p, dim)
             c = arr[i]
             c.grid = p["grid"].h
             c.w = _ptr(p["w"], torch.float64, "w", ctx.device)
@@ -446,6 +636,27 @@ class Batched:
             pass
 
 
+def _check_patch(i, p, dim):
+    """Shapes of one patch of the batched form (see Batched)."""
+    g = p["grid"]
+    xy, pts = p["xy"], p["pts"]
+    _need(xy, (None, 2), f"patch {i} xy")
+    _numel(p["z"], xy.shape[0], f"patch {i} z")
+    _numel(p["w"], g.N, f"patch {i} w")
+    P = p["P"]
+    if not isinstance(P, torch.Tensor) or P.dim() != 2 or P.shape[0] != g.N or P.shape[1] != g.N:
+        raise ValueError(f"patch {i} P: expected {g.N} x {g.N}")
+    _need(pts, (None, dim), f"patch {i} pts")
+    Q = pts.shape[0]
+    _numel(p["f"], Q, f"patch {i} f")
+    _need(p.get("grad"), (Q, 2), f"patch {i} grad")
+    if dim == 3:
+        _numel(p.get("resid"), Q, f"patch {i} resid")
+        _need(p.get("jac"), (Q, 6), f"patch {i} jac")
+        if p.get("pose") is None:
+            raise ValueError(f"patch {i}: pose required for dim 3")
+
+
 def _pose(pose):
     if pose is None:
         return None
@@ -460,14 +671,19 @@ def _pose(pose):
 class Grid:
     """Neighbour-binned center table (rbf_grid)."""
 
-    def __init__(self, ctx: Context, params: Params, centers: torch.Tensor):
+    def __init__(self, ctx: Context, params: Params, centers: torch.Tensor,
+                 entry: str = "rbf_grid_create"):
         self.ctx = ctx
         self.params = params
         h = C.c_void_p()
         pc = params.c()
-        ctx._check(ctx.lib.rbf_grid_create(
-            ctx.h, C.byref(pc), _ptr(centers, torch.float64, "centers", ctx.device),
-            centers.shape[0], C.byref(h)), "rbf_grid_create")
+        _need(centers, (None, 2), "centers")
+        cp = _ptr(centers, torch.float64, "centers", ctx.device)
+        if entry == "rbf_bin_centers":
+            st = ctx.lib.rbf_bin_centers(ctx.h, cp, centers.shape[0], C.byref(pc), C.byref(h))
+        else:
+            st = ctx.lib.rbf_grid_create(ctx.h, C.byref(pc), cp, centers.shape[0], C.byref(h))
+        ctx._check(st, entry)
         self.h = h
         N = C.c_int64()
         nbx, nby, mc = C.c_int32(), C.c_int32(), C.c_int32()

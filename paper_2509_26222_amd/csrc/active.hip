@@ -189,5 +189,5 @@ extern "C" rbf_status rbf_update_active(rbf_ctx* ctx, const rbf_params* p, const
   }
   if (rs != RBF_OK) return rs;
   if (!n_done) return RBF_OK;
-  return update_done(ctx, M, B, n_done);
+  return update_done(ctx, M, B, seq0, n_done);
 }

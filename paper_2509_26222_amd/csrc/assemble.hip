@@ -303,4 +303,25 @@ rbf_status rbf_assemble_gram(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* 
   return RBF_OK;
 }
 
+rbf_status rbf_assemble(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* xy,
+                        const double* z, int64_t M, int32_t what, rbf_prec prec, void* phi_val,
+                        int32_t* phi_col, int32_t* phi_nnz, int32_t kmax, rbf_csr* H, double* b,
+                        int32_t add_lambda) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  if (what == 0 || (what & ~(RBF_ASSEMBLE_PHI | RBF_ASSEMBLE_GRAM)) != 0)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_assemble: what must be PHI and/or GRAM");
+  if ((what & RBF_ASSEMBLE_GRAM) != 0) {
+    if (prec != RBF_F64)
+      return fail(ctx, RBF_E_INVALID_ARG, "rbf_assemble: the Gram matrix is FP64 only");
+    if (!H || !g || H->n != g->N)
+      return fail(ctx, RBF_E_INVALID_ARG, "rbf_assemble: H missing or H->n != N");
+  }
+  if ((what & RBF_ASSEMBLE_PHI) != 0)
+    RBF_TRY(rbf_assemble_phi(ctx, p, g, xy, M, prec, phi_val, phi_col, phi_nnz, kmax));
+  if ((what & RBF_ASSEMBLE_GRAM) != 0)
+    RBF_TRY(rbf_assemble_gram(ctx, p, g, xy, z, M, H->rowptr, H->colidx, H->vals, b,
+                              add_lambda));
+  return RBF_OK;
+}
+
 }  // extern "C"

@@ -182,8 +182,7 @@ rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params, const rbf_pa
       st = update_workspace(k, p.grid->N, kmax, std::min<int64_t>(B, std::max<int64_t>(p.M, 1)),
                             gemm_prec, &ws);
       if (st != RBF_OK) break;
-      EvalWs ews;
-      if ((st = eval_workspace(k, p.grid, p.Q, &ews)) != RBF_OK) break;
+      if ((st = eval_workspace(k, p.grid)) != RBF_OK) break;
     }
   }
   if (st == RBF_OK && hipDeviceSynchronize() != hipSuccess) st = RBF_E_HIP;

@@ -205,8 +205,10 @@ __global__ void __launch_bounds__(SORT_CHUNK) k_sort_scatter(const int32_t* __re
   perm[offs[c * nkeys + k] + r] = (int32_t)i;
 }
 
-rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
-                           int32_t nkeys, int32_t* perm, int32_t* start) {
+// One stable counting sort (chunk counts, their scan, the scatter); the
+// count table has nchunks x nkeys entries.
+static rbf_status counting_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n, int32_t nkeys,
+                                int32_t* perm, int32_t* start) {
   const int64_t nchunks = n > 0 ? ceil_div(n, SORT_CHUNK) : 1;
   rbf_status st;
   int32_t* counts = (int32_t*)ws_get(ctx, WS_SORT2,
@@ -228,6 +230,81 @@ rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
     k_sort_scatter<<<nchunks, SORT_CHUNK, 0, ctx->stream>>>(keys, n, nkeys, counts, perm);
     RBF_LAUNCHED(ctx, "k_sort_scatter");
   }
+  return RBF_OK;
+}
+
+// Radix passes of a large key space: digits of RADIX_BITS bits.
+constexpr int RADIX_BITS = 13;
+constexpr int64_t SORT_COUNTS_MAX = (int64_t)1 << 24;  // direct count table limit
+
+__global__ void __launch_bounds__(256) k_sort_digit(const int32_t* __restrict__ keys,
+                                                    const int32_t* __restrict__ order,
+                                                    int64_t n, int shift,
+                                                    int32_t* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  const int32_t k = keys[order ? order[s] : s];
+  out[s] = (k >> shift) & ((1 << RADIX_BITS) - 1);
+}
+
+__global__ void __launch_bounds__(256) k_sort_compose(const int32_t* __restrict__ p1,
+                                                      const int32_t* __restrict__ p2, int64_t n,
+                                                      int32_t* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  out[s] = p1[p2[s]];
+}
+
+// start[k] = first sorted position whose key is >= k (k = 0..nkeys), by
+// binary search over the sorted keys keys[perm[.]].
+__global__ void __launch_bounds__(256) k_sort_starts(const int32_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ perm,
+                                                     int64_t n, int32_t nkeys,
+                                                     int32_t* __restrict__ start) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k > nkeys) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[perm[mid]] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[k] = (int32_t)lo;
+}
+
+rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
+                           int32_t nkeys, int32_t* perm, int32_t* start) {
+  const int64_t nchunks = n > 0 ? ceil_div(n, SORT_CHUNK) : 1;
+  if (nchunks * (int64_t)nkeys <= SORT_COUNTS_MAX || n == 0)
+    return counting_sort(ctx, keys, n, nkeys, perm, start);
+  // Large key space: least-significant-digit radix sort, each pass a
+  // stable counting sort on RADIX_BITS bits, so the result is the same
+  // stable order; then the key offsets by binary search.
+  if (nkeys > (1 << (2 * RADIX_BITS)))
+    return fail(ctx, RBF_E_INVALID_ARG, "stable_key_sort: %d keys exceed the radix range",
+                (int)nkeys);
+  rbf_status st;
+  const size_t nd = ((size_t)1 << RADIX_BITS) + 1;
+  int32_t* tmp = (int32_t*)ws_get(ctx, WS_SORT3, sizeof(int32_t) * (3 * (size_t)n + nd), &st);
+  if (!tmp) return st;
+  int32_t* digit = tmp;
+  int32_t* p1 = tmp + n;
+  int32_t* p2 = tmp + 2 * n;
+  int32_t* dstart = tmp + 3 * n;  // digit offsets of a pass (not needed after it)
+  const unsigned gb = (unsigned)ceil_div(n, 256);
+  k_sort_digit<<<gb, 256, 0, ctx->stream>>>(keys, nullptr, n, 0, digit);
+  RBF_LAUNCHED(ctx, "k_sort_digit");
+  RBF_TRY(counting_sort(ctx, digit, n, 1 << RADIX_BITS, p1, dstart));
+  k_sort_digit<<<gb, 256, 0, ctx->stream>>>(keys, p1, n, RADIX_BITS, digit);
+  RBF_LAUNCHED(ctx, "k_sort_digit");
+  RBF_TRY(counting_sort(ctx, digit, n, 1 << RADIX_BITS, p2, dstart));
+  k_sort_compose<<<gb, 256, 0, ctx->stream>>>(p1, p2, n, perm);
+  RBF_LAUNCHED(ctx, "k_sort_compose");
+  k_sort_starts<<<(unsigned)ceil_div((int64_t)nkeys + 1, 256), 256, 0, ctx->stream>>>(
+      keys, perm, n, nkeys, start);
+  RBF_LAUNCHED(ctx, "k_sort_starts");
   return RBF_OK;
 }
 
@@ -311,9 +388,9 @@ rbf_status rbf_ctx_set_update_streams(rbf_ctx* ctx, int32_t streams) {
   return RBF_OK;
 }
 
-rbf_status rbf_ctx_set_eval_binned(rbf_ctx* ctx, int32_t on) {
+rbf_status rbf_ctx_set_update_joseph(rbf_ctx* ctx, int32_t on) {
   if (!ctx) return RBF_E_INVALID_ARG;
-  ctx->eval_binned = on != 0;
+  ctx->joseph = on != 0;
   return RBF_OK;
 }
 

@@ -51,6 +51,16 @@ __global__ void __launch_bounds__(256) k_bin_keys(const double* __restrict__ xy,
   keys[i] = by * g.nbx + bx;
 }
 
+__global__ void __launch_bounds__(256) k_egather(const double* __restrict__ c, int64_t n,
+                                                 const int32_t* __restrict__ idx,
+                                                 double* __restrict__ cxy) {
+  int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  int64_t i = idx[s];
+  cxy[2 * s] = c[2 * i];
+  cxy[2 * s + 1] = c[2 * i + 1];
+}
+
 __global__ void __launch_bounds__(256) k_grid_gather(const double* __restrict__ c, int64_t n,
                                                      const int32_t* __restrict__ idx,
                                                      int32_t* __restrict__ rank,
@@ -133,6 +143,14 @@ rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* p, const double* cent
   if (fx * fy > double(1 << 26))
     return fail(ctx, RBF_E_INVALID_ARG,
                 "rbf_grid_create: %.0f x %.0f bins (centers too spread for sigma)", fx, fy);
+  // evaluation bins over the same origin
+  const double eh = p->cutoff * p->sigma * EVAL_BIN_MARGIN / EVAL_BINS_PER_RC;
+  const double efx = std::floor((box[2] - x0) / eh) + 2.0;
+  const double efy = std::floor((box[3] - y0) / eh) + 2.0;
+  if (efx * efy > double(1 << 26) || efx > double(1 << 14) || efy > double(1 << 14))
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_grid_create: %.0f x %.0f evaluation bins (at most 16384 per axis and "
+                "2^26 in all; centers too spread for sigma)", efx, efy);
   rbf_grid* g = new (std::nothrow) rbf_grid;
   if (!g) return RBF_E_NOMEM;
   memset(g, 0, sizeof(*g));
@@ -147,12 +165,20 @@ rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* p, const double* cent
   g->sigma = p->sigma;
   g->cutoff = p->cutoff;
   g->sigma_eps = p->sigma_eps;
+  g->eh = eh;
+  g->inv_eh = 1.0 / eh;
+  g->enbx = (int32_t)efx;
+  g->enby = (int32_t)efy;
   const int64_t nbins = (int64_t)g->nbx * g->nby;
+  const int64_t enbins = (int64_t)g->enbx * g->enby;
   bool ok = hipMalloc(&g->d_start, sizeof(int32_t) * (nbins + 1)) == hipSuccess &&
             hipMalloc(&g->d_idx, sizeof(int32_t) * N) == hipSuccess &&
             hipMalloc(&g->d_rank, sizeof(int32_t) * N) == hipSuccess &&
             hipMalloc(&g->d_cxy, sizeof(double) * 2 * N) == hipSuccess &&
-            hipMalloc(&g->d_cxyf, sizeof(float) * 2 * N) == hipSuccess;
+            hipMalloc(&g->d_cxyf, sizeof(float) * 2 * N) == hipSuccess &&
+            hipMalloc(&g->d_estart, sizeof(int32_t) * (enbins + 1)) == hipSuccess &&
+            hipMalloc(&g->d_eidx, sizeof(int32_t) * N) == hipSuccess &&
+            hipMalloc(&g->d_ecxy, sizeof(double) * 2 * N) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     rbf_grid_destroy(g);
@@ -171,6 +197,23 @@ rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* p, const double* cent
     k_grid_gather<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(centers, N, g->d_idx, g->d_rank,
                                                              g->d_cxy, g->d_cxyf);
     st = check_launch(ctx, "k_grid_gather");
+  }
+  // the same centers in evaluation-bin order
+  if (st == RBF_OK) {
+    GridGeom eg;
+    eg.x0 = x0;
+    eg.y0 = y0;
+    eg.inv_h = g->inv_eh;
+    eg.nbx = g->enbx;
+    eg.nby = g->enby;
+    k_bin_keys<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(centers, N, eg, keys);
+    st = check_launch(ctx, "k_bin_keys");
+  }
+  if (st == RBF_OK)
+    st = stable_key_sort(ctx, keys, N, (int32_t)enbins, g->d_eidx, g->d_estart);
+  if (st == RBF_OK) {
+    k_egather<<<ceil_div(N, 256), 256, 0, ctx->stream>>>(centers, N, g->d_eidx, g->d_ecxy);
+    st = check_launch(ctx, "k_egather");
   }
   int32_t* d_mc = nullptr;
   if (st == RBF_OK) {
@@ -195,6 +238,11 @@ rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* p, const double* cent
   return RBF_OK;
 }
 
+rbf_status rbf_bin_centers(rbf_ctx* ctx, const double* centers, int64_t N,
+                           const rbf_params* p, rbf_grid** out) {
+  return rbf_grid_create(ctx, p, centers, N, out);
+}
+
 rbf_status rbf_grid_destroy(rbf_grid* g) {
   if (!g) return RBF_E_INVALID_ARG;
   (void)hipSetDevice(g->device);
@@ -203,6 +251,9 @@ rbf_status rbf_grid_destroy(rbf_grid* g) {
   if (g->d_rank) (void)hipFree(g->d_rank);
   if (g->d_cxy) (void)hipFree(g->d_cxy);
   if (g->d_cxyf) (void)hipFree(g->d_cxyf);
+  if (g->d_estart) (void)hipFree(g->d_estart);
+  if (g->d_eidx) (void)hipFree(g->d_eidx);
+  if (g->d_ecxy) (void)hipFree(g->d_ecxy);
   delete g;
   return RBF_OK;
 }

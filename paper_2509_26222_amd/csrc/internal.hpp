@@ -21,6 +21,9 @@ enum WsSlot {
   WS_SORT0,
   WS_SORT1,
   WS_SORT2,
+  WS_SORT3,     // radix passes of stable_key_sort (digits, two permutations)
+  WS_POSE,      // evaluation at a pose increment: pose, right Jacobian, gradient
+  WS_JOSEPH,    // update, Joseph form: L^{-1}, K^T, FP32 operands
   WS_UPD_ELL,   // update: regressor rows of a batch
   WS_UPD_UT,    // update: U^T then V^T (B x ldu)
   WS_UPD_S,     // update: S then L (B x B)
@@ -31,7 +34,6 @@ enum WsSlot {
   WS_UPD_FLAGS, // update: touched 128-row blocks of P, two batches
   WS_UPD_GROUPS,// update: per 64-row group, the distinct rows of P and dense H
   WS_UPD_VT,    // update: V^T = L^{-1} U^T, two buffers
-  WS_LINV_F32,  // update, mixed form: L^{-1} and U^T rounded to float
   WS_ACT_IDX,   // active-rows update: flags / compact map, active list, w_A
   WS_ACT_P,     // active-rows update: compact block P_AA
   WS_SOLVE0,
@@ -65,9 +67,9 @@ struct rbf_ctx {
   // rbf_update keeps to one stream (set for the batched form's branches,
   // whose graph capture does not take the two-stream schedule)
   int32_t single_stream;
-  // rbf_eval groups the points by bin and stages candidates in LDS
-  // (rbf_ctx_set_eval_binned); off by default
-  int32_t eval_binned;
+  // rbf_update applies the covariance update in the Joseph form (FP32
+  // products only; rbf_ctx_set_update_joseph)
+  int32_t joseph;
   void* ws[rbf::WS_COUNT];
   size_t ws_bytes[rbf::WS_COUNT];
   int64_t last_index;
@@ -96,7 +98,24 @@ struct rbf_grid {
   int32_t* d_rank;   // original center index -> sorted position
   double* d_cxy;     // sorted centers, interleaved (x, y), f64
   float* d_cxyf;     // sorted centers, interleaved (x, y), f32
+  // Evaluation bins: side eh of about a third of the evaluation support
+  // cutoff*sigma, same origin (x0, y0), row-major; the centers sorted by
+  // them give the evaluation kernels short candidate runs per bin row.
+  double eh, inv_eh;
+  int32_t enbx, enby;
+  int32_t* d_estart;  // enbx*enby + 1 offsets into the eval-sorted order
+  int32_t* d_eidx;    // eval-sorted position -> original center index
+  double* d_ecxy;     // eval-sorted centers, interleaved (x, y), f64
 };
+
+namespace rbf {
+// Evaluation bin side in units of the support radius cutoff*sigma: a
+// point's support spans at most 7 bin rows (2 * EVAL_BINS_PER_RC /
+// (1 + margin) + a pad < 6 bin widths).
+constexpr double EVAL_BINS_PER_RC = 3.0;
+constexpr double EVAL_BIN_MARGIN = 1.01;
+constexpr int EVAL_MAX_ROWS = 8;
+}  // namespace rbf
 
 namespace rbf {
 
@@ -179,21 +198,9 @@ void prof_end(rbf_ctx* ctx, int kind);
 // inside stream capture).
 rbf_status fill_zero(rbf_ctx* ctx, void* p, size_t bytes);
 
-// Workspace of the binned evaluation of Q points on grid g (bin keys, the
-// permutation, bin offsets and cursors, and the packed center table); the
+// Workspace of an evaluation on grid g (the packed center table); the
 // batched plan reserves it before capture.
-struct EvalWs {
-  int32_t* keys;
-  int32_t* perm;
-  int32_t* counts;  // nbins + 2 offsets (scanned in place)
-  int32_t* cursor;  // nbins + 2 per-bin ranks
-};
-rbf_status eval_workspace(rbf_ctx* ctx, const rbf_grid* g, int64_t Q, EvalWs* ws);
-// With the context's binned mode on, query sets of at least this size use
-// the binned evaluation (if the largest neighbourhood fits in EVAL_LDS_MAX
-// bytes of LDS).
-constexpr int64_t EVAL_BINNED_MIN = 2048;
-constexpr size_t EVAL_LDS_MAX = 48 * 1024;
+rbf_status eval_workspace(rbf_ctx* ctx, const rbf_grid* g);
 
 // Create the context's second stream and its two events if not yet done.
 rbf_status ensure_aux(rbf_ctx* ctx);
@@ -209,8 +216,10 @@ struct StreamSwap {
   StreamSwap& operator=(const StreamSwap&) = delete;
 };
 
-// Stable counting sort by a precomputed key in [0, nkeys): writes perm
-// (sorted position -> item) and start (nkeys + 1 offsets).
+// Stable sort by a precomputed key in [0, nkeys): writes perm (sorted
+// position -> item) and start (nkeys + 1 offsets). One counting sort when
+// its count table (one row of nkeys per 1024 items) is small, else two
+// 13-bit radix passes (nkeys <= 2^26). start holds nkeys + 1 entries.
 rbf_status stable_key_sort(rbf_ctx* ctx, const int32_t* keys, int64_t n,
                            int32_t nkeys, int32_t* perm, int32_t* start);
 

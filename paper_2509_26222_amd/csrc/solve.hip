@@ -13,6 +13,7 @@
 // x += solve(b - calH x) until ||b - calH x|| <= rtol ||b|| per column.
 // Dense blocks use the FP64 MFMA kernels of the covariance update.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <vector>
 
@@ -378,13 +379,23 @@ __global__ void __launch_bounds__(256) k_dot_sum(const double* __restrict__ part
 // Scalars of the iteration (device): rz = r.z, rz_new, pq = p.(calH p), rr.
 enum { SC_RZ = 0, SC_RZN = 1, SC_PQ = 2, SC_RR = 3, SC_N = 4 };
 
-// w += alpha p, r -= alpha q, alpha = rz / pq
+// A step is taken only with positive curvature of both the preconditioner
+// (r.z > 0) and calH (p.calH p > 0) and a finite step length; the host
+// applies the same test to stop the iteration.
+__host__ __device__ inline bool pcg_step_ok(double rz, double pq) {
+  // a <= DBL_MAX is false for NaN and infinity
+  return rz > 0.0 && pq > 0.0 && rz / pq <= DBL_MAX;
+}
+
+// w += alpha p, r -= alpha q, alpha = rz / pq; nothing is written unless
+// pcg_step_ok holds, so w keeps the last accepted iterate.
 __global__ void __launch_bounds__(256) k_pcg_step(double* __restrict__ w, double* __restrict__ r,
                                                   const double* __restrict__ p,
                                                   const double* __restrict__ q, int64_t N,
                                                   const double* __restrict__ sc) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= N) return;
+  if (!pcg_step_ok(sc[SC_RZ], sc[SC_PQ])) return;
   const double alpha = sc[SC_RZ] / sc[SC_PQ];
   w[e] += alpha * p[e];
   r[e] -= alpha * q[e];
@@ -479,7 +490,7 @@ extern "C" rbf_status rbf_refine(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
       ++it;
       RBF_TRY(dot(r, r, SC_RR));
       RBF_TRY(read());
-      if (!(h[SC_RZ] > 0.0) || !(h[SC_PQ] > 0.0)) {  // P / R or calH not positive definite
+      if (!pcg_step_ok(h[SC_RZ], h[SC_PQ])) {  // P / R or calH not positive definite
         breakdown = true;
         break;
       }

@@ -281,6 +281,9 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
 // as k_syrk_f64; the k-range of row block I stops at its last row
 // ((I + 1) * 128), where X is zero beyond. Heavier row blocks are issued
 // first.
+// UPPER: X upper triangular instead (the operand holds X transposed all
+// the same), the k-range of row block I starting at its first row.
+template <bool UPPER>
 __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restrict__ LiT,
                                                            int32_t n,
                                                            const double* __restrict__ Ut,
@@ -290,9 +293,11 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restr
                                                            int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int nI = (n + ST - 1) / ST;
-  const int I = nI - 1 - (int)(blockIdx.x / nJ), J = (int)(blockIdx.x % nJ);
+  const int I = UPPER ? (int)(blockIdx.x / nJ) : nI - 1 - (int)(blockIdx.x / nJ);
+  const int J = (int)(blockIdx.x % nJ);
   const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
-  const int K = min(n, (I + 1) * ST);
+  const int kb = UPPER ? I * ST : 0;  // first k of the row block (a multiple of SKC)
+  const int K = UPPER ? n : min(n, (I + 1) * ST);
   __shared__ double As[2][SKC][SLD];
   __shared__ double Bs[2][SKC][SLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -302,18 +307,18 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restr
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-  const int nch = (K + SKC - 1) / SKC;
+  const int nch = (K - kb + SKC - 1) / SKC;
   double2 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
-  load_stage<SYRK_NT>(LiT, n, n, 0, K, I0, ra);
-  load_stage<SYRK_NT>(Ut, ldu, ncols, 0, K, J0, rb);
+  load_stage<SYRK_NT>(LiT, n, n, kb, K, I0, ra);
+  load_stage<SYRK_NT>(Ut, ldu, ncols, kb, K, J0, rb);
   store_stage<SYRK_NT, SLD>(As[0], ra);
   store_stage<SYRK_NT, SLD>(Bs[0], rb);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nch) {
-      load_stage<SYRK_NT>(LiT, n, n, (ch + 1) * SKC, K, I0, ra);
-      load_stage<SYRK_NT>(Ut, ldu, ncols, (ch + 1) * SKC, K, J0, rb);
+      load_stage<SYRK_NT>(LiT, n, n, kb + (ch + 1) * SKC, K, I0, ra);
+      load_stage<SYRK_NT>(Ut, ldu, ncols, kb + (ch + 1) * SKC, K, J0, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < SKC; kk += 4) {
@@ -419,7 +424,7 @@ __global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ U
 template <bool BATCH>
 __device__ inline void epilogue_f32acc_w8(double* __restrict__ P, int64_t ldp, int64_t N,
                                           int64_t I0, int64_t J0, bool diag,
-                                          const v4f acc[2][4]) {
+                                          const v4f acc[2][4], double sgn = 1.0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   if (!BATCH) {
@@ -432,7 +437,7 @@ __device__ inline void epilogue_f32acc_w8(double* __restrict__ P, int64_t ldp, i
           const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
           const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
           if (gi < N && gj < N && (!diag || gi >= gj)) {
-            const double nv = P[gi * ldp + gj] - (double)acc[mi][ni][v];
+            const double nv = P[gi * ldp + gj] - sgn * (double)acc[mi][ni][v];
             P[gi * ldp + gj] = nv;
             if (gi != gj) P[gj * ldp + gi] = nv;
           }
@@ -515,13 +520,18 @@ __device__ inline void store_stage_f32(float (*X)[FLD], const float4 v[1024 / NT
   }
 }
 
+// P -= sgn X1 X2^T on the lower tiles, mirrored (X2 = X1 unless given:
+// the product is symmetric in every use).
 __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
                                                      int64_t N, const float* __restrict__ Uf,
                                                      int64_t ldu, int32_t K, int64_t T,
                                                      int64_t per_xcd,
                                                      const int32_t* __restrict__ flags, int part,
                                                      const int32_t* __restrict__ status,
-                                                     int64_t seq) {
+                                                     int64_t seq,
+                                                     const float* __restrict__ Uf2 = nullptr,
+                                                     double sgn = 1.0) {
+  const float* __restrict__ Ub = Uf2 ? Uf2 : Uf;
   if (seq_skip(status, seq)) return;
   const int64_t t = xcd_tile(per_xcd);
   if (t >= T) return;
@@ -541,7 +551,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
   const int nch = (K + FKC - 1) / FKC;
   float4 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
   load_stage_f32<SYRK_NT>(Uf, ldu, N, 0, K, I0, ra);
-  load_stage_f32<SYRK_NT>(Uf, ldu, N, 0, K, J0, rb);
+  load_stage_f32<SYRK_NT>(Ub, ldu, N, 0, K, J0, rb);
   store_stage_f32<SYRK_NT>(As[0], ra);
   store_stage_f32<SYRK_NT>(Bs[0], rb);
   __syncthreads();
@@ -549,7 +559,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
     const int buf = ch & 1;
     if (ch + 1 < nch) {
       load_stage_f32<SYRK_NT>(Uf, ldu, N, (ch + 1) * FKC, K, I0, ra);
-      load_stage_f32<SYRK_NT>(Uf, ldu, N, (ch + 1) * FKC, K, J0, rb);
+      load_stage_f32<SYRK_NT>(Ub, ldu, N, (ch + 1) * FKC, K, J0, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < FKC; kk += 4) {
@@ -571,77 +581,7 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
     }
     __syncthreads();
   }
-  epilogue_f32acc_w8<false>(P, ldp, N, I0, J0, I == J, acc);
-}
-
-// The triangular solve's product V^T = X U^T of the mixed form on FP32 MFMA
-// (operands rounded to float once per batch, FP32 accumulation, V^T stored
-// in FP64): same tiles, k-range and order of row blocks as k_linv_apply.
-__global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply_f32(const float* __restrict__ Lf,
-                                                               int32_t n,
-                                                               const float* __restrict__ Uf,
-                                                               int64_t ldu, int64_t ncols,
-                                                               double* __restrict__ Vt,
-                                                               int32_t nJ,
-                                                               const int32_t* __restrict__ status,
-                                                               int64_t seq) {
-  if (seq_skip(status, seq)) return;
-  const int nI = (n + ST - 1) / ST;
-  const int I = nI - 1 - (int)(blockIdx.x / nJ), J = (int)(blockIdx.x % nJ);
-  const int64_t I0 = (int64_t)I * ST, J0 = (int64_t)J * ST;
-  const int K = min(n, (I + 1) * ST);
-  __shared__ __attribute__((aligned(16))) float As[2][FKC][FLD];
-  __shared__ __attribute__((aligned(16))) float Bs[2][FKC][FLD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  v4f acc[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-  const int nch = (K + FKC - 1) / FKC;
-  float4 ra[1024 / SYRK_NT], rb[1024 / SYRK_NT];
-  load_stage_f32<SYRK_NT>(Lf, n, n, 0, K, I0, ra);
-  load_stage_f32<SYRK_NT>(Uf, ldu, ncols, 0, K, J0, rb);
-  store_stage_f32<SYRK_NT>(As[0], ra);
-  store_stage_f32<SYRK_NT>(Bs[0], rb);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) {
-      load_stage_f32<SYRK_NT>(Lf, n, n, (ch + 1) * FKC, K, I0, ra);
-      load_stage_f32<SYRK_NT>(Uf, ldu, ncols, (ch + 1) * FKC, K, J0, rb);
-    }
-#pragma unroll
-    for (int kk = 0; kk < FKC; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      float a[2], b[4];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) a[q] = As[buf][kr][wm * 32 + q * 16 + (lane & 15)];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = Bs[buf][kr][wn * 64 + q * 16 + (lane & 15)];
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
-    }
-    if (ch + 1 < nch) {
-      store_stage_f32<SYRK_NT>(As[buf ^ 1], ra);
-      store_stage_f32<SYRK_NT>(Bs[buf ^ 1], rb);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 4; ++ni)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t gi = I0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
-        const int64_t gj = J0 + wn * 64 + ni * 16 + (lane & 15);
-        if (gi < n && gj < ncols) Vt[gi * ldu + gj] = (double)acc[mi][ni][v];
-      }
+  epilogue_f32acc_w8<false>(P, ldp, N, I0, J0, I == J, acc, sgn);
 }
 
 constexpr int BKC = 64;      // k per stage (two 16x16x32 MFMA steps)
@@ -815,33 +755,76 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
 }
 
 rbf_status linv_apply(rbf_ctx* ctx, const double* LiT, int32_t n, const double* Ut,
-                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq, rbf_prec prec) {
+                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq) {
   if (n <= 0 || ncols <= 0) return RBF_OK;
   const int64_t nI = ceil_div(n, ST), nJ = ceil_div(ncols, ST);
-  if (prec == RBF_F64) {
-    k_linv_apply<<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(LiT, n, Ut, ldu, ncols, Vt,
-                                                                    (int32_t)nJ, ctx->d_status,
-                                                                    seq);
-    RBF_LAUNCHED(ctx, "k_linv_apply");
-    return RBF_OK;
-  }
-  // mixed form: X and U^T (all n rows, the padding ones being zero) rounded
-  // to float into a slot of their own (the product's low-precision copy of
-  // V^T may still be in use by the previous batch), then the FP32 product
+  k_linv_apply<false><<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(
+      LiT, n, Ut, ldu, ncols, Vt, (int32_t)nJ, ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_linv_apply");
+  return RBF_OK;
+}
+
+__global__ void __launch_bounds__(256) k_transpose_f64(const double* __restrict__ A, int32_t n,
+                                                       double* __restrict__ B,
+                                                       const int32_t* __restrict__ status,
+                                                       int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8)
+    if (by + r < n && bx + tx < n) t[r][tx] = A[(int64_t)(by + r) * n + bx + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8)
+    if (bx + r < n && by + tx < n) B[(int64_t)(bx + r) * n + by + tx] = t[tx][r];
+}
+
+rbf_status syrk_update_joseph(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Vt,
+                              const double* Ut, const double* LiT, int64_t ldu, int32_t Bc,
+                              int32_t Bpc, int64_t seq) {
   rbf_status st;
-  float* Lf = (float*)ws_get(ctx, WS_LINV_F32,
-                             sizeof(float) * ((size_t)n * n + (size_t)n * ldu), &st);
-  if (!Lf) return st;
-  float* Uf = Lf + (size_t)n * n;
-  k_cvt_f32<<<ceil_div((int64_t)n * n, 256), 256, 0, ctx->stream>>>(LiT, n, n, n, Lf,
-                                                                    ctx->d_status, seq);
+  const size_t ku = (size_t)Bpc * ldu;
+  char* wsb = (char*)ws_get(ctx, WS_JOSEPH,
+                            sizeof(double) * ((size_t)Bpc * Bpc + ku) + sizeof(float) * 4 * ku,
+                            &st);
+  if (!wsb) return st;
+  double* Lr = (double*)wsb;           // L^{-1} row-major
+  double* Kt = Lr + (size_t)Bpc * Bpc;  // K^T = L^{-T} V^T (FP64)
+  float* X = (float*)(Kt + ku);        // [K^T; U^T; K^T] (3 Bc rows), then V^T
+  float* Vf = X + 3 * (size_t)Bc * ldu;
+  const dim3 gt((unsigned)ceil_div(Bpc, 32), (unsigned)ceil_div(Bpc, 32));
+  k_transpose_f64<<<gt, 256, 0, ctx->stream>>>(LiT, Bpc, Lr, ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_transpose_f64");
+  const int64_t nI = ceil_div(Bpc, ST), nJ = ceil_div(N, ST);
+  k_linv_apply<true><<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(
+      Lr, Bpc, Vt, ldu, N, Kt, (int32_t)nJ, ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_linv_apply");
+  const unsigned gc = (unsigned)ceil_div((int64_t)Bc * ldu, 256);
+  k_cvt_f32<<<gc, 256, 0, ctx->stream>>>(Kt, ldu, Bc, N, X, ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_cvt_f32");
-  k_cvt_f32<<<ceil_div((int64_t)n * ldu, 256), 256, 0, ctx->stream>>>(Ut, ldu, n, ncols, Uf,
-                                                                      ctx->d_status, seq);
+  k_cvt_f32<<<gc, 256, 0, ctx->stream>>>(Ut, ldu, Bc, N, X + (size_t)Bc * ldu, ctx->d_status,
+                                         seq);
   RBF_LAUNCHED(ctx, "k_cvt_f32");
-  k_linv_apply_f32<<<(unsigned)(nI * nJ), SYRK_NT, 0, ctx->stream>>>(
-      Lf, n, Uf, ldu, ncols, Vt, (int32_t)nJ, ctx->d_status, seq);
-  RBF_LAUNCHED(ctx, "k_linv_apply_f32");
+  k_cvt_f32<<<gc, 256, 0, ctx->stream>>>(Kt, ldu, Bc, N, X + 2 * (size_t)Bc * ldu,
+                                         ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_cvt_f32");
+  k_cvt_f32<<<gc, 256, 0, ctx->stream>>>(Vt, ldu, Bc, N, Vf, ctx->d_status, seq);
+  RBF_LAUNCHED(ctx, "k_cvt_f32");
+  const int64_t nt = ceil_div(N, ST);
+  const int64_t T = nt * (nt + 1) / 2;
+  const int64_t per_xcd = ceil_div(T, 8);
+  const unsigned grid = (unsigned)(per_xcd * 8);
+  prof_begin(ctx, RBF_PROF_SYRK);
+  // P -= K U^T + U K^T: [K U] [U K]^T over 2 Bc terms
+  k_syrk_f32<<<grid, SYRK_NT, 0, ctx->stream>>>(P, ldp, N, X, ldu, 2 * Bc, T, per_xcd, nullptr,
+                                                0, ctx->d_status, seq, X + (size_t)Bc * ldu,
+                                                1.0);
+  RBF_LAUNCHED(ctx, "k_syrk_f32");
+  // P += K S K^T = V V^T
+  k_syrk_f32<<<grid, SYRK_NT, 0, ctx->stream>>>(P, ldp, N, Vf, ldu, Bc, T, per_xcd, nullptr, 0,
+                                                ctx->d_status, seq, nullptr, -1.0);
+  RBF_LAUNCHED(ctx, "k_syrk_f32");
+  prof_end(ctx, RBF_PROF_SYRK);
   return RBF_OK;
 }
 

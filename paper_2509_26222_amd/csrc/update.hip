@@ -1017,11 +1017,14 @@ rbf_status update_workspace(rbf_ctx* ctx, int64_t N, int32_t kmax, int64_t Bmax,
     ws->glist = (int32_t*)(gw + (size_t)ng * Rcap * 64 * sizeof(double));
     ws->gR = ws->glist + (size_t)ng * Rcap;
   }
-  if (gemm_prec != RBF_F64 &&
-      !ws_get(ctx, WS_LINV_F32, sizeof(float) * ((size_t)Bp * Bp + (size_t)Bp * ldu), &st))
-    return st;
   if (gemm_prec == RBF_F32) {
     if (!ws_get(ctx, WS_UPD_VLO, sizeof(float) * (size_t)Bp * ldu, &st)) return st;
+    if (ctx->joseph &&
+        !ws_get(ctx, WS_JOSEPH,
+                sizeof(double) * ((size_t)Bp * Bp + (size_t)Bp * ldu) +
+                    sizeof(float) * 4 * (size_t)Bp * ldu,
+                &st))
+      return st;
   } else if (gemm_prec == RBF_BF16) {
     if (!ws_get(ctx, WS_UPD_VLO, 2 * 2 * (size_t)N * Bp, &st)) return st;
   }
@@ -1184,6 +1187,21 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
                       const double* xy, const double* z, int64_t M, int64_t B,
                       rbf_prec gemm_prec) {
   RBF_TRY(set_device(ctx));
+  // The two-stream schedule is not captured: under stream capture (a
+  // caller's graph) a context set to two streams returns an error instead
+  // (a process crash was seen once while capturing it, with its cause not
+  // established; the batched form's branches use one stream).
+  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusActive;
+  if (hipStreamIsCapturing(ctx->stream, &cap_st) != hipSuccess) {
+    (void)hipGetLastError();  // not left for the next launch check
+    cap_st = hipStreamCaptureStatusActive;
+  }
+  if (!ctx->single_stream && cap_st != hipStreamCaptureStatusNone)
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_update: the two-stream schedule cannot be captured (set streams = 1)");
+  if (ctx->joseph && (gemm_prec != RBF_F32 || !ctx->single_stream))
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_update: the Joseph form is available with FP32 products on one stream");
   const int32_t kmax = g->max_cand > 0 ? g->max_cand : 1;
   const int64_t ldu = ceil_div(N + 1, 32) * 32;
   UpdWs ws;
@@ -1206,16 +1224,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
   // (regressor rows, U, S, Cholesky, V, w). Batch bi+1's gather reads only
   // the rows of P in its touched blocks, which part 1 of batch bi's product
   // finishes first; part 2 (all other tiles) overlaps the chain.
-  // Under stream capture (the batched form's graph, or a caller's) the
-  // update keeps to the single-stream schedule: a process crash was seen
-  // while capturing the two-stream one, with its cause not established.
-  hipStreamCaptureStatus cap_st = hipStreamCaptureStatusActive;
-  if (hipStreamIsCapturing(ctx->stream, &cap_st) != hipSuccess) {
-    (void)hipGetLastError();  // not left for the next launch check
-    cap_st = hipStreamCaptureStatusActive;
-  }
-  const bool two =
-      nb_total > 1 && !ctx->single_stream && cap_st == hipStreamCaptureStatusNone;
+  const bool two = nb_total > 1 && !ctx->single_stream;
   if (two) RBF_TRY(ensure_aux(ctx));
   hipStream_t ms = ctx->stream;
   hipStream_t as = two ? ctx->aux : ctx->stream;
@@ -1289,7 +1298,7 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     RBF_TRY(chol_blocked(ctx, S, Bpc, Lb, Linv, ctx->index_base + bi, sq, ws.LiT));
     prof_end(ctx, RBF_PROF_CHOL);
     prof_begin(ctx, RBF_PROF_TRSM);
-    RBF_TRY(linv_apply(ctx, ws.LiT, Bpc, Ut, ldu, N + 1, Vt, sq, gemm_prec));
+    RBF_TRY(linv_apply(ctx, ws.LiT, Bpc, Ut, ldu, N + 1, Vt, sq));
     prof_end(ctx, RBF_PROF_TRSM);
     dim3 gw((unsigned)ceil_div(N, 256), (unsigned)ceil_div(Bc, 64));
     k_upd_w_part<<<gw, 256, 0, ctx->stream>>>(Vt, ldu, N, Bc, wpart, ctx->d_status, sq);
@@ -1316,8 +1325,12 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
       sizes(bi, &Bc, &Bpc);
       RBF_TRY(rows(bi));
       RBF_TRY(chain(bi));
-      RBF_TRY(syrk_update(ctx, P, ldp, N, VtB[bi & 1], ldu, Bc, gemm_prec, nullptr, 0,
-                          seq0 + bi));
+      if (ctx->joseph)
+        RBF_TRY(syrk_update_joseph(ctx, P, ldp, N, VtB[bi & 1], UtB[bi & 1], ws.LiT, ldu, Bc,
+                                   Bpc, seq0 + bi));
+      else
+        RBF_TRY(syrk_update(ctx, P, ldp, N, VtB[bi & 1], ldu, Bc, gemm_prec, nullptr, 0,
+                            seq0 + bi));
     }
   } else {
     RBF_HIP(ctx, hipEventRecord(ctx->ev_fwd, ms));
@@ -1356,16 +1369,26 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
 }
 
 // After update_run: wait for the stream and report the points absorbed
-// (all M, or the batches before the first failing one) and the status.
-rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t* n_done) {
-  int32_t h[4];
+// (all M, or the batches before the first failing one) and the status. An
+// error recorded before this call's first launch group seq0 (a pending
+// error of an earlier asynchronous call, or one outside any group) made
+// every batch skip: nothing was absorbed, and that error is returned.
+rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t seq0, int64_t* n_done) {
+  int32_t h[6];
   RBF_HIP(ctx, hipMemcpyAsync(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost,
                               ctx->stream));
   RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (h[0] != 0) {
     int64_t idx;
+    uint64_t key;
     memcpy(&idx, h + 2, sizeof(idx));
-    const int64_t done = (idx - ctx->index_base) * B;
+    memcpy(&key, h + 4, sizeof(key));
+    const int64_t failed_seq = (int64_t)(SEQ_TOP - key);  // smallest failing group
+    int64_t done = 0;
+    if (failed_seq >= seq0) {
+      done = (idx - ctx->index_base) * B;
+      if (done < 0) done = 0;
+    }
     *n_done = done < M ? done : M;
     return rbf_sync_status(ctx);
   }
@@ -1386,7 +1409,8 @@ extern "C" rbf_status rbf_update(rbf_ctx* ctx, const rbf_params* p, const rbf_gr
   RBF_TRY(update_check(ctx, p, g, w, P, ldp, xy, z, M, batch, gemm_prec));
   if (M == 0) return RBF_OK;
   const int64_t B = batch > 0 ? batch : UPDATE_DEFAULT_BATCH;
+  const int64_t seq0 = ctx->seq;  // launch group of the first batch
   RBF_TRY(update_run(ctx, p, g, nullptr, g->N, w, P, ldp, xy, z, M, B, gemm_prec));
   if (!n_done) return RBF_OK;
-  return update_done(ctx, M, B, n_done);
+  return update_done(ctx, M, B, seq0, n_done);
 }

@@ -39,6 +39,15 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
                        int64_t ldu, int32_t Bc, rbf_prec prec, const int32_t* flags,
                        int part, int64_t seq);
 
+// Joseph form of the same update with FP32 products: with the gain
+// K = U S^{-1} = V L^{-1} formed in FP64 (K^T = L^{-T} V^T from LiT, the
+// rows of L^{-1} transposed, n = Bpc), P += -(K U^T + U K^T) + K S K^T,
+// K S K^T = V V^T, each product on FP32 MFMA from FP32-rounded operands and
+// accumulated into the FP64 P with the mirrored write. Ut: U^T of the batch.
+rbf_status syrk_update_joseph(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Vt,
+                              const double* Ut, const double* LiT, int64_t ldu, int32_t Bc,
+                              int32_t Bpc, int64_t seq);
+
 // Device workspace of rbf_update for N centers, kmax candidates per point
 // and batches of at most Bmax points (all slots grown up front, so later
 // calls with these sizes allocate nothing).
@@ -91,11 +100,10 @@ rbf_status chol_blocked(rbf_ctx* ctx, double* S, int32_t n, double* Lb, double* 
 // entry), chol_blocked also forms X = L^{-1} transposed: LiT[c][r] = X[r][c].
 // linv_apply then computes V^T = X U^T (n x ncols, rows of U^T with leading
 // dimension ldu) into Vt (leading dimension ldu) on FP64 MFMA: the block
-// triangular solve as one product. prec = RBF_F32 or RBF_BF16 (the mixed
-// form) rounds X and U^T to float and multiplies on FP32 MFMA.
+// triangular solve as one product (FP64 in every form: the gain V feeds the
+// weight update w += V t directly).
 rbf_status linv_apply(rbf_ctx* ctx, const double* LiT, int32_t n, const double* Ut,
-                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq,
-                      rbf_prec prec = RBF_F64);
+                      int64_t ldu, int64_t ncols, double* Vt, int64_t seq);
 
 // X := L^{-1} X (trans = false) or X := L^{-T} X (trans = true) in place for
 // X with nblk*64 rows, ncols columns and leading dimension ldx, with L given
@@ -121,7 +129,8 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
 
 // Wait for the context's stream and report the points absorbed: M, or the
 // points of the batches before the first failing one (whose error is
-// returned and cleared).
-rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t* n_done);
+// returned and cleared). seq0 is the launch group of the call's first
+// batch; an error recorded before it leaves n_done = 0.
+rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t seq0, int64_t* n_done);
 
 }  // namespace rbf

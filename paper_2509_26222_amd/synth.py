@@ -378,14 +378,17 @@ class Patch:
 
 
 def patches_case(seed: int = 4, count: int = 256, n_range=(200, 8000),
-                 m_range=(1000, 40000), spacing: float = 0.5):
+                 m_range=(1000, 40000), spacing: float = 0.5, only=None):
     """Independent patches; centers on a 0.5 m grid (first N_p nodes of a
     round(sqrt(N_p))-wide row-major mesh, +/-0.1 m jitter), points uniform
-    over the covered rectangle, terrain flat / bumpy / stair."""
+    over the covered rectangle, terrain flat / bumpy / stair. With `only` (a
+    set of patch indices) the heights of the other patches are not computed
+    (their z is None); every random stream is drawn as without it, so the
+    selected patches are the same."""
     ss = np.random.SeedSequence(seed).spawn(6)
     r_c, r_t, r_p, r_n = [np.random.default_rng(s) for s in ss[:4]]
     out = []
-    for _ in range(count):
+    for idx in range(count):
         npc = int(r_c.integers(n_range[0], n_range[1] + 1))
         mp = int(r_p.integers(m_range[0], m_range[1] + 1))
         nx = int(round(math.sqrt(npc)))
@@ -419,6 +422,7 @@ def patches_case(seed: int = 4, count: int = 256, n_range=(200, 8000),
         rows = int(math.ceil(npc / nx))
         xy = np.stack([r_p.uniform(0, w_side, mp),
                        r_p.uniform(0, rows * spacing, mp)], 1)
-        z = terr.height(xy) + r_n.normal(0.0, 0.02, size=mp)
+        noise = r_n.normal(0.0, 0.02, size=mp)
+        z = terr.height(xy) + noise if (only is None or idx in only) else None
         out.append(Patch(centers, xy, z, kind))
     return Params(), out

@@ -20,6 +20,14 @@ from paper_2509_26222_amd.autograd import rbf_eval_f_r
 pytestmark = pytest.mark.gpu
 
 
+def _off_cutoff(pts, R, t, centers, p, margin):
+    """1.0 for body points whose world xy is farther than `margin` (m) from
+    every center's cutoff circle, else 0.0."""
+    xi = O.to_world(pts, R, t)
+    d = np.sqrt(O.sq_dist(xi[:, :2], centers))
+    return (np.abs(d - p.cutoff * p.sigma) > margin).all(1).astype(np.float64)
+
+
 def _close(a, b, rel):
     scale = max(np.abs(b).max(), 1e-30)
     return np.abs(a - b).max() <= rel * scale
@@ -90,8 +98,9 @@ def test_autograd_fd_f64_subset(ctx, diff_case):
     P = dev(pts[idx]).requires_grad_(True)
     W = dev(w).requires_grad_(True)
     D = torch.zeros(6, dtype=torch.float64, device="cuda", requires_grad=True)
-    gf = dev(rng.normal(size=2000))
-    gr = dev(rng.normal(size=2000))
+    keep = _off_cutoff(pts[idx], R, t, centers, p, 1e-3)  # smooth near the base pose
+    gf = dev(rng.normal(size=2000) * keep)
+    gr = dev(rng.normal(size=2000) * keep)
     f, r = rbf_eval_f_r(ctx, p, grid, R, t, P, W, D)
     L = (gf * f).sum() + (gr * r).sum()
     L.backward()
@@ -147,3 +156,44 @@ def test_autograd_f32_production_vs_oracle(ctx, diff_case):
     assert np.max(err / nrm) <= 1e-3
     assert np.linalg.norm(host(W.grad) - rw) / np.linalg.norm(rw) <= 1e-3
     assert np.linalg.norm(host(D.grad) - rpose) / np.linalg.norm(rpose) <= 1e-3
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e-3, 1e-6])
+def test_eval_at_increment_matches_pose_and_fd(ctx, small, scale):
+    """rbf_eval_at forms R0 Exp(dtheta), t0 + dt on the device: its outputs
+    match the oracle at the pose composed on the host with scipy's rotation
+    vector map, for a large increment and for small ones (the series branch
+    of the exponential map), and the autograd gradient w.r.t. the increment
+    (through the right Jacobian) matches central differences."""
+    from scipy.spatial.transform import Rotation
+    s, p, w, grid, pts, R, t = small
+    d = np.array([0.3, -0.2, 0.5, 0.1, -0.05, 0.02]) * scale
+    Rd = R @ Rotation.from_rotvec(d[:3]).as_matrix()
+    td = t + d[3:]
+    out = ctx.eval_at(p, grid, dev(w), dev(pts), (R, t), dev(d), z_off=0.02)
+    f0, g0, r0, J0 = O.eval_pose(pts, Rd, td, 0.02, s.centers, w, p.sigma, p.cutoff)
+    assert _close(host(out["f"]), f0, 1e-12)
+    assert _close(host(out["resid"]), r0, 1e-12)
+    assert _close(host(out["jac"]), J0, 1e-11)
+    rng = np.random.default_rng(4)
+    # the truncated kernel jumps at the cutoff circle: points within 1 mm
+    # of it (a perturbation of h moves a point by ~1e-5 m) get zero weight,
+    # so that the central differences see a smooth function
+    keep = _off_cutoff(pts, Rd, td, s.centers, p, 1e-3)
+    gf = dev(rng.normal(size=pts.shape[0]) * keep)
+    gr = dev(rng.normal(size=pts.shape[0]) * keep)
+    D = dev(d).requires_grad_(True)
+    f, r = rbf_eval_f_r(ctx, p, grid, R, t, dev(pts), dev(w), D)
+    ((gf * f).sum() + (gr * r).sum()).backward()
+
+    def L(dd):
+        with torch.no_grad():
+            f_, r_ = rbf_eval_f_r(ctx, p, grid, R, t, dev(pts), dev(w), dd)
+            return float((gf * f_).sum() + (gr * r_).sum())
+
+    h = 1e-6
+    for k in range(6):
+        e = torch.zeros(6, dtype=torch.float64, device="cuda")
+        e[k] = h
+        fd = (L(D.detach() + e) - L(D.detach() - e)) / (2 * h)
+        assert fd == pytest.approx(float(D.grad[k]), rel=1e-5, abs=1e-6)

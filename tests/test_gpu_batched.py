@@ -91,3 +91,64 @@ def test_batched_reports_failed_patch(ctx):
     assert torch.equal(A[0]["w"], B[0]["w"])
     plan.close()
     ctx.sync_status()
+
+
+def test_batched_full_size_patches(ctx):
+    """Eight patches of the full 256-patch workload (centers up to 8000, scans
+    up to 40k points): its four costliest (N_p^2 M_p) and four drawn at
+    random, batched on four branches against the sequential plain calls bit
+    for bit, and the largest and one random patch against the oracle's
+    sparse batch ridge solution (weights within 1e-9)."""
+    p = api.Params()
+    _, sizes = synth.patches_case(seed=4, count=256, only=set())
+    cost = np.array([r.centers.shape[0] ** 2 * r.xy.shape[0] for r in sizes])
+    rng = np.random.default_rng(11)
+    top = list(np.argsort(cost)[-4:])
+    rest = [i for i in range(256) if i not in top]
+    sel = sorted(top + list(rng.choice(rest, 4, replace=False)))
+    _, raw = synth.patches_case(seed=4, count=256, only=set(sel))
+    assert max(raw[i].centers.shape[0] for i in sel) > 7000
+    assert max(raw[i].xy.shape[0] for i in sel) > 30000
+
+    def build():
+        out = []
+        for i in sel:
+            r = raw[i]
+            grid = ctx.grid(p, dev(r.centers))
+            N = grid.N
+            xs, zs, _ = ctx.sort_points(grid, dev(r.xy), dev(r.z))
+            pts = torch.cat([xs, zs[:, None]], 1).float().contiguous()
+            Q = pts.shape[0]
+            out.append(dict(
+                grid=grid, raw=r, w=torch.zeros(N, dtype=torch.float64, device="cuda"),
+                P=torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam),
+                xy=xs, z=zs, pts=pts, pose=(np.eye(3), np.zeros(3)),
+                f=torch.empty(Q, dtype=torch.float32, device="cuda"),
+                grad=torch.empty((Q, 2), dtype=torch.float32, device="cuda"),
+                resid=torch.empty(Q, dtype=torch.float32, device="cuda"),
+                jac=torch.empty((Q, 6), dtype=torch.float32, device="cuda"), batch=0))
+        return out
+
+    A = build()
+    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", streams=4,
+                       default_batch=1024)
+    plan.run()
+    assert plan.sync() == -1
+    plan.close()
+    B = build()
+    run_sequential(ctx, p, B, default_batch=1024)
+    for a, b in zip(A, B):
+        for k in ("w", "P", "f", "grad", "resid", "jac"):
+            assert torch.equal(a[k], b[k]), k
+    largest = int(np.argmax([cost[i] for i in sel]))
+    drawn = next(j for j, i in enumerate(sel) if i not in top)
+    for j in (largest, drawn):
+        r = A[j]["raw"]
+        wb, _ = O.ridge_batch(r.xy, r.z, r.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R,
+                              sparse=True, with_P=False)
+        err = np.linalg.norm(host(A[j]["w"]) - wb) / np.linalg.norm(wb)
+        print(f"patch {sel[j]}: N {r.centers.shape[0]}, M {r.xy.shape[0]}, w rel {err:.2e}")
+        assert err <= 1e-9
+    del A, B
+    torch.cuda.empty_cache()
+    ctx.sync_status()

@@ -5,9 +5,10 @@ rbf_assemble_gram, with that P as preconditioner.
 
 Bounds (stated targets of the mixed path): heights within 1e-4 m and height
 gradients within 1e-3 (relative to the largest gradient) of the FP64
-oracle's at the queries. The error of the low-precision recursion before
-refinement, of w and of P are printed for the record. P stays exactly
-symmetric."""
+oracle's at the queries after refinement; P within the rounding bound of
+its low-precision products (_p_bound) of the oracle's R calH^{-1}. The
+error of the recursion before refinement and of w are printed for the
+record. P stays exactly symmetric."""
 import numpy as np
 import pytest
 import torch
@@ -28,6 +29,23 @@ def _errors(q, centers, w, wb, p):
     return ef, eg, ew
 
 
+def _p_bound(prec, B, nb, p):
+    """Entrywise bound on |P - R calH^{-1}| after nb low-precision covariance
+    products of B points each. A product forms sum_k V_ik V_jk with FP32
+    accumulation: FP32 operands (each rounded once, u = 2^-24) err by at
+    most gamma_{B+2} |V_i| |V_j|; split BF16 operands V = V_hi + V_lo + e
+    (|e| <= 2^-16 |V|, the V_lo V_lo^T term dropped, 3B exact products)
+    by (3 2^-16 + gamma_{3B+2}) |V_i| |V_j|. With |V_i|^2 = (V V^T)_ii <=
+    P_ii <= R / lambda, each product adds at most that times R / lambda."""
+    u = 2.0 ** -24
+
+    def gamma(n):
+        return n * u / (1 - n * u)
+
+    per = gamma(B + 2) if prec == "f32" else 3 * 2.0 ** -16 + gamma(3 * B + 2)
+    return nb * per * p.R / p.lam
+
+
 def _refine(ctx, p, grid, xy, z, w, P):
     rowptr, colidx = ctx.gram_pattern(p, grid)
     vals, b = ctx.assemble_gram(p, grid, xy, z, rowptr, colidx)
@@ -46,13 +64,17 @@ def test_mixed_update_heights(ctx, prec, batch):
     ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=batch, gemm_prec=prec)
     assert torch.equal(P, P.T)
     wb, Pb = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R)
-    eP = np.abs(host(P) - Pb).max() / np.abs(Pb).max()
+    eP_abs = np.abs(host(P) - Pb).max()
+    bound = _p_bound(prec, batch, -(-s.xy.shape[0] // batch), p)
+    eP = eP_abs / np.abs(Pb).max()
     ef0, eg0, ew0 = _errors(s.queries, s.centers, host(w), wb, p)
     rel, iters, _ = _refine(ctx, p, grid, dev(s.xy), dev(s.z), w, P)
     ef, eg, ew = _errors(s.queries, s.centers, host(w), wb, p)
-    print(f"{prec} batch {batch}: P rel {eP:.2e}; recursion only: max|df| {ef0:.2e} m, "
+    print(f"{prec} batch {batch}: P max abs err {eP_abs:.2e} (bound {bound:.2e}), rel to "
+          f"max|P| {eP:.2e}; recursion only: max|df| {ef0:.2e} m, "
           f"grad rel {eg0:.2e}, w rel {ew0:.2e}; refined ({iters} CG iterations, relres "
           f"{rel:.1e}): max|df| {ef:.2e} m, grad rel {eg:.2e}, w rel {ew:.2e}")
+    assert eP_abs <= bound
     assert ef <= 1e-4
     assert eg <= 1e-3
 
@@ -154,32 +176,111 @@ def test_mixed_bf16_eight_frames_refined_each_frame(ctx):
     assert info == 0
 
 
-def test_mixed_update_40k_centers_batch_4096(ctx):
+def test_mixed_update_40k_centers_ten_batches_4096(ctx):
     """The 40k-center map (100 x 100 m at 0.5 m, dense P of 12.8 GB) absorbing
-    two batches of 4096 points with FP32 covariance products and FP64
-    Cholesky of S, then FP64 refinement; heights and gradients at 1000
-    sampled queries against the oracle's sparse batch solution."""
+    ten sequential batches of 4096 points with FP32 covariance products and
+    FP64 Cholesky of S. Against the oracle's sparse batch ridge solution:
+    64 sampled columns of P against R calH^{-1} e_j, with the bound of the
+    FP32 products stated below; then, after FP64 refinement of w, heights
+    and gradients at 1000 sampled queries.
+
+    Bound on P: _p_bound (FP32 operands, FP32 accumulation over B = 4096
+    terms per product, ten products), far above the FP64 rounding of the
+    rest of the recursion."""
     case = synth.large_case(3)
     p = api.Params()
     grid = ctx.grid(p, dev(case.centers))
     N = grid.N
     assert N == 40000
-    xy, z = synth.large_points(case, 8192)
+    B, nb = 4096, 10
+    xy, z = synth.large_points(case, B * nb)
     w = torch.zeros(N, dtype=torch.float64, device="cuda")
     P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
     xs, zs, _ = ctx.sort_points(grid, dev(xy), dev(z))
-    assert ctx.update(p, grid, w, P, xs, zs, batch=4096, gemm_prec="f32") == 8192
-    H, b = O.gram(xy, z, case.centers, p.sigma, p.cutoff, 0.0, p.lam, sparse=True)
-    wb = O.spd_solve(H, b)
+    for k in range(nb):  # ten sequential calls of one batch each
+        assert ctx.update(p, grid, w, P, xs[k * B:(k + 1) * B], zs[k * B:(k + 1) * B],
+                          batch=B, gemm_prec="f32") == B
+    xh, zh = host(xs), host(zs)
+    H, b = O.gram(xh, zh, case.centers, p.sigma, p.cutoff, 0.0, p.lam, sparse=True)
     rng = np.random.default_rng(3)
-    q = rng.uniform(xy.min(0), xy.max(0), size=(1000, 2))
+    cols = np.sort(rng.choice(N, 64, replace=False))
+    E = np.zeros((N, 65))
+    E[cols, np.arange(64)] = 1.0
+    E[:, 64] = b
+    X = O.spd_solve(H, E)
+    Pref, wb = p.R * X[:, :64], X[:, 64]
+    Pg = host(P[:, torch.as_tensor(cols, device="cuda")])
+    bound = _p_bound("f32", B, nb, p)
+    eP = np.abs(Pg - Pref).max()
+    eP_rel = np.linalg.norm(Pg - Pref, axis=0) / np.linalg.norm(Pref, axis=0)
+    q = rng.uniform(xh.min(0), xh.max(0), size=(1000, 2))
     ef0, eg0, ew0 = _errors(q, case.centers, host(w), wb, p)
     rel, iters, _ = _refine(ctx, p, grid, xs, zs, w, P)
     ef, eg, ew = _errors(q, case.centers, host(w), wb, p)
     del P
     torch.cuda.empty_cache()
-    print(f"f32 40k centers, batch 4096: recursion only: max|df| {ef0:.2e} m, grad rel "
-          f"{eg0:.2e}; refined ({iters} CG iterations, relres {rel:.1e}): max|df| {ef:.2e} m, "
-          f"grad rel {eg:.2e}, w rel {ew:.2e}")
+    print(f"f32 40k centers, {nb} batches of {B}: P columns max abs err {eP:.2e} (bound "
+          f"{bound:.2e}; max |P| {np.abs(Pref).max():.2e}), column rel err max "
+          f"{eP_rel.max():.2e} median {np.median(eP_rel):.2e}; recursion only: max|df| "
+          f"{ef0:.2e} m, grad rel {eg0:.2e}, w rel {ew0:.2e}; refined ({iters} CG iterations, "
+          f"relres {rel:.1e}): max|df| {ef:.2e} m, grad rel {eg:.2e}, w rel {ew:.2e}")
+    assert eP <= bound
     assert ef <= 1e-4
     assert eg <= 1e-3
+
+
+def test_refine_indefinite_preconditioner_keeps_w(ctx):
+    """With a negative definite preconditioner (P = -I) the first conjugate
+    gradient step finds r.z < 0: no step is written, w keeps the given
+    iterate bit for bit, and the call reports RBF_E_NO_CONVERGE."""
+    s = synth.small_case(0, n_points=600, n_queries=10)
+    p = api.Params()
+    grid = ctx.grid(p, dev(s.centers))
+    N = grid.N
+    rowptr, colidx = ctx.gram_pattern(p, grid)
+    vals, b = ctx.assemble_gram(p, grid, dev(s.xy), dev(s.z), rowptr, colidx)
+    w = torch.linspace(-0.1, 0.1, N, dtype=torch.float64, device="cuda")
+    w0 = w.clone()
+    P = -torch.eye(N, dtype=torch.float64, device="cuda")
+    rel, iters, st = ctx.refine(p, rowptr, colidx, vals, b, P, w, rtol=1e-12, max_iter=10,
+                                check=False)
+    assert st == 5  # RBF_E_NO_CONVERGE
+    assert iters == 1
+    assert torch.equal(w, w0)
+    assert np.isfinite(rel)
+    ctx.sync_status()
+
+
+def test_mixed_f32_joseph_form(ctx):
+    """FP32 products in the Joseph form (gain K formed in FP64, three FP32
+    products into the FP64 P) against the plain FP32 form on the small
+    case: P's error against the oracle is printed for both (the Joseph
+    terms are larger than V V^T and cancel, so its rounding error bound is
+    larger by about sqrt(cond S)); both keep P exactly symmetric and reach
+    the height target after refinement. The Joseph form needs FP32 products
+    on one stream."""
+    s = synth.small_case(0)
+    p = api.Params()
+    grid = ctx.grid(p, dev(s.centers))
+    N = grid.N
+    wb, Pb = O.ridge_batch(s.xy, s.z, s.centers, p.sigma, p.cutoff, 0.0, p.lam, p.R)
+    errs = {}
+    try:
+        for joseph in (False, True):
+            ctx.set_update_joseph(joseph)
+            w = torch.zeros(N, dtype=torch.float64, device="cuda")
+            P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
+            ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=256, gemm_prec="f32")
+            assert torch.equal(P, P.T)
+            errs[joseph] = np.abs(host(P) - Pb).max()
+            rel, iters, _ = _refine(ctx, p, grid, dev(s.xy), dev(s.z), w, P)
+            ef, eg, _ = _errors(s.queries, s.centers, host(w), wb, p)
+            assert ef <= 1e-4 and eg <= 1e-3
+        w = torch.zeros(N, dtype=torch.float64, device="cuda")
+        P = torch.eye(N, dtype=torch.float64, device="cuda") * (p.R / p.lam)
+        with pytest.raises(api.RbfError):
+            ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=256, gemm_prec="bf16")
+    finally:
+        ctx.set_update_joseph(False)
+    print(f"f32 P max abs err vs oracle: plain {errs[False]:.2e}, Joseph {errs[True]:.2e}")
+    assert np.isfinite(errs[True])

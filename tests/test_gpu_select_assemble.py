@@ -131,3 +131,35 @@ def test_sort_points(ctx, case):
     # points of one bin are contiguous: consecutive points are close on average
     step = np.linalg.norm(np.diff(s.xy[pm], axis=0), axis=1)
     assert np.median(step) < 1.5
+
+
+def test_bin_centers_and_assemble_entry_points(ctx):
+    """rbf_bin_centers and rbf_assemble (PHI, GRAM and both in one call) give
+    bit for bit what rbf_grid_create, rbf_assemble_phi and rbf_assemble_gram
+    give on the same inputs, and the regressor rows match the oracle."""
+    s = synth.small_case(0, n_points=1500, n_queries=10)
+    p = api.Params()
+    g1 = ctx.grid(p, dev(s.centers))
+    g2 = ctx.bin_centers(p, dev(s.centers))
+    assert (g1.N, g1.nbx, g1.nby, g1.max_candidates) == (g2.N, g2.nbx, g2.nby,
+                                                          g2.max_candidates)
+    xy, z = dev(s.xy), dev(s.z)
+    v1, c1, n1 = ctx.assemble_phi(p, g1, xy)
+    rowptr, colidx = ctx.gram_pattern(p, g1)
+    hv1, b1 = ctx.assemble_gram(p, g1, xy, z, rowptr, colidx)
+    both = ctx.assemble(p, g2, xy, z, what=("phi", "gram"), H=(rowptr, colidx, None))
+    only_phi = ctx.assemble(p, g2, xy, what=("phi",), prec="f32")
+    only_gram = ctx.assemble(p, g2, xy, z, what=("gram",), H=(rowptr, colidx, None))
+    v2, c2, n2 = both["phi"]
+    assert torch.equal(v1, v2) and torch.equal(c1, c2) and torch.equal(n1, n2)
+    for hv2, b2 in (both["gram"], only_gram["gram"]):
+        assert torch.equal(hv1, hv2) and torch.equal(b1, b2)
+    vf, cf, nf = only_phi["phi"]
+    assert torch.equal(cf, c1) and torch.equal(vf, v1.float())
+    Phi = O.regressor_dense(s.xy, s.centers, p.sigma, p.cutoff, 0.0)
+    rows = np.zeros_like(Phi)
+    vh, ch, nh = host(v2), host(c2), host(n2)
+    for i in range(Phi.shape[0]):
+        rows[i, ch[i, :nh[i]]] = vh[i, :nh[i]]
+    assert np.abs(rows - Phi).max() <= 1e-14
+    ctx.sync_status()

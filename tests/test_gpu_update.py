@@ -207,3 +207,48 @@ def test_update_unsorted_and_sorted_points_large_grid(ctx):
         assert _rel(host(w), wb) <= TOL_W, sort
         assert np.abs(host(P) - Pb).max() <= TOL_W * np.abs(Pb).max(), sort
         assert torch.equal(P, P.T)
+
+
+def test_update_with_pending_error_absorbs_nothing(ctx, small):
+    """A device error left pending by an earlier asynchronous call (here a
+    capacity error of the regressor rows, kmax too small) makes every batch
+    of the next update skip: the synchronous call returns that error, w and
+    P are unchanged, and the following update runs normally."""
+    s, p, grid, wb, Pb = small
+    ctx.sync_status()
+    ctx.assemble_phi(p, grid, dev(s.xy[:50]), kmax=2)  # records RBF_E_CAPACITY
+    w, P = _state(grid.N, p)
+    w0, P0 = w.clone(), P.clone()
+    with pytest.raises(api.RbfError) as e:
+        ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=256)
+    assert e.value.status == 6  # RBF_E_CAPACITY, from the earlier call
+    assert torch.equal(w, w0) and torch.equal(P, P0)
+    assert ctx.update(p, grid, w, P, dev(s.xy), dev(s.z), batch=256) == s.xy.shape[0]
+    assert _rel(host(w), wb) <= TOL_W
+
+
+def test_two_stream_update_refused_under_capture(small):
+    """The two-stream schedule is not captured into graphs: on a capturing
+    stream rbf_update returns RBF_E_INVALID_ARG before enqueuing anything,
+    and (w, P) are untouched; the one-stream schedule is unaffected."""
+    s, p, grid, wb, Pb = small
+    side = torch.cuda.Stream()
+    c2 = api.Context(0, stream=side)
+    c2.set_update_streams(2)
+    w, P = _state(grid.N, p)
+    w0, P0 = w.clone(), P.clone()
+    xy, z = dev(s.xy), dev(s.z)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        with pytest.raises(api.RbfError) as e:
+            c2.update(p, grid, w, P, xy, z, batch=256, sync=False)
+    assert e.value.status == 1  # RBF_E_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.equal(w, w0) and torch.equal(P, P0)
+    c2.set_update_streams(1)
+    with torch.cuda.stream(side):
+        assert c2.update(p, grid, w, P, xy, z, batch=256) == s.xy.shape[0]
+    torch.cuda.synchronize()
+    assert _rel(host(w), wb) <= TOL_W
+    c2.close()
