@@ -421,6 +421,28 @@ rbf_status rbf_eval_adjoint_at(rbf_ctx* ctx, const rbf_params* params, const rbf
                                const void* gbar_f, const void* gbar_r, void* d_pts,
                                double* d_w, double* d_delta);
 
+/* Largest center count (grid N) that rbf_eval_noalloc accepts. */
+#define RBF_EVAL_NOALLOC_MAX_CENTERS 131072
+
+/* rbf_eval for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as rbf_eval (bitwise), but the call
+ * allocates nothing: its packed center table (x, y, w and index per
+ * center, 32 bytes in FP64, 16 in FP32) lives in a device array of the
+ * library of RBF_EVAL_NOALLOC_MAX_CENTERS x 32 bytes (4 MiB), one per GPU,
+ * held until the process ends. The caller still passes the inputs and
+ * outputs. Returns
+ * RBF_E_CAPACITY, before any launch, if the grid holds more than
+ * RBF_EVAL_NOALLOC_MAX_CENTERS centers. Every call on one GPU, from any
+ * context, shares that GPU's array and rewrites the first N entries, so
+ * calls that overlap on one GPU (on different streams, or from several
+ * threads) race and must be ordered by the caller. */
+rbf_status rbf_eval_noalloc(rbf_ctx* ctx, const rbf_params* params,
+                            const rbf_grid* grid, const double* w, const void* pts,
+                            int64_t Q, int32_t dim, const double* pose, double z_off,
+                            rbf_prec prec, void* f, void* grad, void* resid,
+                            void* jac);
+
 /* Gauss-Newton terms of the manifold residual, fused into the evaluation:
  * the Levenberg-Marquardt minimisation of eq. cost_fn (subsection "The
  * Manifold Constraints") takes the manifold term's normal-equation blocks

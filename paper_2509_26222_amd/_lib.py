@@ -83,6 +83,8 @@ SIGNATURES = {
                              C.POINTER(dbl), C.POINTER(i32)]),
     "rbf_eval": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl), dbl,
                            C.c_int, vp, vp, vp, vp]),
+    "rbf_eval_noalloc": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl), dbl,
+                                   C.c_int, vp, vp, vp, vp]),
     "rbf_eval_at": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(dbl), vp, dbl, C.c_int, vp,
                               vp, vp, vp]),
     "rbf_eval_adjoint_at": (C.c_int, [vp, pp, vp, vp, vp, i64, C.POINTER(dbl), vp, C.c_int,

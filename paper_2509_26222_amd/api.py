@@ -444,8 +444,11 @@ class Context:
         return rel.value, it.value, st
 
     def eval(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
-             pose=None, z_off: float = 0.0, grad=True, resid=True, jac=True):
-        """f, grad f and (pose form) residual and Jacobian at the points."""
+             pose=None, z_off: float = 0.0, grad=True, resid=True, jac=True,
+             noalloc: bool = False):
+        """f, grad f and (pose form) residual and Jacobian at the points.
+        noalloc=True calls rbf_eval_noalloc (the library allocates no device
+        memory; the output tensors are still allocated here)."""
         _need(pts, (None, None), "pts")
         Q, dim = pts.shape
         _check_eval(grid, w, pts, pose)
@@ -458,10 +461,11 @@ class Context:
         J = torch.empty((Q, 6), dtype=dt, device=dev) if (jac and dim == 3) else None
         pose_c = _pose(pose)
         pc = params.c()
-        self._check(self.lib.rbf_eval(
+        fn = self.lib.rbf_eval_noalloc if noalloc else self.lib.rbf_eval
+        self._check(fn(
             self.h, C.byref(pc), grid.h, _ptr(w, torch.float64, "w", self.device),
             _ptr(pts, None, "pts", self.device), Q, dim, pose_c, z_off, prec, _ptr(f), _ptr(g),
-            _ptr(r), _ptr(J)), "rbf_eval")
+            _ptr(r), _ptr(J)), "rbf_eval_noalloc" if noalloc else "rbf_eval")
         return {"f": f, "grad": g, "resid": r, "jac": J}
 
     def eval_at(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,

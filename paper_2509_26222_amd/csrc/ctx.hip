@@ -341,6 +341,10 @@ rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream) {
     delete c;
     return RBF_E_HIP;
   }
+  if (eval_scratch_init(device) != RBF_OK) {
+    delete c;
+    return RBF_E_HIP;
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess)
     c->cu_count = cus;

@@ -24,6 +24,7 @@
 // v_exp_f32): per candidate two subtractions, the squared distance, the
 // exponential, the support test and three accumulations.
 #include <cmath>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -815,11 +816,72 @@ static rbf_status pose_at(rbf_ctx* ctx, const double* pose0, const double* delta
   return RBF_OK;
 }
 
+// ---- allocation-free evaluation (rbf_eval_noalloc)
+//
+// The packed center table of rbf_eval_noalloc lives in this device array
+// instead of the context's workspace, so that entry point allocates
+// nothing. Each GPU the library runs on holds its own copy at its own
+// address until the process ends. In host code the array's name is only a
+// host-side stand-in, never a device address: eval_scratch_init looks the
+// device address up once per device (from rbf_ctx_create, with the device
+// current) and kernels receive that pointer.
+static __device__ __align__(256) double4 scratch[RBF_EVAL_NOALLOC_MAX_CENTERS];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+rbf_status eval_scratch_init(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return RBF_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return RBF_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return RBF_E_HIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return RBF_OK;
+}
+
+static void* eval_scratch(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace rbf
 
 using namespace rbf;
 
 extern "C" {
+
+rbf_status rbf_eval_noalloc(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                            const double* w, const void* pts, int64_t Q, int32_t dim,
+                            const double* pose, double z_off, rbf_prec prec, void* f,
+                            void* grad, void* resid, void* jac) {
+  if (!ctx) return RBF_E_INVALID_ARG;
+  RBF_TRY(check_eval_args(ctx, p, g, w, pts, Q, dim, pose, prec, "rbf_eval_noalloc"));
+  RBF_TRY(check_eval_out(ctx, prec, grad, jac, "rbf_eval_noalloc"));
+  if (Q > 0 && !f) return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval_noalloc: f is required");
+  if (dim == 2 && (resid || jac))
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval_noalloc: resid/jac need dim == 3");
+  if (g->N > RBF_EVAL_NOALLOC_MAX_CENTERS)
+    return fail(ctx, RBF_E_CAPACITY,
+                "rbf_eval_noalloc: %lld centers exceed the maximum of %d (use rbf_eval)",
+                (long long)g->N, (int)RBF_EVAL_NOALLOC_MAX_CENTERS);
+  if (Q == 0) return RBF_OK;
+  RBF_TRY(set_device(ctx));
+  void* tab = eval_scratch(ctx->device);
+  if (!tab)
+    return fail(ctx, RBF_E_HIP, "rbf_eval_noalloc: no device address of the scratch table");
+  if (prec == RBF_F64)
+    return eval_direct<double>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac,
+                               (double4*)tab);
+  return eval_direct<float>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac,
+                            (float4*)tab);
+}
 
 rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
                     const void* pts, int64_t Q, int32_t dim, const double* pose, double z_off,

@@ -202,6 +202,10 @@ rbf_status fill_zero(rbf_ctx* ctx, void* p, size_t bytes);
 // batched plan reserves it before capture.
 rbf_status eval_workspace(rbf_ctx* ctx, const rbf_grid* g);
 
+// Look up, once per device (that device current), the device address of
+// the scratch table of rbf_eval_noalloc; called by rbf_ctx_create.
+rbf_status eval_scratch_init(int device);
+
 // Create the context's second stream and its two events if not yet done.
 rbf_status ensure_aux(rbf_ctx* ctx);
 
