@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -445,20 +446,30 @@ class Context:
 
     def eval(self, params: Params, grid: "Grid", w: torch.Tensor, pts: torch.Tensor,
              pose=None, z_off: float = 0.0, grad=True, resid=True, jac=True,
-             noalloc: bool = False):
+             noalloc: bool = False, out: dict | None = None):
         """f, grad f and (pose form) residual and Jacobian at the points.
         noalloc=True calls rbf_eval_noalloc (the library allocates no device
-        memory; the output tensors are still allocated here)."""
+        memory). out: output tensors to write (keys f, grad, resid, jac, as
+        returned), instead of new ones."""
         _need(pts, (None, None), "pts")
         Q, dim = pts.shape
         _check_eval(grid, w, pts, pose)
         prec = _PREC[pts.dtype]
         dt = pts.dtype
         dev = pts.device
-        f = torch.empty(Q, dtype=dt, device=dev)
-        g = torch.empty((Q, 2), dtype=dt, device=dev) if grad else None
-        r = torch.empty(Q, dtype=dt, device=dev) if (resid and dim == 3) else None
-        J = torch.empty((Q, 6), dtype=dt, device=dev) if (jac and dim == 3) else None
+        if out is not None:
+            f, g, r, J = out["f"], out.get("grad"), out.get("resid"), out.get("jac")
+            _need(f, (Q,), "f")
+            _need(g, (Q, 2), "grad")
+            _need(r, (Q,), "resid")
+            _need(J, (Q, 6), "jac")
+            for name, t in (("f", f), ("grad", g), ("resid", r), ("jac", J)):
+                _ptr(t, dt, name, self.device)
+        else:
+            f = torch.empty(Q, dtype=dt, device=dev)
+            g = torch.empty((Q, 2), dtype=dt, device=dev) if grad else None
+            r = torch.empty(Q, dtype=dt, device=dev) if (resid and dim == 3) else None
+            J = torch.empty((Q, 6), dtype=dt, device=dev) if (jac and dim == 3) else None
         pose_c = _pose(pose)
         pc = params.c()
         fn = self.lib.rbf_eval_noalloc if noalloc else self.lib.rbf_eval
@@ -665,8 +676,8 @@ def _pose(pose):
     if pose is None:
         return None
     R, t = pose
-    vals = [float(v) for v in list(torch.as_tensor(R).reshape(-1).tolist())
-            + list(torch.as_tensor(t).reshape(-1).tolist())]
+    vals = [float(v) for v in np.asarray(R, dtype=np.float64).reshape(-1)] + \
+        [float(v) for v in np.asarray(t, dtype=np.float64).reshape(-1)]
     if len(vals) != 12:
         raise ValueError("pose must be (R 3x3, t 3)")
     return (C.c_double * 12)(*vals)
