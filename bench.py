@@ -120,12 +120,12 @@ def batched_leg(ctx, api, synth, n_patches, tune):
         return out
 
     patches = build()
-    streams, batch = 4, 1024
+    tile, batch = "auto", 1024
     table = None
     if tune:
         sample = patches[:: max(1, len(patches) // 16)]
-        (streams, batch), table = T.tune_batched(ctx, p, sample, streams=(1, 2, 4, 8),
-                                                 batches=(512, 1024, 2048), reps=1)
+        (tile, batch), table = T.tune_batched(ctx, p, sample, tiles=("auto", "128", "sub"),
+                                              batches=(512, 1024, 2048), reps=1)
     # sequential plain calls, one patch after another
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -136,7 +136,7 @@ def batched_leg(ctx, api, synth, n_patches, tune):
     t_seq = time.perf_counter() - t0
     ctx.sync_status()
     plan = api.Batched(ctx, p, patches, dim=3, eval_prec="f32", gemm_prec="f64",
-                       streams=streams, default_batch=batch)
+                       tile=tile, default_batch=batch)
     plan.run()  # capture + first run
     plan.sync()
     torch.cuda.synchronize()
@@ -145,11 +145,11 @@ def batched_leg(ctx, api, synth, n_patches, tune):
     plan.sync()
     t_graph = time.perf_counter() - t0
     plan.close()
-    out = {"patches": len(patches), "streams": streams, "batch": batch,
+    out = {"patches": len(patches), "tile": tile, "batch": batch,
            "sequential_s": t_seq, "graph_s": t_graph, "speedup": t_seq / t_graph,
            "update_points": int(sum(q["xy"].shape[0] for q in patches))}
     if table:
-        out["tuning"] = {f"{s}x{b}": round(v, 4) for (s, b), v in table.items()}
+        out["tuning"] = {f"{t}x{b}": round(v, 4) for (t, b), v in table.items()}
     del patches
     torch.cuda.empty_cache()
     return out

@@ -501,27 +501,45 @@ typedef struct {
 
 typedef struct rbf_batched rbf_batched;
 
-/* Plan the recursive update (as rbf_update) followed by the evaluation (as
- * rbf_eval) of n independent patches, to be run as ONE hipGraph launch on
- * the context's stream. The patches are spread over `streams` (1..16)
- * concurrent branches of the graph by longest-processing-time assignment on
- * the cost N_p^2 M_p; each branch has its own workspace, reserved here, so
- * a run allocates nothing. The patch table is copied; the buffers it points
- * to must stay valid while the plan lives. Calls on `ctx` must not run
- * concurrently with the plan's runs. */
+/* Tile shape of the batched covariance products (FP64; the FP32 and BF16
+ * products always use 128x128 tiles). */
+enum {
+  RBF_TILE_AUTO = 0, /* per patch: whole rounds of 128x128 tiles, the rest as
+                        32x64 sub-tiles (the rule of rbf_update)            */
+  RBF_TILE_128 = 1,  /* 128x128 tiles, 8 waves each                         */
+  RBF_TILE_SUB = 2   /* every tile as 32x64 sub-tiles (more, shorter groups) */
+};
+
+/* Plan the recursive update (as rbf_update, eqs. kf_w_update and
+ * H_inverse_update) followed by the evaluation (as rbf_eval) of n
+ * independent patches (n <= 65535), to be run as ONE hipGraph launch. The
+ * patches advance in lockstep over their Kalman batches: round t absorbs
+ * batch t of every patch that has one, and each stage of a round (regressor
+ * rows, U, S, every Cholesky step, the gain, w, the covariance product) is
+ * one kernel launch over all of the round's patches. Each patch gets its own
+ * device workspace, reserved here (about 16 (N_p + 32) B_p + 24 B_p^2 bytes
+ * plus the grouped-gather blocks, B_p its batch rounded up to 64), so a run
+ * allocates nothing. Results equal those of rbf_update and rbf_eval called
+ * on each patch, bit for bit. `tile` is one of RBF_TILE_*; `default_batch`
+ * (0: 1024) is the batch of patches whose own `batch` is 0. The patch table
+ * is copied; the buffers it points to must stay valid while the plan lives.
+ * Calls on `ctx` must not run concurrently with the plan's runs. The Joseph
+ * option of the context does not apply to the plan. */
 rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params,
                             const rbf_patch* patches, int32_t n, int32_t dim,
                             rbf_prec eval_prec, rbf_prec gemm_prec,
-                            int32_t streams, int64_t default_batch,
+                            int32_t tile, int64_t default_batch,
                             double z_off, rbf_batched** out);
-/* Enqueue one run of the plan: the first call captures the graph, later
- * calls relaunch it. Asynchronous. */
+/* Enqueue one run of the plan on the context's stream (ordered after its
+ * earlier work, and before its later work): the first call captures the
+ * graph on the plan's own stream, later calls relaunch it. Asynchronous. */
 rbf_status rbf_batched_run(rbf_batched* b);
 /* Synchronise; return the device error of the last run (RBF_OK if none)
  * and, in *failed_patch (host, may be NULL), the lowest index of a patch
- * whose update failed (-1 if none). A failed patch keeps the state of its
- * last committed batch; the later patches of its branch were skipped and
- * keep their previous state. */
+ * whose update failed (-1 if none). A failed patch keeps the state of the
+ * batch before its failing one (its later batches are skipped, its
+ * evaluation still runs on that state); the other patches are not
+ * affected. */
 rbf_status rbf_batched_sync(rbf_batched* b, int32_t* failed_patch);
 rbf_status rbf_batched_destroy(rbf_batched* b);
 

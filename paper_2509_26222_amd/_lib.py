@@ -18,6 +18,7 @@ STATUS_NAMES = {
 }
 F64, F32, BF16 = 0, 1, 2
 SELECT_RADIUS, SELECT_VOXEL = 0, 1
+RBF_TILE_AUTO, RBF_TILE_128, RBF_TILE_SUB = 0, 1, 2
 
 
 class Params(C.Structure):

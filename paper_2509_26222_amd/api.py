@@ -582,16 +582,23 @@ def _check_eval(grid, w, pts, pose):
     _numel(w, grid.N, "w")
 
 
+_TILE = {"auto": L.RBF_TILE_AUTO, "128": L.RBF_TILE_128, "sub": L.RBF_TILE_SUB}
+
+
 class Batched:
-    """rbf_batched: update + evaluation of many patches as one graph launch.
+    """rbf_batched: update + evaluation of many patches as one graph launch,
+    each stage of the recursion batched across the patches.
 
     Each patch is a dict with keys grid (Grid), w, P, xy, z, pts and, for
     dim 3, pose=(R, t); outputs f (required), grad, resid, jac; optional
-    batch. The tensors are kept alive by this object."""
+    batch. tile: "auto", "128" or "sub" (shape of the FP64 covariance
+    product tiles). The tensors are kept alive by this object."""
 
     def __init__(self, ctx: Context, params: Params, patches: list, dim: int = 3,
-                 eval_prec="f32", gemm_prec="f64", streams: int = 4,
+                 eval_prec="f32", gemm_prec="f64", tile: str = "auto",
                  default_batch: int = 0, z_off: float = 0.0):
+        if tile not in _TILE:
+            raise ValueError(f"tile: one of {sorted(_TILE)}")
         self.ctx = ctx
         self._keep = patches
         arr = (L.Patch * len(patches))()
@@ -623,7 +630,7 @@ class Batched:
         h = C.c_void_p()
         pc = params.c()
         ctx._check(ctx.lib.rbf_batched_plan(ctx.h, C.byref(pc), arr, len(patches), dim,
-                                            _prec(eval_prec), _prec(gemm_prec), streams,
+                                            _prec(eval_prec), _prec(gemm_prec), _TILE[tile],
                                             default_batch, z_off, C.byref(h)),
                    "rbf_batched_plan")
         self.h = h

@@ -61,8 +61,9 @@ __device__ inline bool tile_in_part(const int32_t* __restrict__ flags, int part,
   return part == 1 ? f : !f;
 }
 
-__device__ inline int64_t xcd_tile(int64_t per_xcd) {
-  const int64_t bid = blockIdx.x;
+// Workgroup bid (consecutive workgroups go to the 8 XCDs in turn) takes
+// local tile bid >> 3 of the run of XCD bid & 7.
+__device__ inline int64_t xcd_tile(int64_t bid, int64_t per_xcd) {
   return (bid & 7) * per_xcd + (bid >> 3);
 }
 
@@ -113,16 +114,12 @@ __device__ inline void store_stage(double (*X)[LD], const double2 v[16 * W / 2 /
 // barrier latency of each 16-deep stage.
 constexpr int SYRK_NT = 512;
 
-__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P, int64_t ldp,
-                                                         int64_t N, const double* __restrict__ Ut,
-                                                         int64_t ldu, int32_t K, int64_t T,
-                                                         int64_t per_xcd,
-                                                         const int32_t* __restrict__ flags,
-                                                         int part,
-                                                         const int32_t* __restrict__ status,
-                                                         int64_t seq) {
+__device__ __forceinline__ void syrk_f64_body(double* __restrict__ P, int64_t ldp, int64_t N,
+    const double* __restrict__ Ut, int64_t ldu, int32_t K, int64_t T, int64_t per_xcd,
+    const int32_t* __restrict__ flags, int part, const int32_t* __restrict__ status, int64_t seq,
+    int64_t bid) {
   if (seq_skip(status, seq)) return;
-  const int64_t t = xcd_tile(per_xcd);
+  const int64_t t = xcd_tile(bid, per_xcd);
   if (t >= T) return;
   int I, J;
   tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
@@ -189,6 +186,12 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P,
       }
 }
 
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P, int64_t ldp,
+    int64_t N, const double* __restrict__ Ut, int64_t ldu, int32_t K, int64_t T, int64_t per_xcd,
+    const int32_t* __restrict__ flags, int part, const int32_t* __restrict__ status, int64_t seq) {
+  syrk_f64_body(P, ldp, N, Ut, ldu, K, T, per_xcd, flags, part, status, seq, blockIdx.x);
+}
+
 // Tail of the FP64 product. A launch of 128x128 tiles runs in rounds of
 // (workgroups per CU x CUs per XCD) tiles per XCD; the tiles past the last
 // full round would leave most CUs idle while they finish. They are computed
@@ -204,17 +207,11 @@ constexpr int SUB_N = 64;
 constexpr int SUB_NT = 512;
 constexpr int SUB_PER_TILE = (ST / SUB_M) * (ST / SUB_N);
 
-__global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P, int64_t ldp,
-                                                          int64_t N,
-                                                          const double* __restrict__ Ut,
-                                                          int64_t ldu, int32_t K, int64_t T,
-                                                          int64_t per_xcd, int64_t main_per_xcd,
-                                                          const int32_t* __restrict__ flags,
-                                                          int part,
-                                                          const int32_t* __restrict__ status,
-                                                          int64_t seq) {
+__device__ __forceinline__ void syrk_f64_tail_body(double* __restrict__ P, int64_t ldp, int64_t N,
+    const double* __restrict__ Ut, int64_t ldu, int32_t K, int64_t T, int64_t per_xcd,
+    int64_t main_per_xcd, const int32_t* __restrict__ flags, int part,
+    const int32_t* __restrict__ status, int64_t seq, int64_t bid) {
   if (seq_skip(status, seq)) return;
-  const int64_t bid = blockIdx.x;
   const int64_t local = main_per_xcd + (bid >> 3) / SUB_PER_TILE;
   const int sub = (int)((bid >> 3) % SUB_PER_TILE);
   const int si = sub / (ST / SUB_N), sj = sub % (ST / SUB_N);
@@ -274,6 +271,14 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
   }
 }
 
+__global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P, int64_t ldp,
+    int64_t N, const double* __restrict__ Ut, int64_t ldu, int32_t K, int64_t T, int64_t per_xcd,
+    int64_t main_per_xcd, const int32_t* __restrict__ flags, int part,
+    const int32_t* __restrict__ status, int64_t seq) {
+  syrk_f64_tail_body(P, ldp, N, Ut, ldu, K, T, per_xcd, main_per_xcd, flags, part, status, seq,
+    blockIdx.x);
+}
+
 // Triangular solve of the update as one product: V^T = X U^T with
 // X = L^{-1} (block lower triangular, held transposed in LiT[k][row],
 // leading dimension n, zero above its diagonal blocks) and U^T (n x ncols,
@@ -284,13 +289,9 @@ __global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail(double* __restrict__ P
 // UPPER: X upper triangular instead (the operand holds X transposed all
 // the same), the k-range of row block I starting at its first row.
 template <bool UPPER>
-__global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restrict__ LiT,
-                                                           int32_t n,
-                                                           const double* __restrict__ Ut,
-                                                           int64_t ldu, int64_t ncols,
-                                                           double* __restrict__ Vt, int32_t nJ,
-                                                           const int32_t* __restrict__ status,
-                                                           int64_t seq) {
+__device__ __forceinline__ void linv_apply_body(const double* __restrict__ LiT,
+    int32_t n, const double* __restrict__ Ut, int64_t ldu, int64_t ncols, double* __restrict__ Vt,
+    int32_t nJ, const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int nI = (n + ST - 1) / ST;
   const int I = UPPER ? (int)(blockIdx.x / nJ) : nI - 1 - (int)(blockIdx.x / nJ);
@@ -352,6 +353,13 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restr
       }
 }
 
+template <bool UPPER>
+__global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restrict__ LiT,
+    int32_t n, const double* __restrict__ Ut, int64_t ldu, int64_t ncols, double* __restrict__ Vt,
+    int32_t nJ, const int32_t* __restrict__ status, int64_t seq) {
+  linv_apply_body<UPPER>(LiT, n, Ut, ldu, ncols, Vt, nJ, status, seq);
+}
+
 // ------------------------------------------------ low-precision operands
 //
 // FP32: V^T is rounded to float (same k-major layout) and multiplied on
@@ -367,10 +375,8 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply(const double* __restr
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-__global__ void __launch_bounds__(256) k_cvt_f32(const double* __restrict__ Ut, int64_t ldu,
-                                                 int32_t K, int64_t N, float* __restrict__ Uf,
-                                                 const int32_t* __restrict__ status,
-                                                 int64_t seq) {
+__device__ __forceinline__ void cvt_f32_body(const double* __restrict__ Ut, int64_t ldu, int32_t K,
+    int64_t N, float* __restrict__ Uf, const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)K * ldu) return;
@@ -378,14 +384,16 @@ __global__ void __launch_bounds__(256) k_cvt_f32(const double* __restrict__ Ut, 
   Uf[e] = c < N ? (float)Ut[e] : 0.0f;
 }
 
+__global__ void __launch_bounds__(256) k_cvt_f32(const double* __restrict__ Ut, int64_t ldu,
+    int32_t K, int64_t N, float* __restrict__ Uf, const int32_t* __restrict__ status, int64_t seq) {
+  cvt_f32_body(Ut, ldu, K, N, Uf, status, seq);
+}
+
 // Transposing split: Vhi[n][k], Vlo[n][k] (ld Kp) from U^T[k][n]; 64x64
 // tiles through LDS; k >= K and n >= N are zero.
-__global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ Ut, int64_t ldu,
-                                                    int32_t K, int64_t N, int32_t Kp,
-                                                    __bf16* __restrict__ Vhi,
-                                                    __bf16* __restrict__ Vlo,
-                                                    const int32_t* __restrict__ status,
-                                                    int64_t seq) {
+__device__ __forceinline__ void cvt_bf16x2_body(const double* __restrict__ Ut, int64_t ldu,
+    int32_t K, int64_t N, int32_t Kp, __bf16* __restrict__ Vhi, __bf16* __restrict__ Vlo,
+    const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   __shared__ double t[64][65];
   const int64_t n0 = (int64_t)blockIdx.x * 64;
@@ -407,6 +415,12 @@ __global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ U
       Vlo[gn * Kp + gk] = lo;
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_cvt_bf16x2(const double* __restrict__ Ut, int64_t ldu,
+    int32_t K, int64_t N, int32_t Kp, __bf16* __restrict__ Vhi, __bf16* __restrict__ Vlo,
+    const int32_t* __restrict__ status, int64_t seq) {
+  cvt_bf16x2_body(Ut, ldu, K, N, Kp, Vhi, Vlo, status, seq);
 }
 
 // P -= C (FP32 accumulators) for the 8-wave layout (wave: rows wm*32 +
@@ -522,18 +536,13 @@ __device__ inline void store_stage_f32(float (*X)[FLD], const float4 v[1024 / NT
 
 // P -= sgn X1 X2^T on the lower tiles, mirrored (X2 = X1 unless given:
 // the product is symmetric in every use).
-__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
-                                                     int64_t N, const float* __restrict__ Uf,
-                                                     int64_t ldu, int32_t K, int64_t T,
-                                                     int64_t per_xcd,
-                                                     const int32_t* __restrict__ flags, int part,
-                                                     const int32_t* __restrict__ status,
-                                                     int64_t seq,
-                                                     const float* __restrict__ Uf2 = nullptr,
-                                                     double sgn = 1.0) {
+__device__ __forceinline__ void syrk_f32_body(double* __restrict__ P, int64_t ldp, int64_t N,
+    const float* __restrict__ Uf, int64_t ldu, int32_t K, int64_t T, int64_t per_xcd,
+    const int32_t* __restrict__ flags, int part, const int32_t* __restrict__ status, int64_t seq,
+    const float* __restrict__ Uf2, double sgn, int64_t bid) {
   const float* __restrict__ Ub = Uf2 ? Uf2 : Uf;
   if (seq_skip(status, seq)) return;
-  const int64_t t = xcd_tile(per_xcd);
+  const int64_t t = xcd_tile(bid, per_xcd);
   if (t >= T) return;
   int I, J;
   tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
@@ -584,7 +593,14 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P,
   epilogue_f32acc_w8<false>(P, ldp, N, I0, J0, I == J, acc, sgn);
 }
 
-constexpr int BKC = 64;      // k per stage (two 16x16x32 MFMA steps)
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32(double* __restrict__ P, int64_t ldp,
+    int64_t N, const float* __restrict__ Uf, int64_t ldu, int32_t K, int64_t T, int64_t per_xcd,
+    const int32_t* __restrict__ flags, int part, const int32_t* __restrict__ status, int64_t seq,
+    const float* __restrict__ Uf2 = nullptr, double sgn = 1.0) {
+  syrk_f32_body(P, ldp, N, Uf, ldu, K, T, per_xcd, flags, part, status, seq, Uf2, sgn, blockIdx.x);
+}
+
+constexpr int BKC = SYRK_BF16_KSTEP;  // k per stage (two 16x16x32 MFMA steps)
 constexpr int BLD = BKC + 8; // LDS pitch in bf16 (144 bytes)
 
 // One thread's share of a BF16 stage (8-wave layout: 4 threads per row of
@@ -622,13 +638,12 @@ __device__ __forceinline__ void load_bf16_stage(const __bf16* __restrict__ Vhi,
   }
 }
 
-__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
-    double* __restrict__ P, int64_t ldp, int64_t N, const __bf16* __restrict__ Vhi,
-    const __bf16* __restrict__ Vlo, int32_t Kp, int64_t T, int64_t per_xcd,
-    const int32_t* __restrict__ flags, int part, const int32_t* __restrict__ status,
-    int64_t seq) {
+__device__ __forceinline__ void syrk_bf16x3_body(double* __restrict__ P, int64_t ldp, int64_t N,
+    const __bf16* __restrict__ Vhi, const __bf16* __restrict__ Vlo, int32_t Kp, int64_t T,
+    int64_t per_xcd, const int32_t* __restrict__ flags, int part,
+    const int32_t* __restrict__ status, int64_t seq, int64_t bid) {
   if (seq_skip(status, seq)) return;
-  const int64_t t = xcd_tile(per_xcd);
+  const int64_t t = xcd_tile(bid, per_xcd);
   if (t >= T) return;
   int I, J;
   tile_of_blocked(t, (int)((N + ST - 1) / ST), &I, &J);
@@ -693,19 +708,34 @@ __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(
   epilogue_f32acc_w8<true>(P, ldp, N, I0, J0, I == J, acc);
 }
 
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3(double* __restrict__ P, int64_t ldp,
+    int64_t N, const __bf16* __restrict__ Vhi, const __bf16* __restrict__ Vlo, int32_t Kp,
+    int64_t T, int64_t per_xcd, const int32_t* __restrict__ flags, int part,
+    const int32_t* __restrict__ status, int64_t seq) {
+  syrk_bf16x3_body(P, ldp, N, Vhi, Vlo, Kp, T, per_xcd, flags, part, status, seq, blockIdx.x);
+}
+
+static_assert(SUB_PER_TILE == SYRK_SUB_PER_TILE, "sub-tiles per tile");
+
+void syrk_tiles(int64_t N, int32_t cu_count, int64_t* T, int64_t* per_xcd,
+                int64_t* main_per_xcd) {
+  const int64_t nt = ceil_div(N, ST);
+  *T = nt * (nt + 1) / 2;
+  *per_xcd = ceil_div(*T, 8);
+  // whole rounds of 128x128 tiles per XCD, the rest as 32x64 sub-tiles
+  const int64_t slots = cu_count > 0 ? (int64_t)cu_count / 8 * 2 : 64;
+  *main_per_xcd = slots > 0 ? *per_xcd / slots * slots : *per_xcd;
+}
+
 rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const double* Ut,
                        int64_t ldu, int32_t Bc, rbf_prec prec, const int32_t* flags,
                        int part, int64_t seq) {
   if (part != 0 && !flags) return fail(ctx, RBF_E_INVALID_ARG, "syrk_update: part without flags");
-  const int64_t nt = ceil_div(N, ST);
-  const int64_t T = nt * (nt + 1) / 2;
-  const int64_t per_xcd = ceil_div(T, 8);
+  int64_t T, per_xcd, main_per_xcd;
+  syrk_tiles(N, ctx->cu_count, &T, &per_xcd, &main_per_xcd);
   const unsigned grid = (unsigned)(per_xcd * 8);
   rbf_status st;
   if (prec == RBF_F64) {
-    // whole rounds of 128x128 tiles per XCD, the rest as 64x64 sub-tiles
-    const int64_t slots = ctx->cu_count > 0 ? (int64_t)ctx->cu_count / 8 * 2 : 64;
-    const int64_t main_per_xcd = slots > 0 ? per_xcd / slots * slots : per_xcd;
     prof_begin(ctx, RBF_PROF_SYRK);
     if (main_per_xcd > 0) {
       k_syrk_f64<<<(unsigned)(main_per_xcd * 8), SYRK_NT, 0, ctx->stream>>>(
@@ -751,6 +781,108 @@ rbf_status syrk_update(rbf_ctx* ctx, double* P, int64_t ldp, int64_t N, const do
                                                ctx->d_status, seq);
   RBF_LAUNCHED(ctx, "k_syrk_bf16x3");
   prof_end(ctx, RBF_PROF_SYRK);
+  return RBF_OK;
+}
+
+// ------------------------------------------------ grouped (many patches)
+
+// Covariance products of a round's jobs, each workgroup finding its job
+// from the prefix of per-job workgroup counts (multiples of 8, so a job's
+// local workgroup index keeps the XCD of the global one).
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64_g(const GJob* __restrict__ jobs,
+                                                           const int64_t* __restrict__ pre,
+                                                           int32_t n) {
+  const int64_t b = blockIdx.x;
+  const int32_t j = job_of(pre, n, b);
+  const GJob& J = jobs[j];
+  syrk_f64_body(J.P, J.ldp, J.N, J.Vt, J.ldu, J.Bc, J.T, J.per_xcd, nullptr, 0, J.status,
+                J.seq, b - pre[j]);
+}
+
+__global__ void __launch_bounds__(SUB_NT) k_syrk_f64_tail_g(const GJob* __restrict__ jobs,
+                                                            const int64_t* __restrict__ pre,
+                                                            int32_t n) {
+  const int64_t b = blockIdx.x;
+  const int32_t j = job_of(pre, n, b);
+  const GJob& J = jobs[j];
+  syrk_f64_tail_body(J.P, J.ldp, J.N, J.Vt, J.ldu, J.Bc, J.T, J.per_xcd, J.main_per_xcd,
+                     nullptr, 0, J.status, J.seq, b - pre[j]);
+}
+
+__global__ void __launch_bounds__(256) k_cvt_f32_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  cvt_f32_body(J.Vt, J.ldu, J.Bc, J.N, (float*)J.vlo, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f32_g(const GJob* __restrict__ jobs,
+                                                           const int64_t* __restrict__ pre,
+                                                           int32_t n) {
+  const int64_t b = blockIdx.x;
+  const int32_t j = job_of(pre, n, b);
+  const GJob& J = jobs[j];
+  syrk_f32_body(J.P, J.ldp, J.N, (const float*)J.vlo, J.ldu, J.Bc, J.T, J.per_xcd, nullptr, 0,
+                J.status, J.seq, nullptr, 1.0, b - pre[j]);
+}
+
+__global__ void __launch_bounds__(256) k_cvt_bf16x2_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int64_t)blockIdx.x * 64 >= J.N || (int)blockIdx.y * 64 >= J.Kp) return;
+  __bf16* V = (__bf16*)J.vlo;
+  cvt_bf16x2_body(J.Vt, J.ldu, J.Bc, J.N, J.Kp, V, V + (size_t)J.N * J.Kp, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_bf16x3_g(const GJob* __restrict__ jobs,
+                                                              const int64_t* __restrict__ pre,
+                                                              int32_t n) {
+  const int64_t b = blockIdx.x;
+  const int32_t j = job_of(pre, n, b);
+  const GJob& J = jobs[j];
+  const __bf16* V = (const __bf16*)J.vlo;
+  syrk_bf16x3_body(J.P, J.ldp, J.N, V, V + (size_t)J.N * J.Kp, J.Kp, J.T, J.per_xcd, nullptr,
+                   0, J.status, J.seq, b - pre[j]);
+}
+
+rbf_status syrk_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
+  if (r.n <= 0) return RBF_OK;
+  if (prec == RBF_F64) {
+    if (r.n_main > 0) {
+      k_syrk_f64_g<<<(unsigned)r.n_main, SYRK_NT, 0, ctx->stream>>>(r.jobs, r.pre_main, r.n);
+      RBF_LAUNCHED(ctx, "k_syrk_f64_g");
+    }
+    if (r.n_tail > 0) {
+      k_syrk_f64_tail_g<<<(unsigned)r.n_tail, SUB_NT, 0, ctx->stream>>>(r.jobs, r.pre_tail,
+                                                                        r.n);
+      RBF_LAUNCHED(ctx, "k_syrk_f64_tail_g");
+    }
+    return RBF_OK;
+  }
+  if (prec == RBF_F32) {
+    k_cvt_f32_g<<<dim3((unsigned)r.cvt_x, 1, (unsigned)r.n), 256, 0, ctx->stream>>>(r.jobs);
+    RBF_LAUNCHED(ctx, "k_cvt_f32_g");
+    k_syrk_f32_g<<<(unsigned)r.n_main, SYRK_NT, 0, ctx->stream>>>(r.jobs, r.pre_main, r.n);
+    RBF_LAUNCHED(ctx, "k_syrk_f32_g");
+    return RBF_OK;
+  }
+  k_cvt_bf16x2_g<<<dim3((unsigned)r.cvt_x, (unsigned)r.cvt_y, (unsigned)r.n), 256, 0,
+                   ctx->stream>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_cvt_bf16x2_g");
+  k_syrk_bf16x3_g<<<(unsigned)r.n_main, SYRK_NT, 0, ctx->stream>>>(r.jobs, r.pre_main, r.n);
+  RBF_LAUNCHED(ctx, "k_syrk_bf16x3_g");
+  return RBF_OK;
+}
+
+// Grouped V^T = L^{-1} U^T (one launch over the round's jobs).
+__global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  const int32_t nI = (J.Bp + ST - 1) / ST, nJ = (int32_t)((J.N + 1 + ST - 1) / ST);
+  if ((int32_t)blockIdx.x >= nI * nJ) return;
+  linv_apply_body<false>(J.LiT, J.Bp, J.Ut, J.ldu, J.N + 1, J.Vt, nJ, J.status, J.seq);
+}
+
+rbf_status linv_apply_grouped(rbf_ctx* ctx, const GRound& r) {
+  if (r.n <= 0 || r.la_x <= 0) return RBF_OK;
+  k_linv_apply_g<<<dim3((unsigned)r.la_x, 1, (unsigned)r.n), SYRK_NT, 0, ctx->stream>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_linv_apply_g");
   return RBF_OK;
 }
 

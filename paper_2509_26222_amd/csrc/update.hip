@@ -35,10 +35,9 @@ constexpr int LDT = NB + 1;  // padded LDS row of a 64x64 tile
 // center), else the center's own index. 16 lanes per point test the
 // candidates 16 at a time; a ballot and popcount prefix keep the entries in
 // candidate order (the order of a serial scan), capped at kmax.
-__global__ void __launch_bounds__(256) k_upd_rows(
-    const double* __restrict__ xy, const double* __restrict__ z, int32_t Bc, int32_t Bp,
-    const double* __restrict__ cxy, const int32_t* __restrict__ idx,
-    const int32_t* __restrict__ colmap,
+__device__ __forceinline__ void upd_rows_body(const double* __restrict__ xy,
+    const double* __restrict__ z, int32_t Bc, int32_t Bp, const double* __restrict__ cxy,
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ colmap,
     const int32_t* __restrict__ start, GridGeom g, RegKU k, int32_t kmax,
     const double* __restrict__ w, double* __restrict__ vals, int32_t* __restrict__ cols,
     int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu, int64_t N,
@@ -96,15 +95,25 @@ __global__ void __launch_bounds__(256) k_upd_rows(
   }
 }
 
+__global__ void __launch_bounds__(256) k_upd_rows(const double* __restrict__ xy,
+    const double* __restrict__ z, int32_t Bc, int32_t Bp, const double* __restrict__ cxy,
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ colmap,
+    const int32_t* __restrict__ start, GridGeom g, RegKU k, int32_t kmax,
+    const double* __restrict__ w, double* __restrict__ vals, int32_t* __restrict__ cols,
+    int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu, int64_t N,
+    int32_t* __restrict__ status, int64_t batch, int64_t seq) {
+  upd_rows_body(xy, z, Bc, Bp, cxy, idx, colmap, start, g, k, kmax, w, vals, cols, nnz, Ut, ldu, N,
+    status, batch, seq);
+}
+
 // U^T[b, n] = sum_k vals[b,k] P[cols[b,k], n]  (P symmetric: rows of P).
 // Block: 8 batch rows x 1024 columns; each thread 4 columns. With gR, only
 // the rows of groups the grouped kernels leave (more than
 // GATHER_GROUP_RMAX distinct rows of P).
-__global__ void __launch_bounds__(256) k_upd_gather_u(
-    const double* __restrict__ P, int64_t ldp, int64_t N, int32_t Bc, int32_t Bp,
-    const double* __restrict__ vals, const int32_t* __restrict__ cols,
-    const int32_t* __restrict__ nnz, double* __restrict__ Ut, int64_t ldu,
-    const int32_t* __restrict__ gR, const int32_t* __restrict__ status, int64_t seq) {
+__device__ __forceinline__ void upd_gather_u_body(const double* __restrict__ P, int64_t ldp,
+    int64_t N, int32_t Bc, int32_t Bp, const double* __restrict__ vals,
+    const int32_t* __restrict__ cols, const int32_t* __restrict__ nnz, double* __restrict__ Ut,
+    int64_t ldu, const int32_t* __restrict__ gR, const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t n0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   const int b0 = blockIdx.y * 8;
@@ -132,18 +141,25 @@ __global__ void __launch_bounds__(256) k_upd_gather_u(
   }
 }
 
+__global__ void __launch_bounds__(256) k_upd_gather_u(const double* __restrict__ P, int64_t ldp,
+    int64_t N, int32_t Bc, int32_t Bp, const double* __restrict__ vals,
+    const int32_t* __restrict__ cols, const int32_t* __restrict__ nnz, double* __restrict__ Ut,
+    int64_t ldu, const int32_t* __restrict__ gR, const int32_t* __restrict__ status, int64_t seq) {
+  upd_gather_u_body(P, ldp, N, Bc, Bp, vals, cols, nnz, Ut, ldu, gR, status, seq);
+}
+
 // Grouped gather, step 1 (one workgroup per group of 64 batch rows): the
 // distinct columns of the group's regressor rows (the rows of P it needs)
 // by an LDS bitmap over the N centers, ranked in ascending order by a
 // popcount scan. Writes the list (padded to a multiple of 4 with row 0) and
 // the dense block H_g[rank][row] (zero where a row has no entry).
-constexpr int GG_NT = 1024;  // threads per group of 64 batch rows
+constexpr int GG_NT = GATHER_GROUP_NT;  // threads per group of 64 batch rows
 
-__global__ void __launch_bounds__(GG_NT) k_gather_groups(
-    const double* __restrict__ vals, const int32_t* __restrict__ cols,
-    const int32_t* __restrict__ nnz, int32_t Bc, int32_t Bp, int32_t kmax, int32_t words,
-    int64_t Rcap, int32_t* __restrict__ glist, int32_t* __restrict__ gR,
-    double* __restrict__ gH, const int32_t* __restrict__ status, int64_t seq) {
+__device__ __forceinline__ void gather_groups_body(const double* __restrict__ vals,
+    const int32_t* __restrict__ cols, const int32_t* __restrict__ nnz, int32_t Bc, int32_t Bp,
+    int32_t kmax, int32_t words, int64_t Rcap, int32_t* __restrict__ glist,
+    int32_t* __restrict__ gR, double* __restrict__ gH, const int32_t* __restrict__ status,
+    int64_t seq) {
   if (seq_skip(status, seq)) return;
   extern __shared__ uint32_t gsm[];
   uint32_t* bits = gsm;
@@ -208,14 +224,22 @@ __global__ void __launch_bounds__(GG_NT) k_gather_groups(
   }
 }
 
+__global__ void __launch_bounds__(GG_NT) k_gather_groups(const double* __restrict__ vals,
+    const int32_t* __restrict__ cols, const int32_t* __restrict__ nnz, int32_t Bc, int32_t Bp,
+    int32_t kmax, int32_t words, int64_t Rcap, int32_t* __restrict__ glist,
+    int32_t* __restrict__ gR, double* __restrict__ gH, const int32_t* __restrict__ status,
+    int64_t seq) {
+  gather_groups_body(vals, cols, nnz, Bc, Bp, kmax, words, Rcap, glist, gR, gH, status, seq);
+}
+
 // Grouped gather, step 2: U^T[b0 + i][n] = sum_r H_g[r][i] P[list[r]][n]
 // on FP64 MFMA, one workgroup per (128 columns, group); wave w owns columns
 // 32w..32w+31 and all 64 rows (4 x 2 blocks of 16 x 16). Rows b >= Bc have
 // no entries and get 0.
-__global__ void __launch_bounds__(256) k_gather_mfma(
-    const double* __restrict__ P, int64_t ldp, int64_t N, const int32_t* __restrict__ glist,
-    const int32_t* __restrict__ gR, const double* __restrict__ gH, int64_t Rcap,
-    double* __restrict__ Ut, int64_t ldu, const int32_t* __restrict__ status, int64_t seq) {
+__device__ __forceinline__ void gather_mfma_body(const double* __restrict__ P, int64_t ldp,
+    int64_t N, const int32_t* __restrict__ glist, const int32_t* __restrict__ gR,
+    const double* __restrict__ gH, int64_t Rcap, double* __restrict__ Ut, int64_t ldu,
+    const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = blockIdx.y;
@@ -291,18 +315,21 @@ __global__ void __launch_bounds__(256) k_gather_mfma(
           Ut[(b0 + 16 * mi + 4 * v + kq) * ldu + colv[ni]] = acc[mi][ni][v];
 }
 
+__global__ void __launch_bounds__(256) k_gather_mfma(const double* __restrict__ P, int64_t ldp,
+    int64_t N, const int32_t* __restrict__ glist, const int32_t* __restrict__ gR,
+    const double* __restrict__ gH, int64_t Rcap, double* __restrict__ Ut, int64_t ldu,
+    const int32_t* __restrict__ status, int64_t seq) {
+  gather_mfma_body(P, ldp, N, glist, gR, gH, Rcap, Ut, ldu, status, seq);
+}
+
 // S[a][b] (a >= b) = sum_k vals[a,k] U^T[b, cols[a,k]] + R delta_ab; the
 // padding rows a >= Bc carry the identity. With gR, only the rows a of
 // groups the grouped kernel leaves.
-__global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
-                                               const int32_t* __restrict__ cols,
-                                               const int32_t* __restrict__ nnz,
-                                               const double* __restrict__ Ut, int64_t ldu,
-                                               int32_t Bc, int32_t Bp, double R,
-                                               double* __restrict__ S,
-                                               const int32_t* __restrict__ gR,
-                                               const int32_t* __restrict__ status,
-                                               int64_t seq) {
+__device__ __forceinline__ void upd_S_body(const double* __restrict__ vals,
+    const int32_t* __restrict__ cols, const int32_t* __restrict__ nnz,
+    const double* __restrict__ Ut, int64_t ldu, int32_t Bc, int32_t Bp, double R,
+    double* __restrict__ S, const int32_t* __restrict__ gR, const int32_t* __restrict__ status,
+    int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int b = blockIdx.y;
   const int a = blockIdx.x * 256 + threadIdx.x;
@@ -320,15 +347,22 @@ __global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
   S[(int64_t)a * Bp + b] = s;
 }
 
+__global__ void __launch_bounds__(256) k_upd_S(const double* __restrict__ vals,
+    const int32_t* __restrict__ cols, const int32_t* __restrict__ nnz,
+    const double* __restrict__ Ut, int64_t ldu, int32_t Bc, int32_t Bp, double R,
+    double* __restrict__ S, const int32_t* __restrict__ gR, const int32_t* __restrict__ status,
+    int64_t seq) {
+  upd_S_body(vals, cols, nnz, Ut, ldu, Bc, Bp, R, S, gR, status, seq);
+}
+
 // The same lower triangle of S from the grouped gather's data: workgroup
 // (ga, gb), gb <= ga, computes S[a][b] for the 64 rows a of group ga and the
 // 64 columns b of block gb as sum_r H_ga[r][a] U^T[b][list_ga[r]] on FP64
 // MFMA (wave w: columns 16w..16w+15, all 64 rows).
-__global__ void __launch_bounds__(256) k_upd_S_groups(
-    const int32_t* __restrict__ glist, const int32_t* __restrict__ gR,
-    const double* __restrict__ gH, int64_t Rcap, const double* __restrict__ Ut, int64_t ldu,
-    int32_t Bc, int32_t Bp, double R, double* __restrict__ S,
-    const int32_t* __restrict__ status, int64_t seq) {
+__device__ __forceinline__ void upd_S_groups_body(const int32_t* __restrict__ glist,
+    const int32_t* __restrict__ gR, const double* __restrict__ gH, int64_t Rcap,
+    const double* __restrict__ Ut, int64_t ldu, int32_t Bc, int32_t Bp, double R,
+    double* __restrict__ S, const int32_t* __restrict__ status, int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int t = blockIdx.x;
   int ga = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -388,6 +422,13 @@ __global__ void __launch_bounds__(256) k_upd_S_groups(
         sv = (a == bcol) ? 1.0 : 0.0;
       S[(int64_t)a * Bp + bcol] = sv;
     }
+}
+
+__global__ void __launch_bounds__(256) k_upd_S_groups(const int32_t* __restrict__ glist,
+    const int32_t* __restrict__ gR, const double* __restrict__ gH, int64_t Rcap,
+    const double* __restrict__ Ut, int64_t ldu, int32_t Bc, int32_t Bp, double R,
+    double* __restrict__ S, const int32_t* __restrict__ status, int64_t seq) {
+  upd_S_groups_body(glist, gR, gH, Rcap, Ut, ldu, Bc, Bp, R, S, status, seq);
 }
 
 // ------------------------------------------------------------- 64x64 tiles
@@ -571,24 +612,24 @@ __device__ inline void linv_work(int u, int kb, int32_t Bp, const double* __rest
 }
 
 // The last block row of L^{-1} (kb = nblk - 1), after the final step.
-__global__ void __launch_bounds__(256) k_linv_row(int32_t Bp, int32_t kb,
-                                                  const double* __restrict__ Lb,
-                                                  const double* __restrict__ Linv,
-                                                  double* __restrict__ LiT,
-                                                  const int32_t* __restrict__ status,
-                                                  int64_t seq) {
+__device__ __forceinline__ void linv_row_body(int32_t Bp, int32_t kb, const double* __restrict__ Lb,
+    const double* __restrict__ Linv, double* __restrict__ LiT, const int32_t* __restrict__ status,
+    int64_t seq) {
   if (seq_skip(status, seq)) return;
   __shared__ double T1[NB][LDT], T2[NB][LDT];
   linv_finish(kb, blockIdx.x, Bp, Lb, Linv, LiT, T1, T2);
 }
 
+__global__ void __launch_bounds__(256) k_linv_row(int32_t Bp, int32_t kb,
+    const double* __restrict__ Lb, const double* __restrict__ Linv, double* __restrict__ LiT,
+    const int32_t* __restrict__ status, int64_t seq) {
+  linv_row_body(Bp, kb, Lb, Linv, LiT, status, seq);
+}
+
 // Factor diagonal block 0.
-__global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S, int32_t Bp,
-                                                    double* __restrict__ Lb,
-                                                    double* __restrict__ Linv,
-                                                    double* __restrict__ LiT,
-                                                    int32_t* __restrict__ status, int64_t batch,
-                                                    int64_t seq) {
+__device__ __forceinline__ void chol_first_body(const double* __restrict__ S, int32_t Bp,
+    double* __restrict__ Lb, double* __restrict__ Linv, double* __restrict__ LiT,
+    int32_t* __restrict__ status, int64_t batch, int64_t seq) {
   if (seq_skip(status, seq)) return;
   __shared__ double T[NB][LDT], Ti[NB][LDT];
   load_tile(T, S, Bp);
@@ -597,6 +638,12 @@ __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S
   store_tile(T, Lb, Bp);
   store_tile(Ti, Linv, NB);
   if (LiT) store_tile_t(Ti, LiT, Bp);
+}
+
+__global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S, int32_t Bp,
+    double* __restrict__ Lb, double* __restrict__ Linv, double* __restrict__ LiT,
+    int32_t* __restrict__ status, int64_t batch, int64_t seq) {
+  chol_first_body(S, Bp, Lb, Linv, LiT, status, batch, seq);
 }
 
 // The diagonal workgroup of step kb (the launch's critical path), with Ta =
@@ -668,13 +715,9 @@ __device__ inline void chol_step_diag(const double* __restrict__ S, int32_t Bp, 
 // launch also carries the inverse's work of step kb (linv_work: kb + kb *
 // (nblk - 1 - kb) workgroups of one or two block products), beside the
 // critical path of the factor.
-__global__ void __launch_bounds__(256, 2) k_chol_step(double* __restrict__ S, int32_t Bp,
-                                                   int32_t nblk, int32_t kb,
-                                                   double* __restrict__ Lb,
-                                                   double* __restrict__ Linv,
-                                                   double* __restrict__ LiT,
-                                                   int32_t* __restrict__ status, int64_t batch,
-                                                   int64_t seq) {
+__device__ __forceinline__ void chol_step_body(double* __restrict__ S, int32_t Bp, int32_t nblk,
+    int32_t kb, double* __restrict__ Lb, double* __restrict__ Linv, double* __restrict__ LiT,
+    int32_t* __restrict__ status, int64_t batch, int64_t seq) {
   if (seq_skip(status, seq)) return;
   // two 64x64 tiles of LDS (67 KB) in every role, so a step workgroup fits
   // on a CU beside one covariance-product workgroup
@@ -744,6 +787,12 @@ __global__ void __launch_bounds__(256, 2) k_chol_step(double* __restrict__ S, in
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         Aij[(int64_t)acc_row(mi, v) * Bp + acc_col(ni)] -= U.c[mi][ni][v];
+}
+
+__global__ void __launch_bounds__(256, 2) k_chol_step(double* __restrict__ S, int32_t Bp,
+    int32_t nblk, int32_t kb, double* __restrict__ Lb, double* __restrict__ Linv,
+    double* __restrict__ LiT, int32_t* __restrict__ status, int64_t batch, int64_t seq) {
+  chol_step_body(S, Bp, nblk, kb, Lb, Linv, LiT, status, batch, seq);
 }
 
 // ----------------------------------------------------------------- TRSM
@@ -920,11 +969,9 @@ __global__ void __launch_bounds__(256) k_trsm_blocks(double* __restrict__ Ut, in
 
 // w[n] += sum_b V^T[b, n] t[b], t = V^T[:, N]; stage 1 sums groups of 64
 // rows into part[g][n], stage 2 adds the groups in order (deterministic).
-__global__ void __launch_bounds__(256) k_upd_w_part(const double* __restrict__ Ut, int64_t ldu,
-                                                    int64_t N, int32_t Bc,
-                                                    double* __restrict__ part,
-                                                    const int32_t* __restrict__ status,
-                                                    int64_t seq) {
+__device__ __forceinline__ void upd_w_part_body(const double* __restrict__ Ut, int64_t ldu,
+    int64_t N, int32_t Bc, double* __restrict__ part, const int32_t* __restrict__ status,
+    int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
@@ -940,17 +987,27 @@ __global__ void __launch_bounds__(256) k_upd_w_part(const double* __restrict__ U
   part[(int64_t)blockIdx.y * N + n] = s0 + s1;
 }
 
-__global__ void __launch_bounds__(256) k_upd_w_sum(double* __restrict__ w,
-                                                   const double* __restrict__ part, int64_t N,
-                                                   int32_t ngroups,
-                                                   const int32_t* __restrict__ status,
-                                                   int64_t seq) {
+__global__ void __launch_bounds__(256) k_upd_w_part(const double* __restrict__ Ut, int64_t ldu,
+    int64_t N, int32_t Bc, double* __restrict__ part, const int32_t* __restrict__ status,
+    int64_t seq) {
+  upd_w_part_body(Ut, ldu, N, Bc, part, status, seq);
+}
+
+__device__ __forceinline__ void upd_w_sum_body(double* __restrict__ w,
+    const double* __restrict__ part, int64_t N, int32_t ngroups, const int32_t* __restrict__ status,
+    int64_t seq) {
   if (seq_skip(status, seq)) return;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   double s = 0.0;
   for (int g = 0; g < ngroups; ++g) s += part[(int64_t)g * N + n];
   w[n] += s;
+}
+
+__global__ void __launch_bounds__(256) k_upd_w_sum(double* __restrict__ w,
+    const double* __restrict__ part, int64_t N, int32_t ngroups, const int32_t* __restrict__ status,
+    int64_t seq) {
+  upd_w_sum_body(w, part, N, ngroups, status, seq);
 }
 
 // Touched row blocks of P: flags[c / SYRK_TILE] = 1 for every center c in
@@ -1262,8 +1319,8 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
     const int64_t sq = seq0 + bi;
     prof_begin(ctx, RBF_PROF_GATHER);
     if (ws.gH) {
-      const int32_t words = (int32_t)ceil_div(N, 32);
-      const size_t lds = sizeof(uint32_t) * (2 * (size_t)words + GG_NT / 64);
+      const int32_t words = gather_group_words(N);
+      const size_t lds = gather_group_lds(words);
       k_gather_groups<<<Bpc / 64, GG_NT, lds, ctx->stream>>>(vals, cols, nnz, Bc, Bpc, kmax, words,
                                                            ws.Rcap, ws.glist, ws.gR, ws.gH,
                                                            ctx->d_status, sq);
@@ -1394,6 +1451,134 @@ rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t seq0, int64_t
   }
   *n_done = M;
   return RBF_OK;
+}
+
+// ------------------------------------------------ grouped (many patches)
+//
+// One launch per stage over the round's jobs (blockIdx.z); a job's
+// workgroups beyond its own grid return at once, the others run the body
+// of the single-patch kernel with the job's arguments.
+
+__global__ void __launch_bounds__(256) k_upd_rows_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];  // rows beyond Bp return inside the body
+  upd_rows_body(J.xy, J.z, J.Bc, J.Bp, J.cxy, J.idx, nullptr, J.start, J.g, J.rk, J.kmax, J.w,
+                J.vals, J.cols, J.nnz, J.Ut, J.ldu, J.N, J.status, J.index, J.seq);
+}
+
+__global__ void __launch_bounds__(GG_NT) k_gather_groups_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  if (!J.gH || (int32_t)blockIdx.x >= J.Bp / 64) return;
+  gather_groups_body(J.vals, J.cols, J.nnz, J.Bc, J.Bp, J.kmax, J.words, J.Rcap, J.glist, J.gR,
+                     J.gH, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_gather_mfma_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  if (!J.gH || (int64_t)blockIdx.x * 128 >= J.N || (int32_t)blockIdx.y >= J.Bp / 64) return;
+  gather_mfma_body(J.P, J.ldp, J.N, J.glist, J.gR, J.gH, J.Rcap, J.Ut, J.ldu, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_upd_gather_u_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int64_t)blockIdx.x * 1024 >= J.N || (int32_t)blockIdx.y * 8 >= J.Bp) return;
+  upd_gather_u_body(J.P, J.ldp, J.N, J.Bc, J.Bp, J.vals, J.cols, J.nnz, J.Ut, J.ldu,
+                    J.gH ? J.gR : nullptr, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_upd_S_groups_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  const int32_t ng = J.Bp / 64;
+  if (!J.gH || (int32_t)blockIdx.x >= ng * (ng + 1) / 2) return;
+  upd_S_groups_body(J.glist, J.gR, J.gH, J.Rcap, J.Ut, J.ldu, J.Bc, J.Bp, J.R, J.S,
+                    J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_upd_S_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int32_t)blockIdx.x * 256 >= J.Bp || (int32_t)blockIdx.y >= J.Bp) return;
+  upd_S_body(J.vals, J.cols, J.nnz, J.Ut, J.ldu, J.Bc, J.Bp, J.R, J.S, J.gH ? J.gR : nullptr,
+             J.status, J.seq);
+}
+
+// L^{-1}^T starts at zero in every batch (its blocks accumulate partial sums).
+__global__ void __launch_bounds__(256) k_zero_lit_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  const int64_t n = (int64_t)J.Bp * J.Bp;
+  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+  if (e0 >= n || seq_skip(J.status, J.seq)) return;
+#pragma unroll
+  for (int u = 0; u < 16; u += 2)
+    *reinterpret_cast<double2*>(J.LiT + e0 + u) = make_double2(0.0, 0.0);
+}
+
+__global__ void __launch_bounds__(256) k_chol_first_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  chol_first_body(J.S, J.Bp, J.Lb, J.Linv, J.LiT, J.status, J.index, J.seq);
+}
+
+__global__ void __launch_bounds__(256, 2) k_chol_step_g(const GJob* __restrict__ jobs,
+                                                        int32_t kb) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int32_t)blockIdx.x >= chol_step_groups(J.Bp, kb)) return;
+  chol_step_body(J.S, J.Bp, J.Bp / NB, kb, J.Lb, J.Linv, J.LiT, J.status, J.index, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_linv_row_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  const int32_t nblk = J.Bp / NB;
+  if ((int32_t)blockIdx.x >= nblk - 1) return;
+  linv_row_body(J.Bp, nblk - 1, J.Lb, J.Linv, J.LiT, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_upd_w_part_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int32_t)blockIdx.y * 64 >= J.Bc) return;  // columns beyond N return in the body
+  upd_w_part_body(J.Vt, J.ldu, J.N, J.Bc, J.wpart, J.status, J.seq);
+}
+
+__global__ void __launch_bounds__(256) k_upd_w_sum_g(const GJob* __restrict__ jobs) {
+  const GJob& J = jobs[blockIdx.z];
+  upd_w_sum_body(J.w, J.wpart, J.N, (J.Bc + 63) / 64, J.status, J.seq);
+}
+
+rbf_status update_round_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
+  if (r.n <= 0) return RBF_OK;
+  const unsigned nz = (unsigned)r.n;
+  hipStream_t s = ctx->stream;
+  k_upd_rows_g<<<dim3(r.rows_x, 1, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_upd_rows_g");
+  if (r.gg_x > 0) {
+    k_gather_groups_g<<<dim3(r.gg_x, 1, nz), GG_NT, r.gg_lds, s>>>(r.jobs);
+    RBF_LAUNCHED(ctx, "k_gather_groups_g");
+    k_gather_mfma_g<<<dim3(r.gm_x, r.gm_y, nz), 256, 0, s>>>(r.jobs);
+    RBF_LAUNCHED(ctx, "k_gather_mfma_g");
+  }
+  k_upd_gather_u_g<<<dim3(r.gu_x, r.gu_y, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_upd_gather_u_g");
+  if (r.sg_x > 0) {
+    k_upd_S_groups_g<<<dim3(r.sg_x, 1, nz), 256, 0, s>>>(r.jobs);
+    RBF_LAUNCHED(ctx, "k_upd_S_groups_g");
+  }
+  k_upd_S_g<<<dim3(r.s_x, r.s_y, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_upd_S_g");
+  k_zero_lit_g<<<dim3(r.zero_x, 1, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_zero_lit_g");
+  k_chol_first_g<<<dim3(1, 1, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_chol_first_g");
+  for (int32_t kb = 0; kb < r.nsteps; ++kb) {
+    k_chol_step_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
+    RBF_LAUNCHED(ctx, "k_chol_step_g");
+  }
+  if (r.lr_x > 0) {
+    k_linv_row_g<<<dim3(r.lr_x, 1, nz), 256, 0, s>>>(r.jobs);
+    RBF_LAUNCHED(ctx, "k_linv_row_g");
+  }
+  RBF_TRY(linv_apply_grouped(ctx, r));
+  k_upd_w_part_g<<<dim3(r.wp_x, r.wp_y, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_upd_w_part_g");
+  k_upd_w_sum_g<<<dim3(r.ws_x, 1, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_upd_w_sum_g");
+  return syrk_grouped(ctx, r, prec);
 }
 
 }  // namespace rbf

@@ -75,6 +75,18 @@ struct UpdWs {
   int64_t Rcap;
 };
 
+// Threads of a grouped-gather workgroup (one group of 64 batch rows), and
+// its dynamic LDS for N centers: the bitmap, the word ranks and one count
+// per wave.
+constexpr int GATHER_GROUP_NT = 1024;
+inline int32_t gather_group_words(int64_t N) { return (int32_t)((N + 31) / 32); }
+inline size_t gather_group_lds(int32_t words) {
+  return sizeof(uint32_t) * (2 * (size_t)words + GATHER_GROUP_NT / 64);
+}
+
+// k extent step of the BF16 operands (their k extent is Bc rounded up to it).
+constexpr int SYRK_BF16_KSTEP = 64;
+
 // Largest N for the grouped gather (its LDS bitmap has one bit per center).
 constexpr int64_t GATHER_GROUP_NMAX = (int64_t)1 << 17;
 
@@ -132,5 +144,108 @@ rbf_status update_run(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
 // returned and cleared). seq0 is the launch group of the call's first
 // batch; an error recorded before it leaves n_done = 0.
 rbf_status update_done(rbf_ctx* ctx, int64_t M, int64_t B, int64_t seq0, int64_t* n_done);
+
+// ------------------------------------------------ grouped (many patches)
+//
+// The batched form runs the recursion of many independent patches in
+// lockstep: round t absorbs batch t of every patch that has one, and each
+// stage of the round (regressor rows, U, S, Cholesky steps, V, w, the
+// covariance product) is ONE launch over all of the round's jobs. A job is
+// one patch's batch; its workgroups take it from blockIdx.z (the grid is the
+// largest job's, the others' surplus workgroups return at once) or, for the
+// covariance products, from a prefix of per-job workgroup counts. Each job
+// runs the same bodies, with the same arguments, as the single-patch
+// launches, so a patch's results are the same bit for bit.
+struct GJob {
+  double* P;  // patch state
+  int64_t ldp, N;
+  double* w;
+  const double* xy;  // this batch's points and heights
+  const double* z;
+  const double* cxy;  // the patch's center grid
+  const int32_t* idx;
+  const int32_t* start;
+  GridGeom g;
+  RegKU rk;
+  double R;  // noise variance of the heights
+  int32_t kmax;
+  int32_t Bc, Bp;  // points of the batch, and padded to a multiple of 64
+  int64_t index;   // status index (patch << 32) + batch
+  int64_t seq;     // launch group (batch + 1) of the patch's status words
+  int32_t* status;
+  double* vals;  // workspace of the patch (as UpdWs)
+  int32_t* cols;
+  int32_t* nnz;
+  double* Ut;
+  int64_t ldu;
+  double* S;
+  double* Lb;
+  double* LiT;
+  double* Linv;
+  double* Vt;
+  double* wpart;
+  int32_t* glist;  // null: no grouped gather for this patch
+  int32_t* gR;
+  double* gH;
+  int64_t Rcap;
+  int32_t words;   // 32-bit words of the grouped gather's bitmap
+  int32_t Kp;      // k extent of the BF16 operands
+  void* vlo;       // low-precision copy of V^T (FP32 / BF16 products)
+  int64_t T, per_xcd, main_per_xcd;  // covariance product: tiles, per XCD,
+                                     // of which as 128x128 tiles
+};
+
+// Launch shapes of one round (largest job per stage, grouped covariance
+// product prefixes), computed on the host from the round's jobs.
+struct GRound {
+  const GJob* jobs;  // device array of the round's jobs
+  int32_t n;
+  int32_t rows_x, gg_x, gm_x, gm_y, gu_x, gu_y, sg_x, s_x, s_y, zero_x;
+  size_t gg_lds;
+  int32_t nsteps;                 // Cholesky step launches (largest nblk - 1)
+  const int32_t* step_x;          // host: workgroups of step kb, kb < nsteps
+  int32_t lr_x, la_x, wp_x, wp_y, ws_x, cvt_x, cvt_y;
+  const int64_t* pre_main;        // device: prefix of 128x128-tile workgroups
+  const int64_t* pre_tail;        // device: prefix of sub-tile workgroups
+  int64_t n_main, n_tail;         // total workgroups of each
+};
+
+// Workgroups of Cholesky step kb for a batch of Bp rows (0: no such step).
+__host__ __device__ inline int32_t chol_step_groups(int32_t Bp, int32_t kb) {
+  const int32_t nblk = Bp / 64, m = nblk - kb - 1;
+  if (m <= 0) return 0;
+  return m + m * (m + 1) / 2 + kb + kb * (nblk - 1 - kb);
+}
+
+// Job of workgroup b of a prefix-mapped launch: the last j with pre[j] <= b
+// (jobs without workgroups have pre[j] == pre[j + 1] and are passed over).
+// The search is uniform across the workgroup.
+__device__ inline int32_t job_of(const int64_t* __restrict__ pre, int32_t n, int64_t b) {
+  int32_t lo = 0, hi = n;  // pre[lo] <= b < pre[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Enqueue round r on the context's stream: every stage of the recursion
+// for all of its jobs, covariance product (prec) included.
+rbf_status update_round_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec);
+
+// The covariance products of a round, and its V^T = L^{-1} U^T (syrk.hip).
+rbf_status syrk_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec);
+rbf_status linv_apply_grouped(rbf_ctx* ctx, const GRound& r);
+
+// Covariance product tiles of N rows: T lower 128x128 tiles, per_xcd of
+// them per XCD, main_per_xcd of those computed whole and the rest as
+// 32x64 sub-tiles (the single-call rule: whole rounds of two workgroups per
+// CU as 128x128 tiles).
+void syrk_tiles(int64_t N, int32_t cu_count, int64_t* T, int64_t* per_xcd,
+                int64_t* main_per_xcd);
+constexpr int SYRK_SUB_PER_TILE = 8;
 
 }  // namespace rbf

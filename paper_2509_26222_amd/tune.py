@@ -1,10 +1,11 @@
 """Autotuner of the batched form.
 
-Chooses the number of concurrent graph branches and the Kalman batch size
-(the K extent of the covariance products P -= V V^T and of the Cholesky of
-S) by timing graph replays of a plan over a sample of the patches. The cost
-of a run does not depend on the values in (w, P), so replays that keep
-updating the sample's state time the same work.
+Chooses the tile shape of the FP64 covariance products ("auto", "128" or
+"sub") and the Kalman batch (the K extent of the covariance products and
+the size of S, whose Cholesky is the latency-bound stage) by timing graph
+replays of a plan over a sample of the patches. The cost of a run does not
+depend on the values in (w, P), so replays that keep updating the sample's
+state time the same work.
 """
 from __future__ import annotations
 
@@ -16,12 +17,12 @@ import torch
 from . import api
 
 
-def time_plan(ctx: api.Context, params: api.Params, patches: list, streams: int,
+def time_plan(ctx: api.Context, params: api.Params, patches: list, tile: str,
               batch: int, reps: int = 2, **kw) -> float:
     """Seconds per graph replay of one plan (after the capturing run)."""
     for q in patches:
         q["batch"] = 0
-    plan = api.Batched(ctx, params, patches, streams=streams, default_batch=batch, **kw)
+    plan = api.Batched(ctx, params, patches, tile=tile, default_batch=batch, **kw)
     try:
         plan.run()  # capture + first run
         plan.sync()
@@ -36,10 +37,11 @@ def time_plan(ctx: api.Context, params: api.Params, patches: list, streams: int,
 
 
 def tune_batched(ctx: api.Context, params: api.Params, sample: list,
-                 streams=(1, 2, 4, 8), batches=(512, 1024, 2048), reps: int = 2, **kw):
-    """Return ((streams, batch), {(streams, batch): seconds}) over the grid."""
+                 tiles=("auto", "128", "sub"), batches=(512, 1024, 2048), reps: int = 2,
+                 **kw):
+    """Return ((tile, batch), {(tile, batch): seconds}) over the grid."""
     table = {}
-    for s, b in itertools.product(streams, batches):
-        table[(s, b)] = time_plan(ctx, params, sample, s, b, reps=reps, **kw)
+    for t, b in itertools.product(tiles, batches):
+        table[(t, b)] = time_plan(ctx, params, sample, t, b, reps=reps, **kw)
     best = min(table, key=table.get)
     return best, table

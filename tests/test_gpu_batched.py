@@ -1,6 +1,8 @@
 """Batched form: many patches of uneven size updated and evaluated by one
-hipGraph launch. The kernels are deterministic (no atomics on this path), so
-the batched results must equal the sequential plain calls bit for bit; the
+hipGraph launch, each stage of the recursion one launch over all patches.
+The kernels are deterministic (no atomics on this path) and every patch runs
+the same kernel bodies on the same arguments as a plain call, so the
+batched results must equal the sequential plain calls bit for bit; the
 plain calls are themselves parity-tested against the oracle, and two
 patches are also checked directly against the oracle here."""
 import numpy as np
@@ -50,12 +52,12 @@ def run_sequential(ctx, p, patches, gemm_prec="f64", default_batch=1024):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("streams", [1, 4])
-def test_batched_equals_sequential(ctx, streams):
+@pytest.mark.parametrize("tile", ["auto", "128", "sub"])
+def test_batched_equals_sequential(ctx, tile):
     p = api.Params()
     A = make_patches(ctx, p, 12)
     B = make_patches(ctx, p, 12)
-    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", streams=streams)
+    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", tile=tile)
     for rep in range(2):  # capture, then replay on the updated state
         plan.run()
         assert plan.sync() == -1
@@ -66,7 +68,7 @@ def test_batched_equals_sequential(ctx, streams):
     plan.close()
     # direct oracle check of two patches after the first run's state: redo one run
     C = make_patches(ctx, p, 12)
-    plan = api.Batched(ctx, p, C, dim=3, eval_prec="f32", gemm_prec="f64", streams=streams)
+    plan = api.Batched(ctx, p, C, dim=3, eval_prec="f32", gemm_prec="f64", tile=tile)
     plan.run()
     plan.sync()
     for q in (C[0], C[7]):
@@ -77,18 +79,44 @@ def test_batched_equals_sequential(ctx, streams):
     plan.close()
 
 
+@pytest.mark.parametrize("gemm_prec", ["f32", "bf16"])
+def test_batched_mixed_products_equal_sequential(ctx, gemm_prec):
+    """The FP32 and split-BF16 covariance products, batched across patches,
+    against the plain calls with the same products (bit for bit)."""
+    p = api.Params()
+    A = make_patches(ctx, p, 10, seed=6)
+    B = make_patches(ctx, p, 10, seed=6)
+    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec=gemm_prec)
+    plan.run()
+    assert plan.sync() == -1
+    plan.close()
+    run_sequential(ctx, p, B, gemm_prec=gemm_prec)
+    for a, b in zip(A, B):
+        for k in ("w", "P", "f", "grad", "resid", "jac"):
+            assert torch.equal(a[k], b[k]), k
+
+
 def test_batched_reports_failed_patch(ctx):
+    """A non-finite height in patch 5 stops patch 5 at its failing batch;
+    every other patch completes as its plain calls do."""
     p = api.Params()
     A = make_patches(ctx, p, 8, nan_patch=5)
-    plan = api.Batched(ctx, p, A, dim=3, streams=8)
+    plan = api.Batched(ctx, p, A, dim=3)
     plan.run()
     with pytest.raises(api.RbfError) as e:
         plan.sync()
     assert e.value.status == 4 and e.value.index == 5
-    # patches on other branches completed
     B = make_patches(ctx, p, 8, nan_patch=5)
-    run_sequential(ctx, p, [B[0]])
-    assert torch.equal(A[0]["w"], B[0]["w"])
+    run_sequential(ctx, p, [q for i, q in enumerate(B) if i != 5])
+    for i in range(8):
+        if i != 5:
+            assert torch.equal(A[i]["w"], B[i]["w"]) and torch.equal(A[i]["P"], B[i]["P"]), i
+    # the failed patch kept the state of the batches before the failing one
+    q = B[5]
+    M = q["xy"].shape[0]
+    bad = (M // 2) // 512 * 512  # batch 512 (odd index): start of the failing batch
+    ctx.update(p, q["grid"], q["w"], q["P"], q["xy"][:bad], q["z"][:bad], batch=512)
+    assert torch.equal(A[5]["w"], q["w"]) and torch.equal(A[5]["P"], q["P"])
     plan.close()
     ctx.sync_status()
 
@@ -96,8 +124,7 @@ def test_batched_reports_failed_patch(ctx):
 def test_batched_full_size_patches(ctx):
     """Eight patches of the full 256-patch workload (centers up to 8000, scans
     up to 40k points): its four costliest (N_p^2 M_p) and four drawn at
-    random, batched on four branches against the sequential plain calls bit
-    for bit, and the largest and one random patch against the oracle's
+    random, batched against the sequential plain calls bit for bit, and the largest and one random patch against the oracle's
     sparse batch ridge solution (weights within 1e-9)."""
     p = api.Params()
     _, sizes = synth.patches_case(seed=4, count=256, only=set())
@@ -130,7 +157,7 @@ def test_batched_full_size_patches(ctx):
         return out
 
     A = build()
-    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", streams=4,
+    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", tile="auto",
                        default_batch=1024)
     plan.run()
     assert plan.sync() == -1
