@@ -88,7 +88,7 @@ def copy_calibrate(mib):
                       "launches": 5}), flush=True)
 
 
-def batched_leg(ctx, api, synth, n_patches, tune):
+def batched_leg(ctx, api, synth, n_patches, tune, chains=2, tile="128", batch=1024):
     """Many uneven patches: one hipGraph launch of the batched plan vs the
     same update + evaluation calls issued one patch after another."""
     import torch
@@ -120,12 +120,12 @@ def batched_leg(ctx, api, synth, n_patches, tune):
         return out
 
     patches = build()
-    tile, batch = "auto", 1024
     table = None
     if tune:
         sample = patches[:: max(1, len(patches) // 16)]
-        (tile, batch), table = T.tune_batched(ctx, p, sample, tiles=("auto", "128", "sub"),
-                                              batches=(512, 1024, 2048), reps=1)
+        (chains, tile, batch), table = T.tune_batched(
+            ctx, p, sample, chains=(1, 2, 4), tiles=("auto", "128", "sub"),
+            batches=(512, 1024, 2048), reps=1)
     # sequential plain calls, one patch after another
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -136,7 +136,7 @@ def batched_leg(ctx, api, synth, n_patches, tune):
     t_seq = time.perf_counter() - t0
     ctx.sync_status()
     plan = api.Batched(ctx, p, patches, dim=3, eval_prec="f32", gemm_prec="f64",
-                       tile=tile, default_batch=batch)
+                       tile=tile, chains=chains, default_batch=batch)
     plan.run()  # capture + first run
     plan.sync()
     torch.cuda.synchronize()
@@ -145,11 +145,11 @@ def batched_leg(ctx, api, synth, n_patches, tune):
     plan.sync()
     t_graph = time.perf_counter() - t0
     plan.close()
-    out = {"patches": len(patches), "tile": tile, "batch": batch,
+    out = {"patches": len(patches), "chains": chains, "tile": tile, "batch": batch,
            "sequential_s": t_seq, "graph_s": t_graph, "speedup": t_seq / t_graph,
            "update_points": int(sum(q["xy"].shape[0] for q in patches))}
     if table:
-        out["tuning"] = {f"{t}x{b}": round(v, 4) for (t, b), v in table.items()}
+        out["tuning"] = {f"{c}x{t}x{b}": round(v, 4) for (c, t, b), v in table.items()}
     del patches
     torch.cuda.empty_cache()
     return out
@@ -224,7 +224,23 @@ def rows_leg(ctx, api, synth, L, od, allxy, centers, grid, frame, w, p, reps=3):
 
     t = timed(solve)
     out["a9_solve_40k"] = {"ms": t * 1e3, "centers": g40.N, "relres": res["rel"],
-                           "refine_sweeps": res["it"], "inner": "f64"}
+                           "refine_sweeps": res["it"], "inner": "f64", "method": "banded"}
+    # the same solve by nested dissection: the pattern analysed once (host),
+    # then factor + solves + refinement per call
+    t0 = time.perf_counter()
+    plan = ctx.solve_plan(rp, ci)
+    t_plan = time.perf_counter() - t0
+    for inner in ("f64",):
+        def solve_nd():
+            x, rel, it, st = plan.run(vals, b, rtol=1e-10, max_iter=20, inner=inner)
+            res.update(rel=rel[0], it=it)
+
+        t = timed(solve_nd)
+        out[f"a9_solve_40k_nd_{inner}"] = {
+            "ms": t * 1e3, "centers": g40.N, "relres": res["rel"], "refine_sweeps": res["it"],
+            "inner": inner, "method": "nested dissection", "plan_ms": t_plan * 1e3,
+            **plan.info()}
+    plan.close()
     g40.close()
     return out
 

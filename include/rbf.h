@@ -340,6 +340,53 @@ rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
                      int64_t nrhs, double rtol, int32_t max_iter,
                      rbf_prec inner, double* relres, int32_t* iters);
 
+/* The same solve for repeated use on one sparsity pattern (the Gram
+ * pattern of a center set), by nested dissection with dense frontal
+ * matrices. rbf_solve_plan_create copies the pattern (rowptr N+1 int64,
+ * colidx int32, device, both triangles) to the host once and analyses it:
+ * each set of unknowns is cut by the level of a breadth-first search from a
+ * pseudo-peripheral unknown (disconnected sets by their components) until
+ * at most `leaf` unknowns remain (0: 512); the tree is numbered in
+ * postorder. It reserves the fronts' device memory (rbf_solve_plan_info:
+ * front_bytes) and synchronises; the plan keeps the device pattern
+ * pointers, which must stay valid and unchanged while it lives.
+ * rbf_solve_plan_run factors calH (vals, nnz f64, device) front height by
+ * front height from the leaves up, every front of a height in one launch
+ * per stage: assembly from calH and the children's update matrices, the
+ * blocked FP64 Cholesky of the front's own block, the gain on FP64 MFMA and
+ * the update matrix by the FP64 covariance product; then solves and refines
+ * in FP64 as rbf_solve (same arguments, nrhs <= 65535, same return codes;
+ * inner must be RBF_F64: with FP32 products in the update matrices the
+ * refinement of the 40k-center map stalls near relres 1e-3; a factor
+ * breakdown returns RBF_E_NOT_SPD with the front's node as index).
+ * The run synchronises; runs on one plan must not overlap. */
+typedef struct rbf_solve_plan rbf_solve_plan;
+rbf_status rbf_solve_plan_create(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
+                                 const int32_t* colidx, int32_t leaf,
+                                 rbf_solve_plan** out);
+rbf_status rbf_solve_plan_run(rbf_solve_plan* plan, const double* vals,
+                              const double* B, int64_t ldb, double* X,
+                              int64_t ldx, int64_t nrhs, double rtol,
+                              int32_t max_iter, rbf_prec inner,
+                              double* relres, int32_t* iters);
+/* nodes of the dissection tree, front heights, bytes of the fronts and
+ * factors, and the largest front (kp + m); any pointer may be NULL. */
+rbf_status rbf_solve_plan_info(const rbf_solve_plan* plan, int32_t* nodes,
+                               int32_t* levels, int64_t* front_bytes,
+                               int32_t* max_front);
+rbf_status rbf_solve_plan_destroy(rbf_solve_plan* plan);
+
+/* The dissection alone, on HOST arrays (no device, no context): new2old
+ * (N int32) receives the elimination order, node_of (N int32) the tree
+ * node of each unknown, parent (cap int32) the parent of each node (-1: the
+ * root); *n_nodes the node count (RBF_E_CAPACITY if above cap). For
+ * checks of the ordering. */
+rbf_status rbf_solve_order_host(int64_t N, const int64_t* rowptr,
+                                const int32_t* colidx, int32_t leaf,
+                                int32_t* new2old, int32_t* node_of,
+                                int32_t* parent, int32_t cap,
+                                int32_t* n_nodes);
+
 /* FP64 iterative refinement of the weights of the recursive update against
  * the information form of the ridge estimator (subsection "The RBF Weight
  * Estimate by Ridge Regression", eqs. RBF_estimator, H_update and
@@ -520,7 +567,11 @@ enum {
  * device workspace, reserved here (about 16 (N_p + 32) B_p + 24 B_p^2 bytes
  * plus the grouped-gather blocks, B_p its batch rounded up to 64), so a run
  * allocates nothing. Results equal those of rbf_update and rbf_eval called
- * on each patch, bit for bit. `tile` is one of RBF_TILE_*; `default_batch`
+ * on each patch, bit for bit. The patches are split into `chains` (1..4)
+ * sets of about equal cost (longest processing time first on N_p^2 M_p);
+ * each set advances through its own rounds on its own stream of the graph,
+ * so the latency-bound stages of one set run beside the covariance
+ * products of another. `tile` is one of RBF_TILE_*; `default_batch`
  * (0: 1024) is the batch of patches whose own `batch` is 0. The patch table
  * is copied; the buffers it points to must stay valid while the plan lives.
  * Calls on `ctx` must not run concurrently with the plan's runs. The Joseph
@@ -528,8 +579,9 @@ enum {
 rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params,
                             const rbf_patch* patches, int32_t n, int32_t dim,
                             rbf_prec eval_prec, rbf_prec gemm_prec,
-                            int32_t tile, int64_t default_batch,
-                            double z_off, rbf_batched** out);
+                            int32_t tile, int32_t chains,
+                            int64_t default_batch, double z_off,
+                            rbf_batched** out);
 /* Enqueue one run of the plan on the context's stream (ordered after its
  * earlier work, and before its later work): the first call captures the
  * graph on the plan's own stream, later calls relaunch it. Asynchronous. */

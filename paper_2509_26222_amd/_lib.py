@@ -80,6 +80,13 @@ SIGNATURES = {
                                     vp, C.POINTER(i64), C.POINTER(i64)]),
     "rbf_solve": (C.c_int, [vp, i64, vp, vp, vp, vp, i64, vp, i64, i64, dbl, i32,
                             C.c_int, C.POINTER(dbl), C.POINTER(i32)]),
+    "rbf_solve_plan_create": (C.c_int, [vp, i64, vp, vp, i32, C.POINTER(vp)]),
+    "rbf_solve_plan_run": (C.c_int, [vp, vp, vp, i64, vp, i64, i64, dbl, i32, C.c_int,
+                                     C.POINTER(dbl), C.POINTER(i32)]),
+    "rbf_solve_plan_info": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64),
+                                      C.POINTER(i32)]),
+    "rbf_solve_plan_destroy": (C.c_int, [vp]),
+    "rbf_solve_order_host": (C.c_int, [i64, vp, vp, i32, vp, vp, vp, i32, C.POINTER(i32)]),
     "rbf_refine": (C.c_int, [vp, i64, vp, vp, vp, vp, vp, i64, dbl, vp, dbl, i32,
                              C.POINTER(dbl), C.POINTER(i32)]),
     "rbf_eval": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl), dbl,
@@ -94,8 +101,8 @@ SIGNATURES = {
                               vp]),
     "rbf_eval_adjoint": (C.c_int, [vp, pp, vp, vp, vp, i64, i32, C.POINTER(dbl),
                                    C.c_int, vp, vp, vp, vp, vp]),
-    "rbf_batched_plan": (C.c_int, [vp, pp, vp, i32, i32, C.c_int, C.c_int, i32, i64,
-                                   dbl, C.POINTER(vp)]),
+    "rbf_batched_plan": (C.c_int, [vp, pp, vp, i32, i32, C.c_int, C.c_int, i32, i32,
+                                   i64, dbl, C.POINTER(vp)]),
     "rbf_batched_run": (C.c_int, [vp]),
     "rbf_batched_sync": (C.c_int, [vp, C.POINTER(i32)]),
     "rbf_batched_destroy": (C.c_int, [vp]),

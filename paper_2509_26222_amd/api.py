@@ -7,7 +7,10 @@ the stream the context enqueues on.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -21,6 +24,29 @@ class RbfError(RuntimeError):
         super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
         self.index = index
+
+
+# Objects holding a library handle. Their handles are released at exit
+# while the HIP runtime is still up (plans and grids before contexts):
+# released from a finaliser during interpreter shutdown (an object still
+# referenced from a traceback, say), the runtime's calls abort the process.
+_LIVE = weakref.WeakSet()
+
+
+def _close_all():
+    for o in sorted(list(_LIVE), key=lambda o: o._close_rank):
+        try:
+            o.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
+
+
+def _track(obj, rank: int):
+    obj._close_rank = rank
+    _LIVE.add(obj)
 
 
 @dataclass
@@ -119,6 +145,7 @@ class Context:
         self._check(self.lib.rbf_ctx_create(C.byref(h), device, C.c_void_p(s.cuda_stream)),
                     "rbf_ctx_create", ctx=False)
         self.h = h
+        _track(self, 2)
 
     def _check(self, st: int, what: str, ctx: bool = True):
         if st != L.RBF_OK:
@@ -159,7 +186,9 @@ class Context:
             self.lib.rbf_ctx_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalising=sys.is_finalizing):
+        if _finalising():  # bound at definition: module globals are gone by then
+            return
         try:
             self.close()
         except Exception:
@@ -407,6 +436,12 @@ class Context:
         out = X if B.dim() == 2 else X.view(-1)
         return out, relres, it.value, st
 
+    def solve_plan(self, rowptr, colidx, leaf: int = 0) -> "SolvePlan":
+        """rbf_solve_plan_create: nested-dissection plan for repeated solves
+        on the pattern (rowptr, colidx); keep both tensors alive and
+        unchanged while the plan lives."""
+        return SolvePlan(self, rowptr, colidx, leaf)
+
     def set_update_joseph(self, on: bool):
         """update() with FP32 products: Joseph form of the covariance update
         (off by default)."""
@@ -582,6 +617,93 @@ def _check_eval(grid, w, pts, pose):
     _numel(w, grid.N, "w")
 
 
+class SolvePlan:
+    """rbf_solve_plan: nested-dissection factor and solves of calH X = B on
+    one sparsity pattern (see Context.solve for the arguments of run)."""
+
+    def __init__(self, ctx: Context, rowptr, colidx, leaf: int = 0):
+        _need(rowptr, (None,), "rowptr")
+        _need(colidx, (None,), "colidx")
+        self.ctx, self.N = ctx, rowptr.shape[0] - 1
+        self.nnz = colidx.shape[0]
+        self._keep = (rowptr, colidx)
+        h = C.c_void_p()
+        ctx._check(ctx.lib.rbf_solve_plan_create(
+            ctx.h, self.N, _ptr(rowptr, torch.int64, "rowptr", ctx.device),
+            _ptr(colidx, torch.int32, "colidx", ctx.device), int(leaf), C.byref(h)),
+            "rbf_solve_plan_create")
+        self.h = h
+        _track(self, 0)
+
+    def info(self) -> dict:
+        n, lv, fb, mf = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()
+        self.ctx._check(self.ctx.lib.rbf_solve_plan_info(self.h, C.byref(n), C.byref(lv),
+                                                         C.byref(fb), C.byref(mf)),
+                        "rbf_solve_plan_info")
+        return {"nodes": n.value, "levels": lv.value, "front_bytes": fb.value,
+                "max_front": mf.value}
+
+    def run(self, vals, B: torch.Tensor, rtol: float = 1e-10, max_iter: int = 10,
+            inner="f64", X: torch.Tensor | None = None):
+        ctx, N = self.ctx, self.N
+        _numel(vals, self.nnz, "vals")
+        Bm = B if B.dim() == 2 else B.view(-1, 1)
+        _need(Bm, (N, None), "B")
+        nrhs = Bm.shape[1]
+        if X is None:
+            X = torch.empty_like(Bm)
+        _need(X, (N, nrhs), "X")
+        rel = (C.c_double * max(nrhs, 1))()
+        it = C.c_int32()
+        st = ctx.lib.rbf_solve_plan_run(
+            self.h, _ptr(vals, torch.float64, "vals", ctx.device),
+            _ptr(Bm, torch.float64, "B", ctx.device), Bm.stride(0),
+            _ptr(X, torch.float64, "X", ctx.device), X.stride(0), nrhs, rtol, max_iter,
+            _prec(inner), rel, C.byref(it))
+        relres = [rel[k] for k in range(nrhs)]
+        if st not in (L.RBF_OK, 5):
+            ctx._check(st, "rbf_solve_plan_run")
+        out = X if B.dim() == 2 else X.view(-1)
+        return out, relres, it.value, st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rbf_solve_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self, _finalising=sys.is_finalizing):
+        if _finalising():  # bound at definition: module globals are gone by then
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_order_host(rowptr, colidx, leaf: int = 0):
+    """rbf_solve_order_host on numpy arrays: (new2old, node_of, parent)."""
+    import numpy as np
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(colidx, dtype=np.int32)
+    N = rp.shape[0] - 1
+    lib = L.lib()
+    new2old = np.empty(N, np.int32)
+    node_of = np.empty(N, np.int32)
+    cap = max(16, 4 * N // max(leaf or 512, 1) + 64)
+    while True:
+        parent = np.empty(cap, np.int32)
+        nn = C.c_int32()
+        st = lib.rbf_solve_order_host(N, rp.ctypes.data, ci.ctypes.data, int(leaf),
+                                      new2old.ctypes.data, node_of.ctypes.data,
+                                      parent.ctypes.data, cap, C.byref(nn))
+        if st == 6 and nn.value > cap:
+            cap = nn.value
+            continue
+        if st != L.RBF_OK:
+            raise RbfError(st, "rbf_solve_order_host", -1)
+        return new2old, node_of, parent[:nn.value]
+
+
 _TILE = {"auto": L.RBF_TILE_AUTO, "128": L.RBF_TILE_128, "sub": L.RBF_TILE_SUB}
 
 
@@ -592,10 +714,11 @@ class Batched:
     Each patch is a dict with keys grid (Grid), w, P, xy, z, pts and, for
     dim 3, pose=(R, t); outputs f (required), grad, resid, jac; optional
     batch. tile: "auto", "128" or "sub" (shape of the FP64 covariance
-    product tiles). The tensors are kept alive by this object."""
+    product tiles); chains: 1..4 patch sets on concurrent streams. The
+    tensors are kept alive by this object."""
 
     def __init__(self, ctx: Context, params: Params, patches: list, dim: int = 3,
-                 eval_prec="f32", gemm_prec="f64", tile: str = "auto",
+                 eval_prec="f32", gemm_prec="f64", tile: str = "auto", chains: int = 2,
                  default_batch: int = 0, z_off: float = 0.0):
         if tile not in _TILE:
             raise ValueError(f"tile: one of {sorted(_TILE)}")
@@ -631,9 +754,10 @@ class Batched:
         pc = params.c()
         ctx._check(ctx.lib.rbf_batched_plan(ctx.h, C.byref(pc), arr, len(patches), dim,
                                             _prec(eval_prec), _prec(gemm_prec), _TILE[tile],
-                                            default_batch, z_off, C.byref(h)),
+                                            chains, default_batch, z_off, C.byref(h)),
                    "rbf_batched_plan")
         self.h = h
+        _track(self, 0)
 
     def run(self):
         self.ctx._check(self.ctx.lib.rbf_batched_run(self.h), "rbf_batched_run")
@@ -651,7 +775,9 @@ class Batched:
             self.ctx.lib.rbf_batched_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalising=sys.is_finalizing):
+        if _finalising():  # bound at definition: module globals are gone by then
+            return
         try:
             self.close()
         except Exception:
@@ -707,6 +833,7 @@ class Grid:
             st = ctx.lib.rbf_grid_create(ctx.h, C.byref(pc), cp, centers.shape[0], C.byref(h))
         ctx._check(st, entry)
         self.h = h
+        _track(self, 1)
         N = C.c_int64()
         nbx, nby, mc = C.c_int32(), C.c_int32(), C.c_int32()
         ctx.lib.rbf_grid_info(h, C.byref(N), C.byref(nbx), C.byref(nby), C.byref(mc))
@@ -719,7 +846,9 @@ class Grid:
             self.ctx.lib.rbf_grid_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalising=sys.is_finalizing):
+        if _finalising():  # bound at definition: module globals are gone by then
+            return
         try:
             self.close()
         except Exception:

@@ -42,6 +42,11 @@ __device__ inline double reg_val(double d2, const RegK& k) {
 
 // ---------------------------------------------------------------- ELL rows
 
+// Sixteen lanes per point: the lanes test the candidates of a bin row 16 at
+// a time, and a ballot with a popcount prefix gives each hit its slot in
+// candidate order (the order of a serial scan); the row's padding is then
+// written 16 slots at a time. The 16 lanes of a point share its loop bounds,
+// so they stay together through every ballot.
 template <typename T>
 __global__ void __launch_bounds__(256) k_assemble_phi(const double* __restrict__ xy, int64_t M,
                                                       const double* __restrict__ cxy,
@@ -52,8 +57,9 @@ __global__ void __launch_bounds__(256) k_assemble_phi(const double* __restrict__
                                                       int32_t* __restrict__ cols,
                                                       int32_t* __restrict__ nnz,
                                                       int32_t* __restrict__ status) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= M) return;
+  const int tid = threadIdx.x, l = tid & 15, gshift = tid & 48;
+  const int64_t i = (int64_t)blockIdx.x * 16 + (tid >> 4);
+  if (i >= M) return;  // whole groups of 16 lanes leave together
   const double x = xy[2 * i], y = xy[2 * i + 1];
   T* vrow = vals + i * kmax;
   int32_t* crow = cols + i * kmax;
@@ -64,25 +70,31 @@ __global__ void __launch_bounds__(256) k_assemble_phi(const double* __restrict__
     for (int by = by0; by <= by1; ++by) {
       const int row = by * g.nbx;
       const int s0 = start[row + bx0], s1 = start[row + bx1 + 1];
-      for (int s = s0; s < s1; ++s) {
-        const double d2 = sq_d(x, y, cxy[2 * s], cxy[2 * s + 1]);
-        if (d2 <= k.rc2) {
-          if (n < kmax) {
-            vrow[n] = (T)reg_val(d2, k);
-            crow[n] = idx[s];
-          }
-          ++n;
+      for (int base = s0; base < s1; base += 16) {
+        const int s = base + l;
+        double d2 = 0.0;
+        bool ok = false;
+        if (s < s1) {
+          d2 = sq_d(x, y, cxy[2 * s], cxy[2 * s + 1]);
+          ok = d2 <= k.rc2;
         }
+        const uint32_t gm = (uint32_t)(__ballot(ok) >> gshift) & 0xFFFFu;
+        const int pos = n + __popc(gm & ((1u << l) - 1u));
+        if (ok && pos < kmax) {
+          vrow[pos] = (T)reg_val(d2, k);
+          crow[pos] = idx[s];
+        }
+        n += __popc(gm);
       }
     }
   }
-  if (n > kmax) set_status(status, RBF_E_CAPACITY, i);
+  if (l == 0 && n > kmax) set_status(status, RBF_E_CAPACITY, i);
   const int w = n < kmax ? n : kmax;
-  for (int q = w; q < kmax; ++q) {
+  for (int q = w + l; q < kmax; q += 16) {
     vrow[q] = (T)0;
     crow[q] = 0;
   }
-  nnz[i] = w;
+  if (l == 0) nnz[i] = w;
 }
 
 // ---------------------------------------------------------- Gram pattern
@@ -220,11 +232,11 @@ rbf_status rbf_assemble_phi(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g
   RBF_TRY(set_device(ctx));
   RegK k = reg_consts(p);
   if (prec == RBF_F64)
-    k_assemble_phi<double><<<ceil_div(M, 256), 256, 0, ctx->stream>>>(
+    k_assemble_phi<double><<<ceil_div(M, 16), 256, 0, ctx->stream>>>(
         xy, M, g->d_cxy, g->d_idx, g->d_start, geom(g), k, kmax, (double*)vals, cols, nnz,
         ctx->d_status);
   else
-    k_assemble_phi<float><<<ceil_div(M, 256), 256, 0, ctx->stream>>>(
+    k_assemble_phi<float><<<ceil_div(M, 16), 256, 0, ctx->stream>>>(
         xy, M, g->d_cxy, g->d_idx, g->d_start, geom(g), k, kmax, (float*)vals, cols, nnz,
         ctx->d_status);
   RBF_LAUNCHED(ctx, "k_assemble_phi");

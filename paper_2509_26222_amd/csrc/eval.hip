@@ -444,28 +444,38 @@ __global__ void __launch_bounds__(256) k_eval_gn(const T* __restrict__ pts, int6
         (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
 }
 
-// Sum the block partials in a fixed order (lane l of term q takes blocks
-// l, l+32, ...; the 32 lane sums meet in a fixed shuffle tree); write
-// J^T J (6x6, both triangles), J^T r (6) and r^T r.
+// Sum the block partials in a fixed order: thread t of the first 1008 (36
+// per term) adds the elements t, t + 1008, ... of the flat partial array
+// (all of term t % 28, read coalesced, every load issued before the first
+// add: the partials come from every XCD), then thread q adds the 36 sums of
+// term q in order; writes J^T J (6x6, both triangles), J^T r (6) and r^T r.
+constexpr int GN_SUM_W = GN_TERMS * 36;
+constexpr int GN_SUM_LOADS = (int)((GN_MAX_BLOCKS * GN_TERMS + GN_SUM_W - 1) / GN_SUM_W);
+static_assert(GN_SUM_W <= 1024, "one workgroup");
 __global__ void __launch_bounds__(1024) k_eval_gn_sum(const double* __restrict__ part,
                                                       int64_t nblocks, double* __restrict__ JtJ,
                                                       double* __restrict__ Jtr,
                                                       double* __restrict__ rtr) {
-  const int q = threadIdx.x >> 5, l = threadIdx.x & 31;
-  if (q >= GN_TERMS) return;  // whole groups of 32 leave together
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t b = l;
-  for (; b + 96 < nblocks; b += 128) {
-    s0 += part[b * GN_TERMS + q];
-    s1 += part[(b + 32) * GN_TERMS + q];
-    s2 += part[(b + 64) * GN_TERMS + q];
-    s3 += part[(b + 96) * GN_TERMS + q];
-  }
-  for (; b < nblocks; b += 32) s0 += part[b * GN_TERMS + q];
-  double s = (s0 + s1) + (s2 + s3);
+  __shared__ double red[GN_SUM_W];
+  const int t = threadIdx.x;
+  const int64_t n = nblocks * GN_TERMS;
+  if (t < GN_SUM_W) {
+    double v[GN_SUM_LOADS];
 #pragma unroll
-  for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
-  if (l != 0) return;
+    for (int u = 0; u < GN_SUM_LOADS; ++u) {
+      const int64_t e = t + (int64_t)u * GN_SUM_W;
+      v[u] = e < n ? part[e] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < GN_SUM_LOADS; ++u) s += v[u];
+    red[t] = s;
+  }
+  __syncthreads();
+  const int q = t;
+  if (q >= GN_TERMS) return;
+  double s = 0.0;
+  for (int c = 0; c < GN_SUM_W / GN_TERMS; ++c) s += red[q + GN_TERMS * c];
   if (q < 21) {
     int a = 0, rem = q;
     while (rem >= 6 - a) {

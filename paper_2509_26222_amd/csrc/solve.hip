@@ -412,6 +412,34 @@ __global__ void __launch_bounds__(256) k_pcg_dir(double* __restrict__ p,
 
 __global__ void k_pcg_shift(double* __restrict__ sc) { sc[SC_RZ] = sc[SC_RZN]; }
 
+// ---- shared with the nested-dissection solver (ndsolve.hip)
+
+rbf_status solve_residual(rbf_ctx* ctx, const int64_t* rowptr, const int32_t* colidx,
+                          const double* vals, int64_t N, const double* B, int64_t ldb,
+                          const double* X, int64_t ldx, int64_t nrhs, double* R) {
+  if (nrhs == 1 && ldb == 1 && ldx == 1) {
+    k_csr_mv16<<<(unsigned)ceil_div(N, 16), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, X,
+                                                                    B, R);
+    RBF_LAUNCHED(ctx, "k_csr_mv16");
+    return RBF_OK;
+  }
+  k_residual<<<ceil_div(N * nrhs, 256), 256, 0, ctx->stream>>>(rowptr, colidx, vals, N, B, ldb,
+                                                               X, ldx, nrhs, R);
+  RBF_LAUNCHED(ctx, "k_residual");
+  return RBF_OK;
+}
+
+rbf_status solve_col_norms(rbf_ctx* ctx, const double* A, int64_t lda, int64_t N, int64_t nrhs,
+                           std::vector<double>& host) {
+  rbf_status st;
+  const int32_t ngroups = (int32_t)ceil_div(N, NRG);
+  double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * (ngroups + 1) * nrhs, &st);
+  if (!part) return st;
+  double* dnorm = (double*)ws_get(ctx, WS_TMP2, sizeof(double) * nrhs, &st);
+  if (!dnorm) return st;
+  return col_norms(ctx, A, lda, N, nrhs, part, dnorm, host);
+}
+
 }  // namespace rbf
 
 using namespace rbf;

@@ -856,6 +856,7 @@ rbf_status syrk_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
     }
     return RBF_OK;
   }
+  if (r.n_main <= 0 || r.cvt_x <= 0) return RBF_OK;  // no tiles (no boundary rows)
   if (prec == RBF_F32) {
     k_cvt_f32_g<<<dim3((unsigned)r.cvt_x, 1, (unsigned)r.n), 256, 0, ctx->stream>>>(r.jobs);
     RBF_LAUNCHED(ctx, "k_cvt_f32_g");
@@ -863,6 +864,7 @@ rbf_status syrk_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
     RBF_LAUNCHED(ctx, "k_syrk_f32_g");
     return RBF_OK;
   }
+  if (r.cvt_y <= 0) return RBF_OK;
   k_cvt_bf16x2_g<<<dim3((unsigned)r.cvt_x, (unsigned)r.cvt_y, (unsigned)r.n), 256, 0,
                    ctx->stream>>>(r.jobs);
   RBF_LAUNCHED(ctx, "k_cvt_bf16x2_g");
@@ -874,9 +876,9 @@ rbf_status syrk_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
 // Grouped V^T = L^{-1} U^T (one launch over the round's jobs).
 __global__ void __launch_bounds__(SYRK_NT, 2) k_linv_apply_g(const GJob* __restrict__ jobs) {
   const GJob& J = jobs[blockIdx.z];
-  const int32_t nI = (J.Bp + ST - 1) / ST, nJ = (int32_t)((J.N + 1 + ST - 1) / ST);
+  const int32_t nI = (J.Bp + ST - 1) / ST, nJ = (int32_t)((J.ncols + ST - 1) / ST);
   if ((int32_t)blockIdx.x >= nI * nJ) return;
-  linv_apply_body<false>(J.LiT, J.Bp, J.Ut, J.ldu, J.N + 1, J.Vt, nJ, J.status, J.seq);
+  linv_apply_body<false>(J.LiT, J.Bp, J.Ut, J.ldu, J.ncols, J.Vt, nJ, J.status, J.seq);
 }
 
 rbf_status linv_apply_grouped(rbf_ctx* ctx, const GRound& r) {

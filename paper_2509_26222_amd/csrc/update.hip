@@ -1541,6 +1541,25 @@ __global__ void __launch_bounds__(256) k_upd_w_sum_g(const GJob* __restrict__ jo
   upd_w_sum_body(J.w, J.wpart, J.N, (J.Bc + 63) / 64, J.status, J.seq);
 }
 
+rbf_status chol_grouped(rbf_ctx* ctx, const GRound& r) {
+  if (r.n <= 0) return RBF_OK;
+  const unsigned nz = (unsigned)r.n;
+  hipStream_t s = ctx->stream;
+  k_zero_lit_g<<<dim3(r.zero_x, 1, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_zero_lit_g");
+  k_chol_first_g<<<dim3(1, 1, nz), 256, 0, s>>>(r.jobs);
+  RBF_LAUNCHED(ctx, "k_chol_first_g");
+  for (int32_t kb = 0; kb < r.nsteps; ++kb) {
+    k_chol_step_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
+    RBF_LAUNCHED(ctx, "k_chol_step_g");
+  }
+  if (r.lr_x > 0) {
+    k_linv_row_g<<<dim3(r.lr_x, 1, nz), 256, 0, s>>>(r.jobs);
+    RBF_LAUNCHED(ctx, "k_linv_row_g");
+  }
+  return RBF_OK;
+}
+
 rbf_status update_round_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
   if (r.n <= 0) return RBF_OK;
   const unsigned nz = (unsigned)r.n;
@@ -1561,18 +1580,7 @@ rbf_status update_round_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec) {
   }
   k_upd_S_g<<<dim3(r.s_x, r.s_y, nz), 256, 0, s>>>(r.jobs);
   RBF_LAUNCHED(ctx, "k_upd_S_g");
-  k_zero_lit_g<<<dim3(r.zero_x, 1, nz), 256, 0, s>>>(r.jobs);
-  RBF_LAUNCHED(ctx, "k_zero_lit_g");
-  k_chol_first_g<<<dim3(1, 1, nz), 256, 0, s>>>(r.jobs);
-  RBF_LAUNCHED(ctx, "k_chol_first_g");
-  for (int32_t kb = 0; kb < r.nsteps; ++kb) {
-    k_chol_step_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
-    RBF_LAUNCHED(ctx, "k_chol_step_g");
-  }
-  if (r.lr_x > 0) {
-    k_linv_row_g<<<dim3(r.lr_x, 1, nz), 256, 0, s>>>(r.jobs);
-    RBF_LAUNCHED(ctx, "k_linv_row_g");
-  }
+  RBF_TRY(chol_grouped(ctx, r));
   RBF_TRY(linv_apply_grouped(ctx, r));
   k_upd_w_part_g<<<dim3(r.wp_x, r.wp_y, nz), 256, 0, s>>>(r.jobs);
   RBF_LAUNCHED(ctx, "k_upd_w_part_g");

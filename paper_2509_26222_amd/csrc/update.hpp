@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cmath>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -189,6 +190,8 @@ struct GJob {
   double* gH;
   int64_t Rcap;
   int32_t words;   // 32-bit words of the grouped gather's bitmap
+  int64_t ncols;   // columns of U^T in the gain product V^T = L^{-1} U^T
+                   // (N + 1 in the recursion: U and the innovation)
   int32_t Kp;      // k extent of the BF16 operands
   void* vlo;       // low-precision copy of V^T (FP32 / BF16 products)
   int64_t T, per_xcd, main_per_xcd;  // covariance product: tiles, per XCD,
@@ -236,6 +239,12 @@ __device__ inline int32_t job_of(const int64_t* __restrict__ pre, int32_t n, int
 // for all of its jobs, covariance product (prec) included.
 rbf_status update_round_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec);
 
+// The blocked Cholesky of every job's S (Bp x Bp, leading dimension Bp)
+// with L^{-1} transposed in LiT, as chol_blocked does for one matrix (uses
+// the jobs' S, Bp, Lb, Linv, LiT, status, index and seq; the round's
+// zero_x, nsteps, step_x and lr_x).
+rbf_status chol_grouped(rbf_ctx* ctx, const GRound& r);
+
 // The covariance products of a round, and its V^T = L^{-1} U^T (syrk.hip).
 rbf_status syrk_grouped(rbf_ctx* ctx, const GRound& r, rbf_prec prec);
 rbf_status linv_apply_grouped(rbf_ctx* ctx, const GRound& r);
@@ -247,5 +256,14 @@ rbf_status linv_apply_grouped(rbf_ctx* ctx, const GRound& r);
 void syrk_tiles(int64_t N, int32_t cu_count, int64_t* T, int64_t* per_xcd,
                 int64_t* main_per_xcd);
 constexpr int SYRK_SUB_PER_TILE = 8;
+
+// Sparse solve helpers (solve.hip): R (N x nrhs, leading dimension nrhs)
+// = B - calH X for calH in CSR; the 2-norms of the nrhs columns of A (N
+// rows, leading dimension lda) in `host` (synchronises).
+rbf_status solve_residual(rbf_ctx* ctx, const int64_t* rowptr, const int32_t* colidx,
+                          const double* vals, int64_t N, const double* B, int64_t ldb,
+                          const double* X, int64_t ldx, int64_t nrhs, double* R);
+rbf_status solve_col_norms(rbf_ctx* ctx, const double* A, int64_t lda, int64_t N, int64_t nrhs,
+                           std::vector<double>& host);
 
 }  // namespace rbf

@@ -1,7 +1,7 @@
 """Autotuner of the batched form.
 
-Chooses the tile shape of the FP64 covariance products ("auto", "128" or
-"sub") and the Kalman batch (the K extent of the covariance products and
+Chooses the number of concurrent patch chains (1, 2 or 4), the tile shape of
+the FP64 covariance products ("auto", "128" or "sub") and the Kalman batch (the K extent of the covariance products and
 the size of S, whose Cholesky is the latency-bound stage) by timing graph
 replays of a plan over a sample of the patches. The cost of a run does not
 depend on the values in (w, P), so replays that keep updating the sample's
@@ -17,12 +17,13 @@ import torch
 from . import api
 
 
-def time_plan(ctx: api.Context, params: api.Params, patches: list, tile: str,
+def time_plan(ctx: api.Context, params: api.Params, patches: list, chains: int, tile: str,
               batch: int, reps: int = 2, **kw) -> float:
     """Seconds per graph replay of one plan (after the capturing run)."""
     for q in patches:
         q["batch"] = 0
-    plan = api.Batched(ctx, params, patches, tile=tile, default_batch=batch, **kw)
+    plan = api.Batched(ctx, params, patches, tile=tile, chains=chains, default_batch=batch,
+                       **kw)
     try:
         plan.run()  # capture + first run
         plan.sync()
@@ -36,12 +37,12 @@ def time_plan(ctx: api.Context, params: api.Params, patches: list, tile: str,
         plan.close()
 
 
-def tune_batched(ctx: api.Context, params: api.Params, sample: list,
+def tune_batched(ctx: api.Context, params: api.Params, sample: list, chains=(1, 2, 4),
                  tiles=("auto", "128", "sub"), batches=(512, 1024, 2048), reps: int = 2,
                  **kw):
-    """Return ((tile, batch), {(tile, batch): seconds}) over the grid."""
+    """Return ((chains, tile, batch), {(chains, tile, batch): seconds})."""
     table = {}
-    for t, b in itertools.product(tiles, batches):
-        table[(t, b)] = time_plan(ctx, params, sample, t, b, reps=reps, **kw)
+    for c, t, b in itertools.product(chains, tiles, batches):
+        table[(c, t, b)] = time_plan(ctx, params, sample, c, t, b, reps=reps, **kw)
     best = min(table, key=table.get)
     return best, table

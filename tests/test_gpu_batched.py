@@ -52,12 +52,13 @@ def run_sequential(ctx, p, patches, gemm_prec="f64", default_batch=1024):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("tile", ["auto", "128", "sub"])
-def test_batched_equals_sequential(ctx, tile):
+@pytest.mark.parametrize("tile,chains", [("auto", 1), ("128", 2), ("sub", 4)])
+def test_batched_equals_sequential(ctx, tile, chains):
     p = api.Params()
     A = make_patches(ctx, p, 12)
     B = make_patches(ctx, p, 12)
-    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", tile=tile)
+    plan = api.Batched(ctx, p, A, dim=3, eval_prec="f32", gemm_prec="f64", tile=tile,
+                       chains=chains)
     for rep in range(2):  # capture, then replay on the updated state
         plan.run()
         assert plan.sync() == -1
@@ -68,7 +69,8 @@ def test_batched_equals_sequential(ctx, tile):
     plan.close()
     # direct oracle check of two patches after the first run's state: redo one run
     C = make_patches(ctx, p, 12)
-    plan = api.Batched(ctx, p, C, dim=3, eval_prec="f32", gemm_prec="f64", tile=tile)
+    plan = api.Batched(ctx, p, C, dim=3, eval_prec="f32", gemm_prec="f64", tile=tile,
+                       chains=chains)
     plan.run()
     plan.sync()
     for q in (C[0], C[7]):
@@ -101,7 +103,7 @@ def test_batched_reports_failed_patch(ctx):
     every other patch completes as its plain calls do."""
     p = api.Params()
     A = make_patches(ctx, p, 8, nan_patch=5)
-    plan = api.Batched(ctx, p, A, dim=3)
+    plan = api.Batched(ctx, p, A, dim=3, chains=3)
     plan.run()
     with pytest.raises(api.RbfError) as e:
         plan.sync()

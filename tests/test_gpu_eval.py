@@ -209,6 +209,17 @@ def test_eval_gn_matches_oracle_jacobian_sums(ctx, dt):
         out = ctx.eval(p, grid, dev(w), dev(pts), pose=(R, t), z_off=0.1)
         J, r = host(out["jac"]), host(out["resid"])
         assert np.abs(J.T @ J - JtJ).max() <= 1e-12 * scale
+    # the last workgroup adds the partials in block order: repeated calls,
+    # with a smaller launch in between, give the same sums bit for bit
+    for n in (20000, 777, 20000):
+        Jn, jn, rn = ctx.eval_gn(p, grid, dev(w), dev(pts[:n], dt), pose=(R, t), z_off=0.1)
+        Jn, jn = host(Jn), host(jn)
+        if n == 20000:
+            assert np.array_equal(Jn, JtJ) and np.array_equal(jn, Jtr) and float(rn) == rtr
+        else:
+            Js, rs = J0[:n], r0[:n]
+            assert np.abs(Jn - Js.T @ Js).max() <= tol * scale
+            assert abs(float(rn) - rs @ rs) <= tol * rtr0
     # empty point set gives zeros
     Z, z, zz = ctx.eval_gn(p, grid, dev(w), torch.zeros((0, 3), dtype=dt, device="cuda"),
                            pose=(R, t))
