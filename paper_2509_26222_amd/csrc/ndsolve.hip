@@ -86,7 +86,9 @@ class Dissector {
       t_.nodes[id].vars = sub;
       return id;
     }
-    // the level holding the median vertex, kept inside [1, nlev - 2]
+    // the level holding the median vertex, kept inside [1, nlev - 2] (a
+    // choice among the levels near it by separator size, tried, made the
+    // tree deeper and its critical path longer)
     int32_t c = lev_[order[order.size() / 2]];
     c = std::max(1, std::min(c, nlev - 2));
     std::vector<int32_t> A, B, S;
@@ -492,15 +494,30 @@ struct rbf_solve_plan {
   int64_t fv_rows;
   size_t asm_total;
   int32_t max_front;
+  // graph replay: the factor reads a copy of the values, the sweeps work on
+  // vectors of the plan's own, both captured on the plan's stream
+  rbf_ctx* gctx;  // context over the plan's stream (launch checks, errors)
+  hipEvent_t ev_a, ev_b;
+  double* vals;   // nnz
+  double* vec;    // bn, yn, tn, xn (Np x nrhs each), front vectors (fv_rows x nrhs)
+  int64_t vec_cap;     // columns the vectors hold
+  int64_t sweep_nrhs;  // columns of the captured sweeps
+  hipGraphExec_t g_factor, g_sweeps;
 };
 
 namespace {
 
 void plan_free(rbf_solve_plan* P) {
   if (!P) return;
+  if (P->g_factor) (void)hipGraphExecDestroy(P->g_factor);
+  if (P->g_sweeps) (void)hipGraphExecDestroy(P->g_sweeps);
   for (void* m : {(void*)P->arena, (void*)P->imap, (void*)P->asm_idx, (void*)P->d_fronts,
-                  (void*)P->d_ea, (void*)P->d_jobs, (void*)P->d_pre})
+                  (void*)P->d_ea, (void*)P->d_jobs, (void*)P->d_pre, (void*)P->vals,
+                  (void*)P->vec})
     if (m) (void)hipFree(m);
+  if (P->ev_a) (void)hipEventDestroy(P->ev_a);
+  if (P->ev_b) (void)hipEventDestroy(P->ev_b);
+  if (P->gctx) rbf_ctx_destroy(P->gctx);
   delete P;
 }
 
@@ -787,6 +804,25 @@ rbf_status rbf_solve_plan_create(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
   if (st == RBF_OK) st = dev_copy(ctx, &P->d_ea, eas);
   if (st == RBF_OK) st = dev_copy(ctx, &P->d_pre, pre);
   if (st == RBF_OK) st = dev_copy(ctx, &P->d_jobs, gjobs);
+  if (st == RBF_OK &&
+      hipMalloc(&P->vals, sizeof(double) * std::max<int64_t>(nnz, 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    st = fail(ctx, RBF_E_NOMEM, "rbf_solve_plan_create: values copy");
+  }
+  if (st == RBF_OK && (hipEventCreateWithFlags(&P->ev_a, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&P->ev_b, hipEventDisableTiming) != hipSuccess))
+    st = fail(ctx, RBF_E_HIP, "rbf_solve_plan_create: events");
+  if (st == RBF_OK) {
+    hipStream_t gs = nullptr;
+    if (hipStreamCreateWithFlags(&gs, hipStreamNonBlocking) != hipSuccess) {
+      st = fail(ctx, RBF_E_HIP, "rbf_solve_plan_create: stream");
+    } else if (rbf_ctx_create(&P->gctx, ctx->device, gs) != RBF_OK) {
+      (void)hipStreamDestroy(gs);
+      st = fail(ctx, RBF_E_HIP, "rbf_solve_plan_create: stream context");
+    } else {
+      P->gctx->owns_stream = 1;
+    }
+  }
   if (st != RBF_OK) {
     plan_free(P);
     return st;
@@ -828,8 +864,8 @@ namespace rbf {
 // Numeric factorization of the plan's pattern with these values: per
 // height, clear the level's fronts, scatter calH into them, add the
 // children's update matrices, then factor, form V^T and the update matrix.
-static rbf_status nd_factor(rbf_solve_plan* P, const double* vals) {
-  rbf_ctx* ctx = P->ctx;
+static rbf_status nd_factor(rbf_solve_plan* P, rbf_ctx* ctx) {
+  const double* vals = P->vals;
   const int32_t H = (int32_t)P->levels.size() - 1;
   for (int32_t h = 0; h <= H; ++h) {
     const NdFront* fr = P->d_fronts + P->front_at[h];
@@ -861,9 +897,8 @@ static rbf_status nd_factor(rbf_solve_plan* P, const double* vals) {
 
 // y = L^{-1} bn up the tree, then x = L^{-T} y down the tree (elimination
 // order, nrhs columns); fv: front vectors, tn: scratch of Np x nrhs.
-static rbf_status nd_sweeps(rbf_solve_plan* P, const double* bn, double* fv, double* yn,
-                            double* tn, double* xn, int64_t nrhs) {
-  rbf_ctx* ctx = P->ctx;
+static rbf_status nd_sweeps(rbf_solve_plan* P, rbf_ctx* ctx, const double* bn, double* fv,
+                            double* yn, double* tn, double* xn, int64_t nrhs) {
   const int32_t H = (int32_t)P->levels.size() - 1;
   const unsigned ny = (unsigned)nrhs;
   for (int32_t h = 0; h <= H; ++h) {
@@ -907,6 +942,40 @@ static rbf_status nd_sweeps(rbf_solve_plan* P, const double* bn, double* fv, dou
   return RBF_OK;
 }
 
+// Capture `body` (launches on the plan's stream context) into *exec on the
+// first use; every use then replays it on the plan's stream, ordered after
+// the caller's stream and before its later work by events.
+template <typename F>
+static rbf_status plan_graph(rbf_solve_plan* P, hipGraphExec_t* exec, F body) {
+  rbf_ctx* ctx = P->ctx;
+  rbf_ctx* g = P->gctx;
+  if (!*exec) {
+    RBF_HIP(ctx, hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    const rbf_status st = body(g);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    if (st != RBF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(ctx, st, "rbf_solve_plan_run: %s", g->err);
+    }
+    if (e != hipSuccess)
+      return fail(ctx, RBF_E_HIP, "rbf_solve_plan_run: capture failed: %s",
+                  hipGetErrorString(e));
+    const hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      *exec = nullptr;
+      return fail(ctx, RBF_E_HIP, "rbf_solve_plan_run: instantiate: %s", hipGetErrorString(ie));
+    }
+  }
+  RBF_HIP(ctx, hipEventRecord(P->ev_a, ctx->stream));
+  RBF_HIP(ctx, hipStreamWaitEvent(g->stream, P->ev_a, 0));
+  RBF_HIP(ctx, hipGraphLaunch(*exec, g->stream));
+  RBF_HIP(ctx, hipEventRecord(P->ev_b, g->stream));
+  RBF_HIP(ctx, hipStreamWaitEvent(ctx->stream, P->ev_b, 0));
+  return RBF_OK;
+}
+
 }  // namespace rbf
 
 extern "C" rbf_status rbf_solve_plan_run(rbf_solve_plan* P, const double* vals, const double* B,
@@ -925,16 +994,32 @@ extern "C" rbf_status rbf_solve_plan_run(rbf_solve_plan* P, const double* vals, 
   RBF_TRY(set_device(ctx));
   RBF_TRY(rbf_sync_status(ctx));  // no pending error: this factor's failures are its own
   rbf_status st;
-  // vectors: bn, yn, tn, xn (Np x nrhs each), the front vectors, R (N x nrhs)
+  // the plan's vectors for nrhs columns (grown when a call brings more); the
+  // sweeps are captured for one column count and recaptured on a change
+  if (P->g_sweeps && nrhs != P->sweep_nrhs) {
+    (void)hipGraphExecDestroy(P->g_sweeps);
+    P->g_sweeps = nullptr;
+  }
+  if (nrhs > P->vec_cap) {
+    RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (P->vec) (void)hipFree(P->vec);
+    P->vec = nullptr;
+    P->vec_cap = 0;
+    const size_t bytes = sizeof(double) * (4 * (size_t)Np + (size_t)P->fv_rows) * nrhs;
+    if (hipMalloc(&P->vec, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, RBF_E_NOMEM, "rbf_solve_plan_run: %zu bytes of vectors", bytes);
+    }
+    P->vec_cap = nrhs;
+  }
   const size_t vn = (size_t)Np * nrhs;
-  double* vec = (double*)ws_get(ctx, WS_SOLVE0,
-                                sizeof(double) * (4 * vn + (size_t)P->fv_rows * nrhs), &st);
-  if (!vec) return st;
-  double *bn = vec, *yn = vec + vn, *tn = vec + 2 * vn, *xn = vec + 3 * vn;
-  double* fv = vec + 4 * vn;
+  double *bn = P->vec, *yn = P->vec + vn, *tn = P->vec + 2 * vn, *xn = P->vec + 3 * vn;
+  double* fv = P->vec + 4 * vn;
   double* Rr = (double*)ws_get(ctx, WS_SOLVE1, sizeof(double) * (size_t)N * nrhs, &st);
   if (!Rr) return st;
-  RBF_TRY(nd_factor(P, vals));
+  RBF_HIP(ctx, hipMemcpyAsync(P->vals, vals, sizeof(double) * (size_t)P->nnz,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+  RBF_TRY(plan_graph(P, &P->g_factor, [&](rbf_ctx* g) { return nd_factor(P, g); }));
   {
     int32_t h[4];
     RBF_HIP(ctx, hipMemcpyAsync(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
@@ -951,7 +1036,9 @@ extern "C" rbf_status rbf_solve_plan_run(rbf_solve_plan* P, const double* vals, 
     k_nd_perm_in<<<(unsigned)ceil_div(Np * nrhs, 256), 256, 0, ctx->stream>>>(
         P->new2old_d, Np, R, ldr, nrhs, bn);
     RBF_LAUNCHED(ctx, "k_nd_perm_in");
-    RBF_TRY(nd_sweeps(P, bn, fv, yn, tn, xn, nrhs));
+    RBF_TRY(plan_graph(P, &P->g_sweeps,
+                       [&](rbf_ctx* g) { return nd_sweeps(P, g, bn, fv, yn, tn, xn, nrhs); }));
+    P->sweep_nrhs = nrhs;
     k_nd_perm_out<<<(unsigned)ceil_div(Np * nrhs, 256), 256, 0, ctx->stream>>>(
         P->new2old_d, Np, xn, nrhs, X, ldx, it == 0);
     RBF_LAUNCHED(ctx, "k_nd_perm_out");

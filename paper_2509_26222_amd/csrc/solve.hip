@@ -250,6 +250,43 @@ __global__ void __launch_bounds__(256) k_residual(const int64_t* __restrict__ ro
   R[r * nrhs + c] = s;
 }
 
+// Dot product in two fixed-order stages: part[g] over 2048-element group g,
+// then out = sum_g part[g] (one workgroup).
+constexpr int DOT_G = 2048;
+__device__ inline double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) sh[tid] += sh[tid + o];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_part(const double* __restrict__ x,
+                                                  const double* __restrict__ y, int64_t N,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int64_t g0 = (int64_t)blockIdx.x * DOT_G;
+  double v = 0.0;
+  for (int u = 0; u < DOT_G / 256; ++u) {
+    const int64_t e = g0 + u * 256 + threadIdx.x;
+    if (e < N) v += x[e] * y[e];
+  }
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_dot_sum(const double* __restrict__ part, int32_t ng,
+                                                 double* __restrict__ out) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int g = threadIdx.x; g < ng; g += 256) v += part[g];
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) *out = t;
+}
+
 // Column sums of squares: part[g][c] over row group g (1024 rows), then
 // out[c] = sum_g part[g][c] in order.
 constexpr int NRG = 1024;
@@ -279,6 +316,19 @@ __global__ void __launch_bounds__(256) k_colsq_sum(const double* __restrict__ pa
 
 static rbf_status col_norms(rbf_ctx* ctx, const double* A, int64_t lda, int64_t N, int64_t nrhs,
                             double* part, double* dout, std::vector<double>& host) {
+  if (nrhs == 1 && lda == 1) {  // one column: a two-stage dot product over many groups
+    const int32_t g = (int32_t)ceil_div(N, DOT_G);
+    k_dot_part<<<g, 256, 0, ctx->stream>>>(A, A, N, part);
+    RBF_LAUNCHED(ctx, "k_dot_part");
+    k_dot_sum<<<1, 256, 0, ctx->stream>>>(part, g, dout);
+    RBF_LAUNCHED(ctx, "k_dot_sum");
+    host.resize(1);
+    RBF_HIP(ctx, hipMemcpyAsync(host.data(), dout, sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    host[0] = std::sqrt(host[0]);
+    return RBF_OK;
+  }
   const int32_t ng = (int32_t)ceil_div(N, NRG);
   dim3 g1((unsigned)ceil_div(nrhs, 256), (unsigned)ng);
   k_colsq_part<<<g1, 256, 0, ctx->stream>>>(A, lda, N, nrhs, part);
@@ -337,43 +387,6 @@ __global__ void __launch_bounds__(256) k_csr_mv16(const int64_t* __restrict__ ro
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
   if (sub == 0) y[r] = b ? b[r] - t : t;
-}
-
-// Dot product in two fixed-order stages: part[g] over 2048-element group g,
-// then out = sum_g part[g] (one workgroup).
-constexpr int DOT_G = 2048;
-__device__ inline double block_sum(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) sh[tid] += sh[tid + o];
-    __syncthreads();
-  }
-  return sh[0];
-}
-
-__global__ void __launch_bounds__(256) k_dot_part(const double* __restrict__ x,
-                                                  const double* __restrict__ y, int64_t N,
-                                                  double* __restrict__ part) {
-  __shared__ double sh[256];
-  const int64_t g0 = (int64_t)blockIdx.x * DOT_G;
-  double v = 0.0;
-  for (int u = 0; u < DOT_G / 256; ++u) {
-    const int64_t e = g0 + u * 256 + threadIdx.x;
-    if (e < N) v += x[e] * y[e];
-  }
-  const double t = block_sum(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-__global__ void __launch_bounds__(256) k_dot_sum(const double* __restrict__ part, int32_t ng,
-                                                 double* __restrict__ out) {
-  __shared__ double sh[256];
-  double v = 0.0;
-  for (int g = threadIdx.x; g < ng; g += 256) v += part[g];
-  const double t = block_sum(v, sh);
-  if (threadIdx.x == 0) *out = t;
 }
 
 // Scalars of the iteration (device): rz = r.z, rz_new, pq = p.(calH p), rr.
