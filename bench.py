@@ -88,7 +88,7 @@ def copy_calibrate(mib):
                       "launches": 5}), flush=True)
 
 
-def batched_leg(ctx, api, synth, n_patches, tune, chains=2, tile="128", batch=1024):
+def batched_leg(ctx, api, synth, n_patches, tune, chains=1, tile="128", batch=1024):
     """Many uneven patches: one hipGraph launch of the batched plan vs the
     same update + evaluation calls issued one patch after another."""
     import torch

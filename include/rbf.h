@@ -346,7 +346,7 @@ rbf_status rbf_solve(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
  * colidx int32, device, both triangles) to the host once and analyses it:
  * each set of unknowns is cut by the level of a breadth-first search from a
  * pseudo-peripheral unknown (disconnected sets by their components) until
- * at most `leaf` unknowns remain (0: 512); the tree is numbered in
+ * at most `leaf` unknowns remain (0: 256); the tree is numbered in
  * postorder. It reserves the fronts' device memory (rbf_solve_plan_info:
  * front_bytes) and synchronises; the plan keeps the device pattern
  * pointers, which must stay valid and unchanged while it lives.

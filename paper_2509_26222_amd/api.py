@@ -689,7 +689,7 @@ def solve_order_host(rowptr, colidx, leaf: int = 0):
     lib = L.lib()
     new2old = np.empty(N, np.int32)
     node_of = np.empty(N, np.int32)
-    cap = max(16, 4 * N // max(leaf or 512, 1) + 64)
+    cap = max(16, 4 * N // max(leaf or 256, 1) + 64)
     while True:
         parent = np.empty(cap, np.int32)
         nn = C.c_int32()
@@ -718,7 +718,7 @@ class Batched:
     tensors are kept alive by this object."""
 
     def __init__(self, ctx: Context, params: Params, patches: list, dim: int = 3,
-                 eval_prec="f32", gemm_prec="f64", tile: str = "auto", chains: int = 2,
+                 eval_prec="f32", gemm_prec="f64", tile: str = "auto", chains: int = 1,
                  default_batch: int = 0, z_off: float = 0.0):
         if tile not in _TILE:
             raise ValueError(f"tile: one of {sorted(_TILE)}")

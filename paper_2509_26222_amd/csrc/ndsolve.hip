@@ -546,7 +546,7 @@ rbf_status rbf_solve_plan_create(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
   if (N <= 0 || N >= ((int64_t)1 << 31) || !rowptr || !colidx || leaf < 0 || leaf > 16384)
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_solve_plan_create: bad arguments");
   RBF_TRY(set_device(ctx));
-  if (leaf == 0) leaf = 512;
+  if (leaf == 0) leaf = 256;
   RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the pattern may still be in flight
   std::vector<int64_t> rp(N + 1);
   RBF_HIP(ctx, hipMemcpy(rp.data(), rowptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost));
@@ -1075,7 +1075,7 @@ extern "C" rbf_status rbf_solve_order_host(int64_t N, const int64_t* rowptr,
   for (int64_t e = 0; e < rowptr[N]; ++e)
     if (colidx[e] < 0 || colidx[e] >= N) return RBF_E_INVALID_ARG;
   NdTree t;
-  nd_analyze(N, rowptr, colidx, leaf > 0 ? leaf : 512, t);
+  nd_analyze(N, rowptr, colidx, leaf > 0 ? leaf : 256, t);
   *n_nodes = (int32_t)t.nodes.size();
   if ((int32_t)t.nodes.size() > cap) return RBF_E_CAPACITY;
   int64_t q = 0;  // the order without padding

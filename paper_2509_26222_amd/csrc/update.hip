@@ -655,7 +655,26 @@ __global__ void __launch_bounds__(256) k_chol_first(const double* __restrict__ S
 // is lower triangular; 40 k-steps per wave instead of 64); the lower 16x16
 // blocks of L_ik L_ik^T, the only ones the factor reads, are dealt round
 // robin (at most 3 blocks, 48 k-steps, per wave).
-__device__ inline void chol_step_diag(const double* __restrict__ S, int32_t Bp, int i,
+// This wave's entries of A_ii in the lower blocks it updates (block b =
+// wave + 4 q, see below), loaded before the workgroup's tiles so that their
+// latency overlaps the tile loads.
+__device__ inline void chol_diag_prefetch(const double* __restrict__ S, int32_t Bp, int i,
+                                          double (&aii)[3][4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const double* Aii = S + (int64_t)i * NB * Bp + (int64_t)i * NB;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int b = wave + 4 * q;
+    const int r = b < 1 ? 0 : b < 3 ? 1 : b < 6 ? 2 : 3;
+    const int n = b - r * (r + 1) / 2;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      aii[q][v] = b < 10 ? Aii[(int64_t)(16 * r + 4 * v + kq) * Bp + 16 * n + li] : 0.0;
+  }
+}
+
+__device__ inline void chol_step_diag(const double (&aii)[3][4], int32_t Bp, int i,
                                       double* __restrict__ Lb, double* __restrict__ Linv,
                                       double* __restrict__ LiT, double (*Ta)[LDT],
                                       double (*Tb)[LDT], int32_t* __restrict__ status,
@@ -677,7 +696,6 @@ __device__ inline void chol_step_diag(const double* __restrict__ S, int32_t Bp, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) Ta[16 * wave + 4 * v + kq][16 * n + li] = l[n][v];
   __syncthreads();
-  const double* Aii = S + (int64_t)i * NB * Bp + (int64_t)i * NB;
   // lower blocks (r, n), n <= r, in order 0:(0,0) 1:(1,0) 2:(1,1) 3:(2,0)
   // 4:(2,1) 5:(2,2) 6:(3,0) 7:(3,1) 8:(3,2) 9:(3,3); wave w takes w, w+4, w+8
 #pragma unroll
@@ -694,7 +712,7 @@ __device__ inline void chol_step_diag(const double* __restrict__ S, int32_t Bp, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rr = 16 * r + 4 * v + kq, cc = 16 * n + li;
-        Tb[rr][cc] = Aii[(int64_t)rr * Bp + cc] - u[v];
+        Tb[rr][cc] = aii[q][v] - u[v];
       }
     }
   }
@@ -744,11 +762,14 @@ __device__ __forceinline__ void chol_step_body(double* __restrict__ S, int32_t B
     i = kb + 1 + ii;
     j = kb + 1 + (u - ii * (ii + 1) / 2);
   }
+  const bool diag = !panel && i == kb + 1 && j == kb + 1;
+  double aii[3][4];
+  if (diag) chol_diag_prefetch(S, Bp, i, aii);
   load_tile(Ta, Linv + (int64_t)kb * NB * NB, NB);
   load_tile(Tb, S + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
   __syncthreads();
-  if (!panel && i == kb + 1 && j == kb + 1) {
-    chol_step_diag(S, Bp, i, Lb, Linv, LiT, Ta, Tb, status, batch, seq);
+  if (diag) {
+    chol_step_diag(aii, Bp, i, Lb, Linv, LiT, Ta, Tb, status, batch, seq);
     return;
   }
   Acc64 A;
