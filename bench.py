@@ -373,6 +373,9 @@ def main():
                                  L.SELECT_VOXEL)
     N = centers.shape[0]
     grid = ctx.grid(p, centers.contiguous())
+    # the selected centers are nodes of the 0.5 m candidate mesh: the
+    # evaluations run in the mesh form (the binned form is timed beside it)
+    grid.set_mesh_roi(od.roi, 0.5)
     nfr = args.frames if args.frames > 0 else args.steps + args.warmup
     nfr = max(1, min(nfr, args.steps + args.warmup))
     frames = []
@@ -520,6 +523,7 @@ def main():
     # region, each launch timed by its own event pair; then launches of 20M
     # points (the frame's scan points repeated), which fill the GPU
     ev = {}
+    grid_b = ctx.grid(p, centers.contiguous())  # the same centers, binned form
     xy0, z0, pts0, pose0 = frames[0]
     big = pts0.repeat(args.eval_fill // pts0.shape[0], 1) if args.eval_fill else None
 
@@ -556,6 +560,12 @@ def main():
         ctx.profile(False)
         gn_wall, gn_us = launches(lambda: ctx.eval_gn(p, grid, w, pts, pose=pose0),
                                   args.eval_reps)
+        ctx.profile(True)
+        launches(lambda: ctx.eval(p, grid_b, w, pts, pose=pose0, out=outs), args.eval_reps)
+        bms_, bn_ = ctx.profile_read(L.PROF_EVAL)
+        ctx.profile(False)
+        gnb_wall, gnb_us = launches(lambda: ctx.eval_gn(p, grid_b, w, pts, pose=pose0),
+                                    args.eval_reps)
         esz = pts.element_size()
         bytes_pt = 3 * esz + 10 * esz  # read xyz, write f, grad(2), r, J(6)
         kern_s = ems * 1e-3 / en
@@ -569,6 +579,9 @@ def main():
             "hbm_frac": q * bytes_pt / kern_s / 1e9 / PEAK_HBM_GBS,
             "gauss_newton_mpts_s_wall": q / gn_wall / 1e6,
             "gauss_newton_call_us": gn_us,
+            "binned": {"kernel_us": bms_ * 1e3 / bn_,
+                       "mpts_s_kernel": q / (bms_ * 1e-3 / bn_) / 1e6,
+                       "gauss_newton_call_us": gnb_us},
         }
         if big is not None:
             bp = big.to(dt_).contiguous()

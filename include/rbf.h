@@ -190,6 +190,31 @@ rbf_status rbf_grid_destroy(rbf_grid* grid);
  * support; subsection "The RBF Approximation Model"). */
 rbf_status rbf_bin_centers(rbf_ctx* ctx, const double* centers, int64_t N,
                            const rbf_params* params, rbf_grid** out);
+/* Declare the grid's centers nodes of a square mesh: node (i, j) at
+ * (x0 + i res, y0 + j res) for integers i, j. This is how the paper places
+ * centers: candidate nodes of a mesh of given resolution over the region
+ * of interest (section on center selection); rbf_select_centers returns
+ * such nodes with x0 = roi[0] + res/2, y0 = roi[1] + res/2. Every center
+ * must lie on a node (up to the rounding of that formula) and no two on
+ * the same node. Afterwards rbf_eval, rbf_eval_at, rbf_eval_gn and
+ * rbf_eval_noalloc on this grid use the mesh form: the Gaussian factors
+ * over the axes, so a point's support is a fixed window of nodes read from
+ * a dense node array, with one exponential per window row and column
+ * instead of one per candidate. Results equal the binned form up to
+ * rounding (the support test is taken on the same scaled squared
+ * distance). rbf_eval_adjoint and the assembly keep the binned form.
+ * res = 0 returns the grid to the binned form. The dense node array covers
+ * the centers' node range plus a margin of the window width: at most
+ * 16384 nodes per axis and 2^26 in all; the support may span at most 12
+ * nodes per axis (2 (cutoff sigma / res + 1/64) < 12). The grid holds the
+ * node map (4 bytes per node) until rbf_grid_destroy; the evaluations keep
+ * the node weights in the context's workspace (8 or 4 bytes per node).
+ * Set the mesh before a batched plan that evaluates on the grid is made.
+ * Errors: RBF_E_INVALID_ARG (a center off the mesh, two on one node, too
+ * many nodes or too wide a window; the grid then keeps its previous form),
+ * RBF_E_NOMEM. Synchronises the context's stream. */
+rbf_status rbf_grid_set_mesh(rbf_ctx* ctx, rbf_grid* grid, double x0, double y0,
+                             double res);
 /* Host outputs: number of centers, bins in x and y, and the largest number
  * of centers that can lie within one point's 3x3 bins (an upper bound on
  * the nonzeros of one regressor row). Any pointer may be NULL. */

@@ -66,6 +66,7 @@ SIGNATURES = {
     "rbf_grid_create": (C.c_int, [vp, pp, vp, i64, C.POINTER(vp)]),
     "rbf_grid_destroy": (C.c_int, [vp]),
     "rbf_bin_centers": (C.c_int, [vp, vp, i64, pp, C.POINTER(vp)]),
+    "rbf_grid_set_mesh": (C.c_int, [vp, vp, dbl, dbl, dbl]),
     "rbf_grid_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32),
                                 C.POINTER(i32), C.POINTER(i32)]),
     "rbf_sort_points": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),

@@ -840,6 +840,20 @@ class Grid:
         self.N = N.value
         self.nbx, self.nby = nbx.value, nby.value
         self.max_candidates = mc.value
+        self.mesh = None
+
+    def set_mesh(self, x0: float, y0: float, res: float) -> "Grid":
+        """Evaluate in the mesh form: the centers are the nodes
+        (x0 + i res, y0 + j res) (rbf_grid_set_mesh); res = 0 switches back."""
+        self.ctx._check(self.ctx.lib.rbf_grid_set_mesh(self.ctx.h, self.h, float(x0),
+                                                       float(y0), float(res)),
+                        "rbf_grid_set_mesh")
+        self.mesh = None if res == 0 else (float(x0), float(y0), float(res))
+        return self
+
+    def set_mesh_roi(self, roi, res: float) -> "Grid":
+        """The mesh of rbf_select_centers over roi at resolution res."""
+        return self.set_mesh(roi[0] + 0.5 * res, roi[1] + 0.5 * res, res)
 
     def close(self):
         if getattr(self, "h", None):

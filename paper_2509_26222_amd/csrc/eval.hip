@@ -108,6 +108,17 @@ __global__ void __launch_bounds__(256) k_pack_centers(const double* __restrict__
   tab[s] = v;
 }
 
+// Mesh form: wt[n] = weight of the center on dense node n, 0 where none.
+template <typename T>
+__global__ void __launch_bounds__(256) k_pack_mesh(const int32_t* __restrict__ map,
+                                                   const double* __restrict__ w, int64_t n,
+                                                   T* __restrict__ wt) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  const int32_t c = map[s];
+  wt[s] = c >= 0 ? (T)w[c] : (T)0;
+}
+
 // Lanes per point: the four lanes of a quad share a point and read
 // consecutive table entries (one 64-byte segment per load instruction), so a
 // wave's gather touches 16 cache lines instead of 64.
@@ -130,6 +141,24 @@ __device__ inline double quad_swap(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
+// Value of lane SRC of this lane's quad, for a float or a double.
+template <int SRC>
+__device__ inline float quad_bcast_v(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), SRC * 0x55, 0xf, 0xf, false));
+}
+template <int SRC>
+__device__ inline double quad_bcast_v(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), SRC * 0x55, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), SRC * 0x55, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <typename T>
+__device__ inline T quad_bcast_any(T v, int src) {  // src known at compile time
+  return src == 0 ? quad_bcast_v<0>(v)
+                  : src == 1 ? quad_bcast_v<1>(v) : src == 2 ? quad_bcast_v<2>(v)
+                                                             : quad_bcast_v<3>(v);
+}
+
 // Sum over the quad (butterfly over lanes ^1 and ^2; every lane gets it).
 template <typename T>
 __device__ inline T quad_sum(T v) {
@@ -268,6 +297,12 @@ __device__ inline void for_candidates(T xs, T ys, const TabReader<T>& tab,
 
 // Point i: world coordinates relative to the grid origin (POSE: from the
 // body point p, xi = R p + t).
+template <typename T>
+__device__ inline void pose_apply(const EvalK<T>& k, T px, T py, T pz, T& xr, T& yr, T& zw) {
+  xr = (k.R[0] * px + k.R[1] * py + k.R[2] * pz + k.t[0]) - k.x0;
+  yr = (k.R[3] * px + k.R[4] * py + k.R[5] * pz + k.t[1]) - k.y0;
+  zw = k.R[6] * px + k.R[7] * py + k.R[8] * pz + k.t[2];
+}
 template <typename T, bool POSE>
 __device__ inline void point_rel(const T* __restrict__ pts, int64_t i, const EvalK<T>& k, T& xr,
                                  T& yr, T& zw, T& px, T& py, T& pz) {
@@ -275,9 +310,7 @@ __device__ inline void point_rel(const T* __restrict__ pts, int64_t i, const Eva
     px = pts[3 * i];
     py = pts[3 * i + 1];
     pz = pts[3 * i + 2];
-    xr = (k.R[0] * px + k.R[1] * py + k.R[2] * pz + k.t[0]) - k.x0;
-    yr = (k.R[3] * px + k.R[4] * py + k.R[5] * pz + k.t[1]) - k.y0;
-    zw = k.R[6] * px + k.R[7] * py + k.R[8] * pz + k.t[2];
+    pose_apply<T>(k, px, py, pz, xr, yr, zw);
   } else {
     const typename Vec2<T>::type p = reinterpret_cast<const typename Vec2<T>::type*>(pts)[i];
     xr = p.x - k.x0;
@@ -317,11 +350,138 @@ __device__ inline void sum_point(T xr, T yr, int part, const TabReader<T>& tab,
   sy = quad_sum(sy_);
 }
 
-template <typename T, bool POSE>
-__global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t Q,
-                                              const typename Vec4<T>::type* __restrict__ tab0,
-                                              int64_t N, const int32_t* __restrict__ estart,
-                                              EGeom g,
+// ---- mesh form (centers on the nodes of a square mesh)
+//
+// With every center a node (x0 + i res, y0 + j res) the Gaussian factors
+// over the axes: phi = exp(-dx'^2) exp(-dy'^2). A point's support lies in a
+// window of MW x MW nodes, whose weights are read from a dense node array
+// (zero where no center, and in a margin of MW nodes around the mesh, so
+// that no window needs a bounds test). Lane j of the quad takes the window
+// columns j, j + 4, ...: per column one exponential, per row one; per node
+// the support test, one product and two accumulations. Every quad does the
+// same work, and the quad's loads cover consecutive nodes.
+
+// Node geometry of one call.
+template <typename T>
+struct MGeom {
+  T hs;       // node spacing in scaled coordinates (res ks)
+  T inv_res;  // 1/res: node coordinates of a point relative to the mesh origin
+  float rp;   // support radius in nodes plus MESH_PAD
+  int32_t ilo, ihi, jlo, jhi;  // range of the window's first column / row
+  int32_t ioff, joff;          // dense column / row of node 0
+  int32_t pw;                  // dense row length (nodes)
+};
+
+// The dense node weights through a buffer resource (reads past the array
+// return zeros; the clamped windows never reach them).
+template <typename T>
+struct MeshReader {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ MeshReader(const T* wt, int64_t n) {
+    r = __builtin_amdgcn_make_buffer_rsrc((void*)wt, (short)0, (int)(n * (int64_t)sizeof(T)),
+                                          0x00020000);
+  }
+  __device__ T load(int voff, int soff) const;
+};
+template <>
+__device__ inline float MeshReader<float>::load(int voff, int soff) const {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ inline double MeshReader<double>::load(int voff, int soff) const {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// f, sum w phi dx', sum w phi dy' at a point (coordinates relative to the
+// mesh origin), summed over the quad.
+template <typename T, int MW>
+__device__ inline void sum_point_mesh(T xr, T yr, int part, const MeshReader<T>& wt,
+                                      const MGeom<T>& m, const EvalK<T>& k, T& f, T& sx,
+                                      T& sy) {
+  constexpr int CPL = MW / LPP;  // columns per lane
+  static_assert(CPL * LPP == MW, "window of whole quads");
+  const float u = (float)(xr * m.inv_res), v = (float)(yr * m.inv_res);
+  const bool ok = fabsf(u) < 16777216.f && fabsf(v) < 16777216.f;  // also NaN
+  const int i0 = ok ? min(max((int)ceilf(u - m.rp), m.ilo), m.ihi) : m.ilo;
+  const int j0 = ok ? min(max((int)ceilf(v - m.rp), m.jlo), m.jhi) : m.jlo;
+  // a point with no finite node coordinates is moved far off the mesh (no
+  // node in its support, every factor exp(-d'^2) zero): f = 0, as binned
+  const T xs = ok ? xr * k.ks : (T)1e18, ys = ok ? yr * k.ks : (T)1e18;
+  T dx[CPL], dx2[CPL], cs[CPL], cy[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    dx[q] = xs - (T)(i0 + part + LPP * q) * m.hs;
+    dx2[q] = dx[q] * dx[q];
+    cs[q] = 0;
+    cy[q] = 0;
+  }
+  // row factors: lane j forms those of rows j, j + 4, ... and the quad
+  // shares them by broadcasts
+  T eown[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const T dyq = ys - (T)(j0 + part + LPP * q) * m.hs;
+    eown[q] = kexp_eval(-(dyq * dyq));
+  }
+  constexpr int SZ = (int)sizeof(T);
+  const int voff = ((j0 + m.joff) * m.pw + (i0 + m.ioff + part)) * SZ;
+  const int rowb = m.pw * SZ;
+#pragma unroll
+  for (int r = 0; r < MW; ++r) {
+    const T dy = ys - (T)(j0 + r) * m.hs;
+    const T dy2 = dy * dy;
+    const T ey = quad_bcast_any(eown[r / LPP], r % LPP);
+    const T lim = k.rc2s - dy2;  // node in the support iff dx'^2 <= lim
+    T w[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) w[q] = wt.load(voff + q * LPP * SZ, r * rowb);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const T pq = w[q] * ey;
+      const T pm = dx2[q] <= lim ? pq : (T)0;
+      cs[q] += pm;
+      cy[q] += pm * dy;
+    }
+  }
+  T f_ = 0, sx_ = 0, sy_ = 0;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const T ex = kexp_eval(-dx2[q]);
+    const T a = ex * cs[q];
+    f_ += a;
+    sx_ += a * dx[q];
+    sy_ += ex * cy[q];
+  }
+  f = quad_sum(f_);
+  sx = quad_sum(sx_);
+  sy = quad_sum(sy_);
+}
+
+// Neighbour structure of a call: the binned table (MW = 0) or the dense
+// node weights of the mesh form (MW = window).
+template <typename T>
+struct Nbr {
+  const void* tab;        // packed table (n entries) or node weights (n nodes)
+  int64_t n;
+  const int32_t* estart;  // binned form
+  EGeom eg;               // binned form
+  MGeom<T> mg;            // mesh form
+};
+
+template <typename T, int MW>
+__device__ inline void sum_nbr(T xr, T yr, int part, const Nbr<T>& nb, const EvalK<T>& k, T& f,
+                               T& sx, T& sy) {
+  if constexpr (MW == 0) {
+    const TabReader<T> tab((const typename Vec4<T>::type*)nb.tab, nb.n);
+    sum_point<T>(xr, yr, part, tab, nb.estart, nb.eg, k, f, sx, sy);
+  } else {
+    const MeshReader<T> wt((const T*)nb.tab, nb.n);
+    sum_point_mesh<T, MW>(xr, yr, part, wt, nb.mg, k, f, sx, sy);
+  }
+}
+
+template <typename T, bool POSE, int MW>
+__global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t Q, Nbr<T> nb,
                                               EvalK<T> k0, const double* __restrict__ dpose,
                                               T* __restrict__ f_out, T* __restrict__ grad_out,
                                               T* __restrict__ r_out, T* __restrict__ jac_out) {
@@ -331,11 +491,10 @@ __global__ void __launch_bounds__(256) k_eval(const T* __restrict__ pts, int64_t
   if (i >= Q) return;  // the lanes of a quad leave together
   EvalK<T> k = k0;
   if (POSE) load_pose(k, dpose);
-  const TabReader<T> tab(tab0, N);
   T xr, yr, zw, px, py, pz;
   point_rel<T, POSE>(pts, i, k, xr, yr, zw, px, py, pz);
   T f, sx, sy;
-  sum_point<T>(xr, yr, part, tab, estart, g, k, f, sx, sy);
+  sum_nbr<T, MW>(xr, yr, part, nb, k, f, sx, sy);
   const T fx = sx * k.gscale, fy = sy * k.gscale;
   // the quad's lanes share the stores
   if (part == 0) f_out[i] = f;
@@ -400,19 +559,17 @@ __device__ inline void gn_share(int lp, const double (&J)[6], double r, double (
 
 // Each quad takes points i, i + stride, ... (grid-stride; the launch is a
 // fixed function of Q) and its lanes accumulate their shares of the points'
-// 28 products in FP64 registers (gn_share). The block's sums (a butterfly
-// over the wave's quads, then the four waves in order) go to
-// part[block][28].
-template <typename T>
-__global__ void __launch_bounds__(256) k_eval_gn(const T* __restrict__ pts, int64_t Q,
-                                                 const typename Vec4<T>::type* __restrict__ tab0,
-                                                 int64_t N, const int32_t* __restrict__ estart,
-                                                 EGeom g, EvalK<T> k,
-                                                 double* __restrict__ part) {
+// 28 products in FP64 registers (gn_share). The block's sums go through
+// LDS: the 64 lane values of each term (16 quads x 4 waves) are added in
+// eight runs of eight by 224 threads, then the eight run sums in order by 28
+// threads, into part[term][block] (term-major, gridDim.x blocks).
+template <typename T, int MW>
+__global__ void __launch_bounds__(256) k_eval_gn(const T* __restrict__ pts, int64_t Q, Nbr<T> nb,
+                                                 EvalK<T> k, double* __restrict__ part) {
   static_assert(GN_TERMS == 7 * LPP, "seven terms per lane of a quad");
-  const TabReader<T> tab(tab0, N);
-  __shared__ double wsum[4][GN_TERMS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double lv[256 * 7];           // [thread][7]
+  __shared__ double runs[GN_TERMS * 8];    // [term][run]
+  const int tid = threadIdx.x;
   const int lp = tid % LPP;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * (256 / LPP);
@@ -420,7 +577,7 @@ __global__ void __launch_bounds__(256) k_eval_gn(const T* __restrict__ pts, int6
     T xr, yr, zw, px, py, pz;
     point_rel<T, true>(pts, i, k, xr, yr, zw, px, py, pz);
     T f, sx, sy;
-    sum_point<T>(xr, yr, lp, tab, estart, g, k, f, sx, sy);
+    sum_nbr<T, MW>(xr, yr, lp, nb, k, f, sx, sy);
     const double fx = (double)sx * (double)k.gscale, fy = (double)sy * (double)k.gscale;
     const double r = (double)zw - (double)k.z_off - (double)f;
     const double g0 = -fx, g1 = -fy, g2 = 1.0;
@@ -432,50 +589,58 @@ __global__ void __launch_bounds__(256) k_eval_gn(const T* __restrict__ pts, int6
     gn_share(lp, J, r, v);
   }
 #pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    double s = v[q];
-#pragma unroll
-    for (int o = 32; o >= LPP; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane < LPP) wsum[wave][7 * lane + q] = s;
-  }
+  for (int q = 0; q < 7; ++q) lv[tid * 7 + q] = v[q];
   __syncthreads();
-  if (tid < GN_TERMS)
-    part[(int64_t)blockIdx.x * GN_TERMS + tid] =
-        (wsum[0][tid] + wsum[1][tid]) + (wsum[2][tid] + wsum[3][tid]);
-}
-
-// Sum the block partials in a fixed order: thread t of the first 1008 (36
-// per term) adds the elements t, t + 1008, ... of the flat partial array
-// (all of term t % 28, read coalesced, every load issued before the first
-// add: the partials come from every XCD), then thread q adds the 36 sums of
-// term q in order; writes J^T J (6x6, both triangles), J^T r (6) and r^T r.
-constexpr int GN_SUM_W = GN_TERMS * 36;
-constexpr int GN_SUM_LOADS = (int)((GN_MAX_BLOCKS * GN_TERMS + GN_SUM_W - 1) / GN_SUM_W);
-static_assert(GN_SUM_W <= 1024, "one workgroup");
-__global__ void __launch_bounds__(1024) k_eval_gn_sum(const double* __restrict__ part,
-                                                      int64_t nblocks, double* __restrict__ JtJ,
-                                                      double* __restrict__ Jtr,
-                                                      double* __restrict__ rtr) {
-  __shared__ double red[GN_SUM_W];
-  const int t = threadIdx.x;
-  const int64_t n = nblocks * GN_TERMS;
-  if (t < GN_SUM_W) {
-    double v[GN_SUM_LOADS];
-#pragma unroll
-    for (int u = 0; u < GN_SUM_LOADS; ++u) {
-      const int64_t e = t + (int64_t)u * GN_SUM_W;
-      v[u] = e < n ? part[e] : 0.0;
-    }
+  if (tid < GN_TERMS * 8) {
+    // term 7 lp + q lives in the threads of lane lp of every quad
+    const int term = tid >> 3, run = tid & 7;
+    const int tl = term / 7, tq = term % 7;
     double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < GN_SUM_LOADS; ++u) s += v[u];
-    red[t] = s;
+    for (int j = 0; j < 8; ++j) s += lv[((run * 8 + j) * LPP + tl) * 7 + tq];
+    runs[tid] = s;
   }
   __syncthreads();
-  const int q = t;
-  if (q >= GN_TERMS) return;
+  if (tid < GN_TERMS) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += runs[tid * 8 + j];
+    part[(int64_t)tid * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Sum the block partials in a fixed order, one workgroup per term:
+// thread t adds the partials t, t + 256, ... of its term (every load issued
+// before the first add), then the 256 sums meet in a fixed tree. Writes
+// J^T J (6x6, both triangles), J^T r (6) and r^T r.
+constexpr int GN_SUM_T = 256;
+constexpr int GN_SUM_LOADS = (int)((GN_MAX_BLOCKS + GN_SUM_T - 1) / GN_SUM_T);
+__global__ void __launch_bounds__(GN_SUM_T) k_eval_gn_sum(const double* __restrict__ part,
+                                                          int64_t nblocks,
+                                                          double* __restrict__ JtJ,
+                                                          double* __restrict__ Jtr,
+                                                          double* __restrict__ rtr) {
+  __shared__ double red[GN_SUM_T];
+  const int t = threadIdx.x, q = blockIdx.x;
+  const double* __restrict__ p = part + (int64_t)q * nblocks;
+  double v[GN_SUM_LOADS];
+#pragma unroll
+  for (int u = 0; u < GN_SUM_LOADS; ++u) {
+    const int64_t e = t + (int64_t)u * GN_SUM_T;
+    v[u] = e < nblocks ? p[e] : 0.0;
+  }
   double s = 0.0;
-  for (int c = 0; c < GN_SUM_W / GN_TERMS; ++c) s += red[q + GN_TERMS * c];
+#pragma unroll
+  for (int u = 0; u < GN_SUM_LOADS; ++u) s += v[u];
+  red[t] = s;
+  __syncthreads();
+#pragma unroll
+  for (int o = GN_SUM_T / 2; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  s = red[0];
   if (q < 21) {
     int a = 0, rem = q;
     while (rem >= 6 - a) {
@@ -636,14 +801,16 @@ static double coord_scale(const rbf_params* p, bool fp32) {
   return fp32 ? std::sqrt(0.5 * l2e) / p->sigma : std::sqrt(0.5) / p->sigma;
 }
 
+// Coordinates are taken relative to the grid origin (binned form) or to
+// the mesh origin (mesh form).
 template <typename T>
 static EvalK<T> make_consts(const rbf_params* p, const rbf_grid* g, const double* pose,
-                            double z_off) {
+                            double z_off, bool mesh = false) {
   EvalK<T> k;
   const double ks = coord_scale(p, sizeof(T) == 4);
   const double rcs = p->cutoff * p->sigma * ks;
-  k.x0 = (T)g->x0;
-  k.y0 = (T)g->y0;
+  k.x0 = (T)(mesh ? g->mx0 : g->x0);
+  k.y0 = (T)(mesh ? g->my0 : g->y0);
   k.ks = (T)ks;
   k.rc2s = (T)(rcs * rcs);
   k.gscale = (T)(-1.0 / (ks * p->sigma * p->sigma));
@@ -664,6 +831,30 @@ static EGeom egeom(const rbf_params* p, const rbf_grid* g) {
   e.nbx = g->enbx;
   e.nby = g->enby;
   return e;
+}
+
+template <typename T>
+static MGeom<T> mgeom(const rbf_params* p, const rbf_grid* g) {
+  MGeom<T> m;
+  m.hs = (T)(g->mres * coord_scale(p, sizeof(T) == 4));
+  m.inv_res = (T)(1.0 / g->mres);
+  m.rp = (float)(p->cutoff * p->sigma / g->mres + MESH_PAD);
+  m.ilo = g->imin - g->mesh_w;
+  m.ihi = g->imin + g->mnx;
+  m.jlo = g->jmin - g->mesh_w;
+  m.jhi = g->jmin + g->mny;
+  m.ioff = g->mesh_w - g->imin;
+  m.joff = g->mesh_w - g->jmin;
+  m.pw = g->mpw;
+  return m;
+}
+
+// Bytes of the evaluation table of grid g in precision T: the packed
+// center table, or the dense node weights of the mesh form.
+template <typename T>
+static size_t table_bytes(const rbf_grid* g, bool mesh) {
+  return mesh ? sizeof(T) * (size_t)g->mpw * (size_t)g->mph
+              : sizeof(typename Vec4<T>::type) * (size_t)(g->N > 0 ? g->N : 1);
 }
 
 static rbf_status check_eval_args(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
@@ -726,65 +917,115 @@ static rbf_status pack(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, con
 
 rbf_status eval_workspace(rbf_ctx* ctx, const rbf_grid* g) {
   rbf_status st;
-  if (!ws_get(ctx, WS_TMP2, sizeof(double4) * (size_t)(g->N > 0 ? g->N : 1), &st)) return st;
+  size_t bytes = table_bytes<double>(g, false);
+  if (g->mesh_w && table_bytes<double>(g, true) > bytes) bytes = table_bytes<double>(g, true);
+  if (!ws_get(ctx, WS_TMP2, bytes, &st)) return st;
   return RBF_OK;
 }
 
-// Evaluation: pack (x', y', w, index) of the eval-sorted centers into `tab`
-// (N entries), then one k_eval launch.
+// The table of one call in `tab`: the mesh form's node weights if mesh,
+// else the packed (x', y', w, index) of the eval-sorted centers.
+template <typename T>
+static rbf_status pack_nbr(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
+                           const double* w, void* tab, bool mesh, Nbr<T>* nb) {
+  nb->tab = tab;
+  nb->estart = g->d_estart;
+  if (mesh) {
+    nb->n = (int64_t)g->mpw * g->mph;
+    nb->mg = mgeom<T>(p, g);
+    k_pack_mesh<T><<<ceil_div(nb->n, 256), 256, 0, ctx->stream>>>(g->d_mesh_map, w, nb->n,
+                                                                  (T*)tab);
+    RBF_LAUNCHED(ctx, "k_pack_mesh");
+  } else {
+    nb->n = g->N;
+    nb->eg = egeom(p, g);
+    RBF_TRY(pack_into<T>(ctx, p, g, w, (typename Vec4<T>::type*)tab));
+  }
+  return RBF_OK;
+}
+
+template <typename T, int MW>
+static void launch_eval(rbf_ctx* ctx, unsigned blocks, int32_t dim, const void* pts, int64_t Q,
+                        const Nbr<T>& nb, const EvalK<T>& k, const double* dpose, void* f,
+                        void* grad, void* resid, void* jac) {
+  if (dim == 3)
+    k_eval<T, true, MW><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, nb, k, dpose, (T*)f,
+                                                         (T*)grad, (T*)resid, (T*)jac);
+  else
+    k_eval<T, false, MW><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, nb, k, nullptr,
+                                                          (T*)f, (T*)grad, nullptr, nullptr);
+}
+
+// Evaluation: the call's table in `tab` (table_bytes<T>(g, mesh) bytes),
+// then one k_eval launch.
 template <typename T>
 static rbf_status eval_direct(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,
                               const double* w, const void* pts, int64_t Q, int32_t dim,
                               const double* pose, double z_off, void* f, void* grad,
-                              void* resid, void* jac, typename Vec4<T>::type* tab,
+                              void* resid, void* jac, void* tab, bool mesh,
                               const double* dpose = nullptr) {
-  RBF_TRY(pack_into<T>(ctx, p, g, w, tab));
-  const EvalK<T> k = make_consts<T>(p, g, pose, z_off);
-  const EGeom eg = egeom(p, g);
+  Nbr<T> nb;
+  RBF_TRY(pack_nbr<T>(ctx, p, g, w, tab, mesh, &nb));
+  const EvalK<T> k = make_consts<T>(p, g, pose, z_off, mesh);
   const unsigned blocks = (unsigned)ceil_div(Q * LPP, 256);
   prof_begin(ctx, RBF_PROF_EVAL);
-  if (dim == 3)
-    k_eval<T, true><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->N, g->d_estart, eg,
-                                                     k,
-                                                     dpose, (T*)f, (T*)grad, (T*)resid,
-                                                     (T*)jac);
-  else
-    k_eval<T, false><<<blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->N, g->d_estart,
-                                                      eg, k, nullptr, (T*)f, (T*)grad, nullptr,
-                                                      nullptr);
+  switch (mesh ? g->mesh_w : 0) {
+    case 0: launch_eval<T, 0>(ctx, blocks, dim, pts, Q, nb, k, dpose, f, grad, resid, jac); break;
+    case 4: launch_eval<T, 4>(ctx, blocks, dim, pts, Q, nb, k, dpose, f, grad, resid, jac); break;
+    case 8: launch_eval<T, 8>(ctx, blocks, dim, pts, Q, nb, k, dpose, f, grad, resid, jac); break;
+    default:
+      launch_eval<T, 12>(ctx, blocks, dim, pts, Q, nb, k, dpose, f, grad, resid, jac);
+      break;
+  }
   RBF_LAUNCHED(ctx, "k_eval");
   prof_end(ctx, RBF_PROF_EVAL);
   return RBF_OK;
 }
 
+// The call's table in the context's workspace.
+template <typename T>
+static rbf_status eval_ws(rbf_ctx* ctx, const rbf_grid* g, bool mesh, void** tab) {
+  rbf_status st;
+  *tab = ws_get(ctx, WS_TMP2, table_bytes<T>(g, mesh), &st);
+  return *tab ? RBF_OK : st;
+}
+
 template <typename T>
 static rbf_status eval_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
                          const void* pts, int64_t Q, int32_t dim, const double* pose,
-                         double z_off, void* f, void* grad, void* resid, void* jac) {
-  rbf_status st;
-  auto* tab = (typename Vec4<T>::type*)ws_get(ctx, WS_TMP2,
-                                               sizeof(typename Vec4<T>::type) * g->N, &st);
-  if (!tab) return st;
-  return eval_direct<T>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac, tab);
+                         double z_off, void* f, void* grad, void* resid, void* jac,
+                         const double* dpose = nullptr) {
+  const bool mesh = g->mesh_w != 0;
+  void* tab;
+  RBF_TRY(eval_ws<T>(ctx, g, mesh, &tab));
+  return eval_direct<T>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac, tab, mesh,
+                        dpose);
 }
 
 template <typename T>
 static rbf_status gn_t(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
                        const void* pts, int64_t Q, const double* pose, double z_off,
                        double* JtJ, double* Jtr, double* rtr) {
-  typename Vec4<T>::type* tab;
-  RBF_TRY(pack<T>(ctx, p, g, w, &tab));
-  const EvalK<T> k = make_consts<T>(p, g, pose, z_off);
-  const EGeom eg = egeom(p, g);
+  const bool mesh = g->mesh_w != 0;
+  void* tab;
+  RBF_TRY(eval_ws<T>(ctx, g, mesh, &tab));
+  Nbr<T> nb;
+  RBF_TRY(pack_nbr<T>(ctx, p, g, w, tab, mesh, &nb));
+  const EvalK<T> k = make_consts<T>(p, g, pose, z_off, mesh);
   int64_t blocks = ceil_div(Q * LPP, 256);
   if (blocks > GN_MAX_BLOCKS) blocks = GN_MAX_BLOCKS;
   rbf_status st;
   double* part = (double*)ws_get(ctx, WS_TMP3, sizeof(double) * GN_TERMS * (size_t)blocks, &st);
   if (!part) return st;
-  k_eval_gn<T><<<(unsigned)blocks, 256, 0, ctx->stream>>>((const T*)pts, Q, tab, g->N,
-                                                          g->d_estart, eg, k, part);
+  const dim3 gr((unsigned)blocks);
+  switch (mesh ? g->mesh_w : 0) {
+    case 0: k_eval_gn<T, 0><<<gr, 256, 0, ctx->stream>>>((const T*)pts, Q, nb, k, part); break;
+    case 4: k_eval_gn<T, 4><<<gr, 256, 0, ctx->stream>>>((const T*)pts, Q, nb, k, part); break;
+    case 8: k_eval_gn<T, 8><<<gr, 256, 0, ctx->stream>>>((const T*)pts, Q, nb, k, part); break;
+    default: k_eval_gn<T, 12><<<gr, 256, 0, ctx->stream>>>((const T*)pts, Q, nb, k, part); break;
+  }
   RBF_LAUNCHED(ctx, "k_eval_gn");
-  k_eval_gn_sum<<<1, 1024, 0, ctx->stream>>>(part, blocks, JtJ, Jtr, rtr);
+  k_eval_gn_sum<<<GN_TERMS, GN_SUM_T, 0, ctx->stream>>>(part, blocks, JtJ, Jtr, rtr);
   RBF_LAUNCHED(ctx, "k_eval_gn_sum");
   return RBF_OK;
 }
@@ -877,7 +1118,16 @@ rbf_status rbf_eval_noalloc(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g
   if (Q > 0 && !f) return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval_noalloc: f is required");
   if (dim == 2 && (resid || jac))
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_eval_noalloc: resid/jac need dim == 3");
-  if (g->N > RBF_EVAL_NOALLOC_MAX_CENTERS)
+  // the mesh form when its node weights fit the scratch array (else the
+  // binned form, which rbf_eval would not take)
+  const size_t cap = sizeof(double4) * (size_t)RBF_EVAL_NOALLOC_MAX_CENTERS;
+  const bool mesh = g->mesh_w != 0 && (prec == RBF_F64 ? table_bytes<double>(g, true)
+                                                       : table_bytes<float>(g, true)) <= cap;
+  if (g->mesh_w && !mesh)
+    return fail(ctx, RBF_E_CAPACITY,
+                "rbf_eval_noalloc: the mesh's %lld nodes exceed the scratch array (use "
+                "rbf_eval)", (long long)g->mpw * g->mph);
+  if (!mesh && g->N > RBF_EVAL_NOALLOC_MAX_CENTERS)
     return fail(ctx, RBF_E_CAPACITY,
                 "rbf_eval_noalloc: %lld centers exceed the maximum of %d (use rbf_eval)",
                 (long long)g->N, (int)RBF_EVAL_NOALLOC_MAX_CENTERS);
@@ -888,9 +1138,9 @@ rbf_status rbf_eval_noalloc(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g
     return fail(ctx, RBF_E_HIP, "rbf_eval_noalloc: no device address of the scratch table");
   if (prec == RBF_F64)
     return eval_direct<double>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac,
-                               (double4*)tab);
-  return eval_direct<float>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac,
-                            (float4*)tab);
+                               tab, mesh);
+  return eval_direct<float>(ctx, p, g, w, pts, Q, dim, pose, z_off, f, grad, resid, jac, tab,
+                            mesh);
 }
 
 rbf_status rbf_eval(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, const double* w,
@@ -922,17 +1172,9 @@ rbf_status rbf_eval_at(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g, con
   RBF_TRY(set_device(ctx));
   double* buf;
   RBF_TRY(pose_at(ctx, pose0, delta, &buf));
-  rbf_status st;
-  if (prec == RBF_F64) {
-    auto* tab = (double4*)ws_get(ctx, WS_TMP2, sizeof(double4) * g->N, &st);
-    if (!tab) return st;
-    return eval_direct<double>(ctx, p, g, w, pts, Q, 3, pose0, z_off, f, grad, resid, jac, tab,
-                               buf);
-  }
-  auto* tab = (float4*)ws_get(ctx, WS_TMP2, sizeof(float4) * g->N, &st);
-  if (!tab) return st;
-  return eval_direct<float>(ctx, p, g, w, pts, Q, 3, pose0, z_off, f, grad, resid, jac, tab,
-                            buf);
+  if (prec == RBF_F64)
+    return eval_t<double>(ctx, p, g, w, pts, Q, 3, pose0, z_off, f, grad, resid, jac, buf);
+  return eval_t<float>(ctx, p, g, w, pts, Q, 3, pose0, z_off, f, grad, resid, jac, buf);
 }
 
 rbf_status rbf_eval_adjoint_at(rbf_ctx* ctx, const rbf_params* p, const rbf_grid* g,

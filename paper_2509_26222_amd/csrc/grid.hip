@@ -5,6 +5,7 @@
 // the support of a point lies in the point's 3x3 neighbourhood of bins.
 // Bins are row-major, so the three bins of one neighbourhood row are
 // contiguous in the sorted center array: a lookup is three contiguous runs.
+#include <cfloat>
 #include <cmath>
 
 #include "internal.hpp"
@@ -104,6 +105,41 @@ __global__ void __launch_bounds__(256) k_permute_points(const double* __restrict
   if (z) z_out[s] = z[i];
 }
 
+// Node map of the mesh form: map[n] = -1 for every node of the padded
+// array, then each center claims its node. flags bit 0: a center is off the
+// mesh; bit 1: two centers share a node.
+__global__ void __launch_bounds__(256) k_mesh_clear(int32_t* __restrict__ map, int64_t n) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s < n) map[s] = -1;
+}
+
+struct MeshDef {
+  double x0, y0, res;
+  int32_t ioff, joff, nx, ny, pw;  // node i -> column i + ioff; nx, ny nodes
+};
+
+// c: the centers in bin order, idx: their original indices.
+__global__ void __launch_bounds__(256) k_mesh_map(const double* __restrict__ c,
+                                                  const int32_t* __restrict__ idx, int64_t n,
+                                                  MeshDef m, int32_t* __restrict__ map,
+                                                  int32_t* __restrict__ flags) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  const double x = c[2 * s], y = c[2 * s + 1];
+  const double fi = rint((x - m.x0) / m.res), fj = rint((y - m.y0) / m.res);
+  // on the mesh: within a few rounding units of the node's coordinate
+  const double nx = m.x0 + fi * m.res, ny = m.y0 + fj * m.res;
+  const double tx = 16.0 * DBL_EPSILON * (fabs(x) + fabs(m.x0) + fabs(fi * m.res));
+  const double ty = 16.0 * DBL_EPSILON * (fabs(y) + fabs(m.y0) + fabs(fj * m.res));
+  const int64_t ci = (int64_t)fi + m.ioff, cj = (int64_t)fj + m.joff;
+  if (!(fabs(x - nx) <= tx && fabs(y - ny) <= ty) || ci < m.ioff || cj < m.joff ||
+      ci >= (int64_t)m.ioff + m.nx || cj >= (int64_t)m.joff + m.ny) {
+    atomicOr(flags, 1);
+    return;
+  }
+  if (atomicCAS(&map[cj * m.pw + ci], -1, idx[s]) != -1) atomicOr(flags, 2);
+}
+
 }  // namespace rbf
 
 using namespace rbf;
@@ -162,6 +198,7 @@ rbf_status rbf_grid_create(rbf_ctx* ctx, const rbf_params* p, const double* cent
   g->inv_h = 1.0 / h;
   g->nbx = (int32_t)fx;
   g->nby = (int32_t)fy;
+  for (int q = 0; q < 4; ++q) g->box[q] = box[q];
   g->sigma = p->sigma;
   g->cutoff = p->cutoff;
   g->sigma_eps = p->sigma_eps;
@@ -243,9 +280,97 @@ rbf_status rbf_bin_centers(rbf_ctx* ctx, const double* centers, int64_t N,
   return rbf_grid_create(ctx, p, centers, N, out);
 }
 
+rbf_status rbf_grid_set_mesh(rbf_ctx* ctx, rbf_grid* g, double x0, double y0, double res) {
+  if (!ctx || !g) return RBF_E_INVALID_ARG;
+  if (g->device != ctx->device)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_grid_set_mesh: grid on another device");
+  RBF_TRY(set_device(ctx));
+  if (res == 0.0) {  // back to the binned form
+    RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (g->d_mesh_map) (void)hipFree(g->d_mesh_map);
+    g->d_mesh_map = nullptr;
+    g->mesh_w = 0;
+    return RBF_OK;
+  }
+  if (!(res > 0) || !std::isfinite(res) || !std::isfinite(x0) || !std::isfinite(y0))
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_grid_set_mesh: bad origin or res");
+  // window: the integers in [u - R - pad, u + R + pad], R = cutoff sigma / res
+  const double R = g->cutoff * g->sigma / res;
+  const double wn = std::floor(2.0 * (R + MESH_PAD)) + 1.0;
+  const int32_t mw = wn <= 4.0 ? 4 : wn <= 8.0 ? 8 : wn <= 12.0 ? 12 : 0;
+  if (!mw)
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_grid_set_mesh: the support spans %.0f nodes per axis (at most 12)", wn);
+  const double fi0 = std::rint((g->box[0] - x0) / res), fi1 = std::rint((g->box[2] - x0) / res);
+  const double fj0 = std::rint((g->box[1] - y0) / res), fj1 = std::rint((g->box[3] - y0) / res);
+  const double nx = fi1 - fi0 + 1.0, ny = fj1 - fj0 + 1.0;
+  if (!(std::fabs(fi0) < 1e9 && std::fabs(fj0) < 1e9) || nx > MESH_MAX_NODES_AXIS ||
+      ny > MESH_MAX_NODES_AXIS || (nx + 2 * mw) * (ny + 2 * mw) > double(1 << 26))
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_grid_set_mesh: %.0f x %.0f nodes (at most 16384 per axis and 2^26 in "
+                "all with the margins)", nx, ny);
+  MeshDef m;
+  m.x0 = x0;
+  m.y0 = y0;
+  m.res = res;
+  m.nx = (int32_t)nx;
+  m.ny = (int32_t)ny;
+  m.ioff = mw - (int32_t)fi0;
+  m.joff = mw - (int32_t)fj0;
+  m.pw = m.nx + 2 * mw;
+  const int32_t ph = m.ny + 2 * mw;
+  const int64_t nodes = (int64_t)m.pw * ph;
+  int32_t* map = nullptr;
+  if (hipMalloc(&map, sizeof(int32_t) * nodes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, RBF_E_NOMEM, "rbf_grid_set_mesh: allocation failed");
+  }
+  rbf_status st;
+  int32_t* flags = (int32_t*)ws_get(ctx, WS_TMP0, sizeof(int32_t), &st);
+  if (flags) st = fill_zero(ctx, flags, sizeof(int32_t));
+  if (st == RBF_OK) {
+    k_mesh_clear<<<ceil_div(nodes, 256), 256, 0, ctx->stream>>>(map, nodes);
+    st = check_launch(ctx, "k_mesh_clear");
+  }
+  if (st == RBF_OK) {
+    k_mesh_map<<<ceil_div(g->N, 256), 256, 0, ctx->stream>>>(g->d_cxy, g->d_idx, g->N, m,
+                                                               map, flags);
+    st = check_launch(ctx, "k_mesh_map");
+  }
+  int32_t hf = 0;
+  if (st == RBF_OK &&
+      (hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream) !=
+           hipSuccess ||
+       hipStreamSynchronize(ctx->stream) != hipSuccess))
+    st = fail(ctx, RBF_E_HIP, "rbf_grid_set_mesh: readback failed");
+  if (st == RBF_OK && hf)
+    st = fail(ctx, RBF_E_INVALID_ARG, "rbf_grid_set_mesh: %s",
+              (hf & 1) ? "a center is not a node of the mesh"
+                       : "two centers lie on the same node");
+  if (st != RBF_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(map);
+    return st;
+  }
+  if (g->d_mesh_map) (void)hipFree(g->d_mesh_map);
+  g->d_mesh_map = map;
+  g->mesh_w = mw;
+  g->mx0 = x0;
+  g->my0 = y0;
+  g->mres = res;
+  g->imin = (int32_t)fi0;
+  g->jmin = (int32_t)fj0;
+  g->mnx = m.nx;
+  g->mny = m.ny;
+  g->mpw = m.pw;
+  g->mph = ph;
+  return RBF_OK;
+}
+
 rbf_status rbf_grid_destroy(rbf_grid* g) {
   if (!g) return RBF_E_INVALID_ARG;
   (void)hipSetDevice(g->device);
+  if (g->d_mesh_map) (void)hipFree(g->d_mesh_map);
   if (g->d_start) (void)hipFree(g->d_start);
   if (g->d_idx) (void)hipFree(g->d_idx);
   if (g->d_rank) (void)hipFree(g->d_rank);

@@ -106,6 +106,17 @@ struct rbf_grid {
   int32_t* d_estart;  // enbx*enby + 1 offsets into the eval-sorted order
   int32_t* d_eidx;    // eval-sorted position -> original center index
   double* d_ecxy;     // eval-sorted centers, interleaved (x, y), f64
+  double box[4];      // center bounding box (min x, min y, max x, max y)
+  // Mesh form of the evaluation (rbf_grid_set_mesh): every center is a node
+  // (mx0 + i res, my0 + j res). mesh_w = 0: off; else the support window
+  // in nodes per axis (4, 8 or 12). The dense node array covers nodes
+  // imin - mesh_w .. imin + mnx - 1 + mesh_w (and the same in j), row-major
+  // with rows of mpw = mnx + 2 mesh_w; d_mesh_map holds the center of each
+  // node or -1.
+  int32_t mesh_w;
+  double mx0, my0, mres;
+  int32_t imin, jmin, mnx, mny, mpw, mph;
+  int32_t* d_mesh_map;
 };
 
 namespace rbf {
@@ -115,6 +126,11 @@ namespace rbf {
 constexpr double EVAL_BINS_PER_RC = 3.0;
 constexpr double EVAL_BIN_MARGIN = 1.01;
 constexpr int EVAL_MAX_ROWS = 8;
+// Mesh form: the window of a point is MESH_W nodes per axis from the first
+// node within (support radius + MESH_PAD) nodes; the pad absorbs the FP32
+// rounding of the node coordinates (at most 2^14 nodes per axis).
+constexpr double MESH_PAD = 1.0 / 64.0;
+constexpr int MESH_MAX_NODES_AXIS = 1 << 14;
 }  // namespace rbf
 
 namespace rbf {

@@ -2,8 +2,8 @@
 memory, for callers that cannot allocate) against rbf_eval: same kernels,
 so the outputs must be bitwise equal. Two calls in a row on one context,
 the second on a smaller center set and fewer points, in FP64 and FP32, in
-the world-xy and the pose form; a grid above the stated maximum is refused
-before any launch."""
+the world-xy and the pose form, with the binned and the mesh form of the
+evaluation; a grid above the stated maximum is refused before any launch."""
 import numpy as np
 import pytest
 import torch
@@ -13,9 +13,9 @@ from paper_2509_26222_amd import api, synth
 pytestmark = pytest.mark.gpu
 
 
-def _case(seed, nx, ny, q):
+def _case(seed, nx, ny, q, mesh=False):
     rng = np.random.default_rng(seed)
-    centers = synth.grid_centers(rng, nx, ny, 0.5)
+    centers = synth.grid_centers(rng, nx, ny, 0.5, jitter=0.0 if mesh else 0.1)
     w = rng.normal(0.0, 0.3, centers.shape[0])
     lo = centers.min(0) - 1.0
     hi = centers.max(0) + 1.0
@@ -30,17 +30,20 @@ def _outputs(ctx, p, grid, w, pts, pose, noalloc):
     return {k: v.cpu() for k, v in out.items() if v is not None}
 
 
+@pytest.mark.parametrize("mesh", [False, True])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("form", ["xy", "pose"])
-def test_noalloc_matches_rbf_eval_two_calls(dtype, form):
+def test_noalloc_matches_rbf_eval_two_calls(dtype, form, mesh):
     d = torch.device("cuda:0")
     p = api.Params()
     ctx = api.Context(0)
     R = synth.rot_zyx(0.4, 0.03, -0.02)
     # first call: 100 x 90 centers, 70,001 points; second: 23 x 31, 3,001
     for seed, nx, ny, q in ((11, 100, 90, 70_001), (12, 23, 31, 3_001)):
-        centers, w_np, xy, z = _case(seed, nx, ny, q)
+        centers, w_np, xy, z = _case(seed, nx, ny, q, mesh)
         grid = ctx.grid(p, torch.from_numpy(centers).to(d))
+        if mesh:  # nodes (i + 1/2) 0.5: the mesh form of the evaluation
+            grid.set_mesh(0.25, 0.25, 0.5)
         w = torch.from_numpy(w_np).to(d)
         if form == "xy":
             pts = torch.from_numpy(xy).to(d).to(dtype).contiguous()
@@ -50,7 +53,7 @@ def test_noalloc_matches_rbf_eval_two_calls(dtype, form):
             world = np.concatenate([xy, z[:, None]], 1)
             pts = torch.from_numpy((world - t) @ R).to(d).to(dtype).contiguous()
             pose = (R, t)
-        print(f"noalloc case: {form} {dtype} N={grid.N} Q={q}", flush=True)
+        print(f"noalloc case: {form} {dtype} mesh={mesh} N={grid.N} Q={q}", flush=True)
         ref = _outputs(ctx, p, grid, w, pts, pose, noalloc=False)
         got = _outputs(ctx, p, grid, w, pts, pose, noalloc=True)
         assert set(got) == set(ref)
