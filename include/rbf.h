@@ -505,8 +505,11 @@ rbf_status rbf_eval_adjoint_at(rbf_ctx* ctx, const rbf_params* params, const rbf
  * held until the process ends. The caller still passes the inputs and
  * outputs. Returns
  * RBF_E_CAPACITY, before any launch, if the grid holds more than
- * RBF_EVAL_NOALLOC_MAX_CENTERS centers. Every call on one GPU, from any
- * context, shares that GPU's array and rewrites the first N entries, so
+ * RBF_EVAL_NOALLOC_MAX_CENTERS centers. On a grid in the mesh form
+ * (rbf_grid_set_mesh) the array holds the dense node weights instead (8 or
+ * 4 bytes per node of the padded mesh), and a mesh whose node weights
+ * exceed the 4 MiB returns RBF_E_CAPACITY. Every call on one GPU, from any
+ * context, shares that GPU's array and rewrites its first entries, so
  * calls that overlap on one GPU (on different streams, or from several
  * threads) race and must be ordered by the caller. */
 rbf_status rbf_eval_noalloc(rbf_ctx* ctx, const rbf_params* params,
