@@ -82,7 +82,10 @@ typedef struct rbf_grid rbf_grid; /* neighbour-binned copy of a center set  */
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
  * (a hipStream_t; NULL = the null stream). *out receives the handle. */
 rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream);
-/* Destroy a context and free its workspace (synchronises its stream). */
+/* Destroy a context and free its workspace (synchronises its stream).
+ * Batched and solve plans made on the context use its device and stream
+ * until they are destroyed: while any is alive the call returns
+ * RBF_E_INVALID_ARG and destroys nothing. */
 rbf_status rbf_ctx_destroy(rbf_ctx* ctx);
 /* Re-bind the context to another stream of the same device. */
 rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream);

@@ -145,6 +145,7 @@ class Context:
         self._check(self.lib.rbf_ctx_create(C.byref(h), device, C.c_void_p(s.cuda_stream)),
                     "rbf_ctx_create", ctx=False)
         self.h = h
+        self._plans = weakref.WeakSet()  # plans made on this context
         _track(self, 2)
 
     def _check(self, st: int, what: str, ctx: bool = True):
@@ -183,6 +184,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for plan in list(getattr(self, "_plans", ())):
+                plan.close()  # plans use the context until they are destroyed
             self.lib.rbf_ctx_destroy(self.h)
             self.h = None
 
@@ -634,6 +637,7 @@ class SolvePlan:
             "rbf_solve_plan_create")
         self.h = h
         _track(self, 0)
+        self.ctx._plans.add(self)
 
     def info(self) -> dict:
         n, lv, fb, mf = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()
@@ -758,6 +762,7 @@ class Batched:
                    "rbf_batched_plan")
         self.h = h
         _track(self, 0)
+        self.ctx._plans.add(self)
 
     def run(self):
         self.ctx._check(self.ctx.lib.rbf_batched_run(self.h), "rbf_batched_run")

@@ -451,6 +451,7 @@ rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params, const rbf_pa
     batched_free(b);
     return fail(ctx, st, "rbf_batched_plan: setup failed: %s", why.c_str());
   }
+  ++ctx->plans;
   *out = b;
   return RBF_OK;
 }
@@ -512,6 +513,7 @@ rbf_status rbf_batched_destroy(rbf_batched* b) {
   (void)hipSetDevice(b->parent->device);
   if (b->cap) (void)hipStreamSynchronize(b->cap->stream);
   (void)hipStreamSynchronize(b->parent->stream);
+  --b->parent->plans;
   return batched_free(b);
 }
 

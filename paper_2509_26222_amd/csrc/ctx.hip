@@ -365,6 +365,11 @@ rbf_status rbf_ctx_create(rbf_ctx** out, int device, void* hip_stream) {
 
 rbf_status rbf_ctx_destroy(rbf_ctx* ctx) {
   if (!ctx) return RBF_E_INVALID_ARG;
+  // a plan keeps using its context's device and stream until it is
+  // destroyed: the context must outlive it
+  if (ctx->plans > 0)
+    return fail(ctx, RBF_E_INVALID_ARG, "rbf_ctx_destroy: %d plan(s) made on this context "
+                "are still alive (destroy them first)", (int)ctx->plans);
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);

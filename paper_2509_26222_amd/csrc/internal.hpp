@@ -82,6 +82,7 @@ struct rbf_ctx {
   int32_t prof_n[RBF_PROF_KINDS];
   int32_t prof_dropped[RBF_PROF_KINDS];
   int32_t owns_stream;  // stream created by the library (batched branches)
+  int32_t plans;        // live batched and solve plans made on this context
   int64_t index_base;   // added to the batch index rbf_update records
   int32_t cu_count;     // compute units of the device (0: unknown)
 };

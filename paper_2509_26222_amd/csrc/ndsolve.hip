@@ -835,6 +835,7 @@ rbf_status rbf_solve_plan_create(rbf_ctx* ctx, int64_t N, const int64_t* rowptr,
     r.step_x = P->step_x[h].data();
   }
   P->asm_total = atot;
+  ++ctx->plans;
   *out = P;
   return RBF_OK;
 }
@@ -853,6 +854,7 @@ rbf_status rbf_solve_plan_destroy(rbf_solve_plan* P) {
   if (!P) return RBF_E_INVALID_ARG;
   (void)hipSetDevice(P->ctx->device);
   (void)hipStreamSynchronize(P->ctx->stream);
+  --P->ctx->plans;
   plan_free(P);
   return RBF_OK;
 }

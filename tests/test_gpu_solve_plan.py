@@ -143,3 +143,18 @@ def test_plan_errors(ctx, small):
     assert st == 0 and O.relres(H, host(x), b) <= 1e-12
     plan.close()
     ctx.sync_status()
+
+
+def test_context_outlives_its_plans(small):
+    """A plan uses its context's device and stream until it is destroyed:
+    rbf_ctx_destroy refuses while a plan is alive (and destroys nothing),
+    Context.close() destroys the context's plans first."""
+    s, p, H, b = small
+    c = api.Context(0)
+    rp, ci, v = csr_dev(H)
+    plan = c.solve_plan(rp, ci, leaf=64)
+    assert c.lib.rbf_ctx_destroy(c.h) == 1  # RBF_E_INVALID_ARG
+    x, rel, it, st = plan.run(v, dev(b), rtol=1e-12, max_iter=5)  # context intact
+    assert st == 0 and O.relres(H, host(x), b) <= 1e-12
+    c.close()
+    assert plan.h is None and c.h is None
