@@ -642,7 +642,7 @@ def main():
             "flops_per_launch": syrk_flops / max(syrk_n, 1),
             "launches_note": ("one launch = one batch's product: k_syrk_f64 over the whole "
                               "rounds of 128x128 tiles, then k_syrk_f64_tail over the "
-                              "leftover tiles as 64x64 sub-tiles, timed together by one "
+                              "leftover tiles as 32x64 sub-tiles, timed together by one "
                               "event pair; achieved = all product flops / all product time"),
         },
         "update_streams": args.streams,
