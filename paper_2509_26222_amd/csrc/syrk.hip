@@ -167,8 +167,11 @@ __device__ __forceinline__ void syrk_f64_body(double* __restrict__ P, int64_t ld
     }
     __syncthreads();
   }
-  // epilogue: P[gi][gj] -= C and mirror (lower tiles; diagonal tiles keep
-  // gi >= gj so each element is written once)
+  // epilogue: P[gi][gj] -= C (lower tiles; diagonal tiles keep gi >= gj so
+  // each element is written once), then the mirror P[gj][gi]. The mirror
+  // goes through LDS (the stage buffer, free now) 32 columns at a time, so
+  // each of its rows is written as one coalesced 1 KB run rather than in
+  // 32-byte pieces of 16 rows per store instruction.
   const bool diag = (I == J);
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -181,9 +184,35 @@ __device__ __forceinline__ void syrk_f64_body(double* __restrict__ P, int64_t ld
         if (gi < N && gj < N && (!diag || gi >= gj)) {
           const double nv = P[gi * ldp + gj] - acc[mi][ni][v];
           P[gi * ldp + gj] = nv;
-          if (gi != gj) P[gj * ldp + gi] = nv;
+          acc[mi][ni][v] = nv;
         }
       }
+  constexpr int MP = ST + 1;  // pitch of the transposed chunk (doubles)
+  static_assert(32 * MP <= 2 * SKC * SLD, "a 32-column chunk fits the stage buffer");
+  double (*Tm)[MP] = reinterpret_cast<double (*)[MP]>(&As[0][0][0]);
+#pragma unroll
+  for (int q = 0; q < ST / 32; ++q) {
+    if (wn == q / 2) {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ni = 2 * (q % 2) + nn;
+            const int c = ni * 16 + (lane & 15) - 32 * (q % 2);  // column in the chunk
+            const int r = wm * 32 + mi * 16 + 4 * v + (lane >> 4);
+            Tm[c][r] = acc[mi][ni][v];
+          }
+    }
+    __syncthreads();
+    for (int e = tid; e < 32 * ST; e += SYRK_NT) {
+      const int c = e / ST, r = e % ST;
+      const int64_t gr = J0 + 32 * q + c, gc = I0 + r;  // mirror of (gc, gr)
+      if (gr < N && gc < N && (!diag || gc > gr)) P[gr * ldp + gc] = Tm[c][r];
+    }
+    __syncthreads();  // the chunk is read before the next one is written
+  }
 }
 
 __global__ void __launch_bounds__(SYRK_NT, 2) k_syrk_f64(double* __restrict__ P, int64_t ldp,
