@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE (x2.0, the copy-kernel calibration) + WRITE_SIZE (x1.0); summary
 # in profiles/k_syrk_and_k_eval_hbm_bytes_odometry_n10k.txt. Valid only for
 # those kernel versions and that shape (None otherwise).
-SYRK_F64_TRAFFIC = {(10000, 1024): 1.9948e9 + 0.8203e9}
+SYRK_F64_TRAFFIC = {(10000, 1024): 1.9686e9 + 0.8004e9}
 
 
 def parse():
