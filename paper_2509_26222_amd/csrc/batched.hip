@@ -257,6 +257,7 @@ static rbf_status batched_build(rbf_batched* b, rbf_ctx* ctx) {
         }
       }
       r.nsteps = nsteps;
+      r.chol_split = 1;  // many factors per launch: bound by throughput
       std::vector<int32_t>& sx = b->step_x[c][t];
       sx.assign(nsteps, 0);
       for (int32_t kb = 0; kb < nsteps; ++kb)

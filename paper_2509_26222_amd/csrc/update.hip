@@ -1537,6 +1537,105 @@ __global__ void __launch_bounds__(256) k_chol_first_g(const GJob* __restrict__ j
   chol_first_body(J.S, J.Bp, J.Lb, J.Linv, J.LiT, J.status, J.index, J.seq);
 }
 
+// Split form of Cholesky step kb, for launches over many factors (the
+// batched form), which are bound by throughput rather than by the critical
+// path of one factor. In chol_step_body every trailing tile forms L_ik and
+// L_jk again from A and Linv_kk (three 64x64 products per tile, no waiting
+// on the panel workgroups); here launch (a) forms each panel block L_ik
+// once (into Lb), factors the next diagonal block and does the inverse's
+// share of the step, and launch (b) updates the trailing tiles from the
+// stored panel: one product per tile. Every element takes the same
+// operations in the same order as in chol_step_body (the stored panel holds
+// the same accumulator values the fused tile forms), so the factor is the
+// same bit for bit.
+__device__ __forceinline__ void chol_panel_body(double* __restrict__ S, int32_t Bp,
+    int32_t nblk, int32_t kb, double* __restrict__ Lb, double* __restrict__ Linv,
+    double* __restrict__ LiT, int32_t* __restrict__ status, int64_t batch, int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  __shared__ double Ta[NB][LDT], Tb[NB][LDT];
+  const int m = nblk - kb - 1;
+  const int t = blockIdx.x;
+  if (t > m) {  // the inverse's work of step kb
+    linv_work(t - m - 1, kb, Bp, Lb, Linv, LiT, Ta, Tb);
+    return;
+  }
+  const bool diag = t == m;
+  const int i = diag ? kb + 1 : kb + 1 + t;
+  double aii[3][4];
+  if (diag) chol_diag_prefetch(S, Bp, i, aii);
+  load_tile(Ta, Linv + (int64_t)kb * NB * NB, NB);
+  load_tile(Tb, S + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
+  __syncthreads();
+  if (diag) {
+    chol_step_diag(aii, Bp, i, Lb, Linv, LiT, Ta, Tb, status, batch, seq);
+    return;
+  }
+  Acc64 A;
+  mm_nt(Tb, Ta, A);  // L_ik = A_ik Linv_kk^T
+  double* out = Lb + (int64_t)i * NB * Bp + (int64_t)kb * NB;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(int64_t)acc_row(mi, v) * Bp + acc_col(ni)] = A.c[mi][ni][v];
+}
+
+// (b): A_ij -= L_ik L_jk^T for the trailing tiles kb < j <= i other than
+// (kb + 1, kb + 1), which launch (a) factored.
+__device__ __forceinline__ void chol_trail_body(double* __restrict__ S, int32_t Bp,
+    int32_t nblk, int32_t kb, const double* __restrict__ Lb, const int32_t* __restrict__ status,
+    int64_t seq) {
+  if (seq_skip(status, seq)) return;
+  __shared__ double Ta[NB][LDT], Tb[NB][LDT];
+  const int u = blockIdx.x + 1;
+  int ii = (int)((sqrt(8.0 * u + 1.0) - 1.0) * 0.5);
+  while ((ii + 1) * (ii + 2) / 2 <= u) ++ii;
+  while (ii * (ii + 1) / 2 > u) --ii;
+  const int i = kb + 1 + ii;
+  const int j = kb + 1 + (u - ii * (ii + 1) / 2);
+  load_tile(Ta, Lb + (int64_t)i * NB * Bp + (int64_t)kb * NB, Bp);
+  if (j != i) load_tile(Tb, Lb + (int64_t)j * NB * Bp + (int64_t)kb * NB, Bp);
+  __syncthreads();
+  Acc64 U;
+  mm_nt(Ta, (j != i) ? Tb : Ta, U);  // L_ik L_jk^T
+  double* Aij = S + (int64_t)i * NB * Bp + (int64_t)j * NB;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Aij[(int64_t)acc_row(mi, v) * Bp + acc_col(ni)] -= U.c[mi][ni][v];
+}
+
+// Workgroups of the split step's launches for a batch of Bp rows: (a) the
+// panel tiles, the diagonal block and the inverse's share; (b) the trailing
+// tiles but the first.
+__host__ __device__ inline int32_t chol_panel_groups(int32_t Bp, int32_t kb) {
+  const int32_t nblk = Bp / 64, m = nblk - kb - 1;
+  return m <= 0 ? 0 : m + 1 + kb + kb * (nblk - 1 - kb);
+}
+__host__ __device__ inline int32_t chol_trail_groups(int32_t Bp, int32_t kb) {
+  const int32_t nblk = Bp / 64, m = nblk - kb - 1;
+  return m <= 0 ? 0 : m * (m + 1) / 2 - 1;
+}
+
+__global__ void __launch_bounds__(256, 2) k_chol_panel_g(const GJob* __restrict__ jobs,
+                                                         int32_t kb) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int32_t)blockIdx.x >= chol_panel_groups(J.Bp, kb)) return;
+  chol_panel_body(J.S, J.Bp, J.Bp / NB, kb, J.Lb, J.Linv, J.LiT, J.status, J.index, J.seq);
+}
+
+__global__ void __launch_bounds__(256, 2) k_chol_trail_g(const GJob* __restrict__ jobs,
+                                                         int32_t kb) {
+  const GJob& J = jobs[blockIdx.z];
+  if ((int32_t)blockIdx.x >= chol_trail_groups(J.Bp, kb)) return;
+  chol_trail_body(J.S, J.Bp, J.Bp / NB, kb, J.Lb, J.status, J.seq);
+}
+
 __global__ void __launch_bounds__(256, 2) k_chol_step_g(const GJob* __restrict__ jobs,
                                                         int32_t kb) {
   const GJob& J = jobs[blockIdx.z];
@@ -1571,8 +1670,16 @@ rbf_status chol_grouped(rbf_ctx* ctx, const GRound& r) {
   k_chol_first_g<<<dim3(1, 1, nz), 256, 0, s>>>(r.jobs);
   RBF_LAUNCHED(ctx, "k_chol_first_g");
   for (int32_t kb = 0; kb < r.nsteps; ++kb) {
-    k_chol_step_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
-    RBF_LAUNCHED(ctx, "k_chol_step_g");
+    // the fused step's workgroup count bounds both split launches' counts
+    if (r.chol_split) {
+      k_chol_panel_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
+      RBF_LAUNCHED(ctx, "k_chol_panel_g");
+      k_chol_trail_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
+      RBF_LAUNCHED(ctx, "k_chol_trail_g");
+    } else {
+      k_chol_step_g<<<dim3(r.step_x[kb], 1, nz), 256, 0, s>>>(r.jobs, kb);
+      RBF_LAUNCHED(ctx, "k_chol_step_g");
+    }
   }
   if (r.lr_x > 0) {
     k_linv_row_g<<<dim3(r.lr_x, 1, nz), 256, 0, s>>>(r.jobs);

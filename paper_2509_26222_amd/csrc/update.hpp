@@ -211,6 +211,10 @@ struct GRound {
   const int64_t* pre_main;        // device: prefix of 128x128-tile workgroups
   const int64_t* pre_tail;        // device: prefix of sub-tile workgroups
   int64_t n_main, n_tail;         // total workgroups of each
+  // Cholesky steps in the split form (a panel launch, then a trailing
+  // launch: throughput over many factors) instead of one launch per step
+  // (the critical path of few factors)
+  int32_t chol_split;
 };
 
 // Workgroups of Cholesky step kb for a batch of Bp rows (0: no such step).
