@@ -212,9 +212,10 @@ rbf_status rbf_bin_centers(rbf_ctx* ctx, const double* centers, int64_t N,
  * nodes per axis (2 (cutoff sigma / res + 1/64) < 12). The grid holds the
  * node map (4 bytes per node) until rbf_grid_destroy; the evaluations keep
  * the node weights in the context's workspace (8 or 4 bytes per node).
- * Set the mesh before a batched plan that evaluates on the grid is made,
- * and do not change the grid's form (this call) while such a plan exists:
- * its captured launches keep the node map's address and the form.
+ * Set the mesh before a batched plan that evaluates on the grid is made:
+ * while such a plan exists (its captured launches keep the node map's
+ * address and the form) this call returns RBF_E_INVALID_ARG, and so does
+ * rbf_grid_destroy on the grid.
  * Errors: RBF_E_INVALID_ARG (a center off the mesh, two on one node, too
  * many nodes or too wide a window; the grid then keeps its previous form),
  * RBF_E_NOMEM. Synchronises the context's stream. */

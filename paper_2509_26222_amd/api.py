@@ -861,8 +861,9 @@ class Grid:
         return self.set_mesh(roi[0] + 0.5 * res, roi[1] + 0.5 * res, res)
 
     def close(self):
-        if getattr(self, "h", None):
-            self.ctx.lib.rbf_grid_destroy(self.h)
+        # refused while a batched plan evaluates on the grid: the handle is
+        # kept (the exit handler closes plans before grids)
+        if getattr(self, "h", None) and self.ctx.lib.rbf_grid_destroy(self.h) == L.RBF_OK:
             self.h = None
 
     def __del__(self, _finalising=sys.is_finalizing):

@@ -453,6 +453,7 @@ rbf_status rbf_batched_plan(rbf_ctx* ctx, const rbf_params* params, const rbf_pa
     return fail(ctx, st, "rbf_batched_plan: setup failed: %s", why.c_str());
   }
   ++ctx->plans;
+  for (const rbf_patch& q : b->patches) ++const_cast<rbf_grid*>(q.grid)->plans;
   *out = b;
   return RBF_OK;
 }
@@ -515,6 +516,7 @@ rbf_status rbf_batched_destroy(rbf_batched* b) {
   if (b->cap) (void)hipStreamSynchronize(b->cap->stream);
   (void)hipStreamSynchronize(b->parent->stream);
   --b->parent->plans;
+  for (const rbf_patch& q : b->patches) --const_cast<rbf_grid*>(q.grid)->plans;
   return batched_free(b);
 }
 

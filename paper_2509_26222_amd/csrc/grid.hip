@@ -284,6 +284,10 @@ rbf_status rbf_grid_set_mesh(rbf_ctx* ctx, rbf_grid* g, double x0, double y0, do
   if (!ctx || !g) return RBF_E_INVALID_ARG;
   if (g->device != ctx->device)
     return fail(ctx, RBF_E_INVALID_ARG, "rbf_grid_set_mesh: grid on another device");
+  if (g->plans > 0)
+    return fail(ctx, RBF_E_INVALID_ARG,
+                "rbf_grid_set_mesh: %d batched plan(s) evaluate on this grid (destroy them "
+                "first)", (int)g->plans);
   RBF_TRY(set_device(ctx));
   if (res == 0.0) {  // back to the binned form
     RBF_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -368,7 +372,7 @@ rbf_status rbf_grid_set_mesh(rbf_ctx* ctx, rbf_grid* g, double x0, double y0, do
 }
 
 rbf_status rbf_grid_destroy(rbf_grid* g) {
-  if (!g) return RBF_E_INVALID_ARG;
+  if (!g || g->plans > 0) return RBF_E_INVALID_ARG;  // a batched plan still evaluates on it
   (void)hipSetDevice(g->device);
   if (g->d_mesh_map) (void)hipFree(g->d_mesh_map);
   if (g->d_start) (void)hipFree(g->d_start);

@@ -118,6 +118,10 @@ struct rbf_grid {
   double mx0, my0, mres;
   int32_t imin, jmin, mnx, mny, mpw, mph;
   int32_t* d_mesh_map;
+  // batched plans that evaluate on this grid (their captured launches keep
+  // its tables' addresses and its form): while any is alive the grid's form
+  // is fixed and the grid is not destroyed
+  int32_t plans;
 };
 
 namespace rbf {

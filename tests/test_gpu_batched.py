@@ -98,6 +98,29 @@ def test_batched_mixed_products_equal_sequential(ctx, gemm_prec):
             assert torch.equal(a[k], b[k]), k
 
 
+def test_grid_fixed_while_a_plan_evaluates_on_it(ctx):
+    """A batched plan's captured launches keep its grids' tables: while the
+    plan exists a grid's form cannot change and the grid is not destroyed
+    (both refused, nothing changed); after the plan is closed both work."""
+    p = api.Params()
+    A = make_patches(ctx, p, 2)
+    plan = api.Batched(ctx, p, A, dim=3)
+    g = A[0]["grid"]
+    with pytest.raises(api.RbfError, match="batched plan"):
+        g.set_mesh(0.25, 0.25, 0.5)
+    assert g.mesh is None
+    h = g.h
+    g.close()  # refused: the handle stays
+    assert g.h is h
+    plan.run()
+    assert plan.sync() == -1
+    plan.close()
+    g.set_mesh(0, 0, 0)  # allowed again (already binned: no change)
+    g.close()
+    assert g.h is None
+    ctx.sync_status()
+
+
 def test_batched_reports_failed_patch(ctx):
     """A non-finite height in patch 5 stops patch 5 at its failing batch;
     every other patch completes as its plain calls do."""
